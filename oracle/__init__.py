@@ -1,0 +1,263 @@
+"""CPU oracle for the CSFD dense-SLAM frame step -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's ``cpu_baseline`` leg may
+import this package.  The product path (the HIP library and its binding) never
+touches it, and the two share no code.
+
+The oracle is ``xslam_oracle.cpp`` (plain C++17 loops over one scalar type:
+real, full ``std::complex<double>`` or bicomplex), built by :func:`build` into
+``liboracle.so`` and called through ctypes.  Scalars cross the interface as
+``ncomp`` doubles: 1 (real), 2 (re, im) or 4 (re, i1, i2, i1i2).
+
+Parity pins live in ``tests/test_oracle_*.py``.  Parts without an independent
+pin are marked "parity unpinned" there and in the design notes: the bilateral
+and pyramid constants, the raycast march schedule and the discontinuity
+threshold (pinned only by special cases).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "xslam_oracle.cpp")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+# parameter ids (the perturbation targets)
+P_PHI_X, P_PHI_Y, P_PHI_Z, P_RHO_X, P_RHO_Y, P_RHO_Z = range(6)
+P_TRUNC, P_WCAP, P_DGATE, P_AGATE, P_ICPW0, P_ICPW1, P_ICPW2 = range(6, 13)
+P_FX, P_FY, P_CX, P_CY, P_DEPTH = range(13, 18)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class OrcConfig(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("dim", C.c_int32 * 3), ("voxel", C.c_double), ("trunc", C.c_double), ("wcap", C.c_double),
+                ("iters", C.c_int32 * 3), ("dgate", C.c_double), ("agate_deg", C.c_double),
+                ("level_w", C.c_double * 3), ("disc_delta", C.c_double),
+                ("bilateral_radius", C.c_int32), ("sigma_px", C.c_double), ("sigma_m", C.c_double),
+                ("near_m", C.c_double), ("init", C.c_int32)]
+
+
+class OrcSeed(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pa", C.c_int32), ("pb", C.c_int32), ("h", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        u8 = C.POINTER(C.c_uint8)
+        i64 = C.POINTER(C.c_int64)
+        i32 = C.POINTER(C.c_int32)
+        cp, sp = C.POINTER(OrcConfig), C.POINTER(OrcSeed)
+        L.orc_se3_exp.argtypes = [sp, dp, dp]
+        L.orc_measure.argtypes = [cp, sp, dp, dp, dp, dp, dp, u8]
+        L.orc_icp_reduce.argtypes = [cp, sp, C.c_int, dp, dp, u8, dp, dp, dp, u8, dp, dp, dp, dp, i64, dp]
+        L.orc_solve.argtypes = [sp, dp, dp, dp, dp]
+        L.orc_solve.restype = C.c_int
+        L.orc_fuse.argtypes = [cp, sp, dp, dp, dp, dp, i64, C.c_int64]
+        L.orc_fuse.restype = C.c_int64
+        L.orc_raycast.argtypes = [cp, sp, dp, dp, dp, i32, C.c_int32, dp, dp, dp, u8, dp, dp]
+        L.orc_track.argtypes = [cp, sp, dp, dp, dp, dp, dp, u8, dp, dp, dp, i64, dp]
+        L.orc_track.restype = C.c_int
+        L.orc_run_sequence.argtypes = [cp, sp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_traj_err.argtypes = [sp, C.c_int, dp, dp, dp]
+        L.orc_eval_f.argtypes = [sp, C.c_double, dp]
+        L.orc_eval_g.argtypes = [sp, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------
+def config(p: dict | None = None, **kw) -> OrcConfig:
+    """Build an OrcConfig from a scenegen preset dict (and keyword overrides)."""
+    d = dict(width=160, height=120, fx=130.0, fy=130.0, cx=79.5, cy=59.5, dim=(128, 128, 128),
+             voxel=0.02, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
+             level_w=(1.0, 1.0, 1.0), disc_delta=0.1, bilateral_radius=3, sigma_px=4.5,
+             sigma_m=0.03, near_m=0.1, init=0)
+    if p is not None:
+        cam = p["camera"]
+        d.update(width=cam["width"], height=cam["height"], fx=cam["fx"], fy=cam["fy"],
+                 cx=cam["cx"], cy=cam["cy"], dim=(p["dim"],) * 3, voxel=p["voxel"],
+                 trunc=p["trunc"], wcap=p["wcap"], iters=tuple(p["icp"]["iters"]),
+                 dgate=p["icp"]["dgate"], agate_deg=p["icp"]["agate_deg"])
+    d.update(kw)
+    c = OrcConfig()
+    for k, v in d.items():
+        if k in ("dim", "iters", "level_w"):
+            arr = getattr(c, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def seed(kind: int = 0, pa: int = -1, pb: int = -1, h: float = 1e-20) -> OrcSeed:
+    return OrcSeed(kind, pa, pb, h)
+
+
+def ncomp(s: OrcSeed) -> int:
+    return {0: 1, 1: 2, 2: 4}[s.kind]
+
+
+def _p(a, dtype=C.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(dtype))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def lift(x, s: OrcSeed) -> np.ndarray:
+    """Real array -> scalars with zero imaginary parts (trailing ncomp axis)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(x.shape + (ncomp(s),))
+    out[..., 0] = x
+    return out
+
+
+# --------------------------------------------------------------------------
+def se3_exp(s: OrcSeed, xi) -> np.ndarray:
+    xi = _f64(xi)
+    out = np.zeros((4, 4, ncomp(s)))
+    lib().orc_se3_exp(C.byref(s), _p(xi), _p(out))
+    return out
+
+
+def measure(c: OrcConfig, s: OrcSeed, depth, depth_dot=None):
+    """-> list of 3 levels: dict(D (H,W,nc), V (H,W,3,nc), N, valid (H,W) uint8)."""
+    nc = ncomp(s)
+    W, H = c.width, c.height
+    sizes = [(H >> l, W >> l) for l in range(3)]
+    tot = sum(h * w for h, w in sizes)
+    D = np.zeros((tot, nc)); V = np.zeros((tot, 3, nc)); N = np.zeros((tot, 3, nc))
+    valid = np.zeros(tot, dtype=np.uint8)
+    lib().orc_measure(C.byref(c), C.byref(s), _p(_f64(depth)), _p(_f64(depth_dot)), _p(D), _p(V), _p(N),
+                      _p(valid, C.c_uint8))
+    out, off = [], 0
+    for h, w in sizes:
+        n = h * w
+        out.append(dict(D=D[off:off + n].reshape(h, w, nc), V=V[off:off + n].reshape(h, w, 3, nc),
+                        N=N[off:off + n].reshape(h, w, 3, nc), valid=valid[off:off + n].reshape(h, w)))
+        off += n
+    return out
+
+
+def icp_reduce(c, s, level, cur, model, Tprev, T):
+    nc = ncomp(s)
+    A = np.zeros((21, nc)); b = np.zeros((6, nc))
+    cnt = C.c_int64(0); r2 = C.c_double(0)
+    lib().orc_icp_reduce(C.byref(c), C.byref(s), level, _p(_f64(cur["V"])), _p(_f64(cur["N"])),
+                         _p(np.ascontiguousarray(cur["valid"], np.uint8), C.c_uint8),
+                         _p(_f64(model["V"])), _p(_f64(model["N"])), _p(_f64(model["Z"])),
+                         _p(np.ascontiguousarray(model["valid"], np.uint8), C.c_uint8),
+                         _p(_f64(Tprev)), _p(_f64(T)), _p(A), _p(b), C.byref(cnt), C.byref(r2))
+    return A, b, cnt.value, r2.value
+
+
+def solve(s, A, b, w=None):
+    nc = ncomp(s)
+    w = lift(1.0, s) if w is None else _f64(w)
+    delta = np.zeros((6, nc))
+    lost = lib().orc_solve(C.byref(s), _p(_f64(A)), _p(_f64(b)), _p(w), _p(delta))
+    return delta, lost
+
+
+def fuse(c, s, F, W, Df, T, idx=None):
+    """In-place-free fusion: returns (F, W, n_updated).  F, W: (N, nc) for the
+    whole volume (x-fastest) or for the listed voxels when ``idx`` is given."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    W = np.array(W, dtype=np.float64, copy=True, order="C")
+    idx_a = None if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+    n = lib().orc_fuse(C.byref(c), C.byref(s), _p(F), _p(W), _p(_f64(Df)), _p(_f64(T)),
+                       _p(idx_a, C.c_int64), 0 if idx_a is None else len(idx_a))
+    return F, W, n
+
+
+def raycast(c, s, F, W, T, pix=None, sched_pose=None, sched_params=None):
+    nc = ncomp(s)
+    npx = c.width * c.height if pix is None else len(pix)
+    V = np.zeros((npx, 3, nc)); N = np.zeros((npx, 3, nc)); Z = np.zeros(npx)
+    valid = np.zeros(npx, dtype=np.uint8)
+    pix_a = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
+    lib().orc_raycast(C.byref(c), C.byref(s), _p(_f64(F)), _p(_f64(W)), _p(_f64(T)),
+                      _p(pix_a, C.c_int32), 0 if pix_a is None else len(pix_a),
+                      _p(V), _p(N), _p(Z), _p(valid, C.c_uint8), _p(_f64(sched_pose)), _p(_f64(sched_params)))
+    if pix is None:
+        H, Wd = c.height, c.width
+        return dict(V=V.reshape(H, Wd, 3, nc), N=N.reshape(H, Wd, 3, nc), Z=Z.reshape(H, Wd),
+                    valid=valid.reshape(H, Wd))
+    return dict(V=V, N=N, Z=Z, valid=valid)
+
+
+def track(c, s, depth, depth_dot, model0, Tprev, Tinit):
+    nc = ncomp(s)
+    Tout = np.zeros((4, 4, nc))
+    cnt = C.c_int64(0); r2 = C.c_double(0)
+    lost = lib().orc_track(C.byref(c), C.byref(s), _p(_f64(depth)), _p(_f64(depth_dot)),
+                           _p(_f64(model0["V"])), _p(_f64(model0["N"])), _p(_f64(model0["Z"])),
+                           _p(np.ascontiguousarray(model0["valid"], np.uint8), C.c_uint8),
+                           _p(_f64(Tprev)), _p(_f64(Tinit)), _p(Tout), C.byref(cnt), C.byref(r2))
+    return Tout, lost, cnt.value, r2.value
+
+
+def run_sequence(c, s, depths, T0, depth_dots=None, want_volume=False, sched_poses=None,
+                 sched_params=None):
+    """-> dict(poses (n,4,4,nc), stats (n,6), F, W (N,nc) if want_volume)."""
+    nc = ncomp(s)
+    depths = _f64(depths)
+    n = depths.shape[0]
+    poses = np.zeros((n, 4, 4, nc))
+    stats = np.zeros((n, 6))
+    nv = c.dim[0] * c.dim[1] * c.dim[2]
+    F = np.zeros((nv, nc)) if want_volume else None
+    W = np.zeros((nv, nc)) if want_volume else None
+    lib().orc_run_sequence(C.byref(c), C.byref(s), n, _p(depths), _p(_f64(depth_dots)), _p(_f64(T0)),
+                           _p(poses), _p(stats), _p(F), _p(W), _p(_f64(sched_poses)),
+                           _p(_f64(sched_params)))
+    out = dict(poses=poses, stats=stats)
+    if want_volume:
+        out.update(F=F, W=W)
+    return out
+
+
+def traj_err(s, poses, gt):
+    out = np.zeros(ncomp(s))
+    poses = _f64(poses)
+    lib().orc_traj_err(C.byref(s), poses.shape[0], _p(poses), _p(_f64(gt)), _p(out))
+    return out
+
+
+def eval_f(s, x):
+    out = np.zeros(ncomp(s))
+    lib().orc_eval_f(C.byref(s), float(x), _p(out))
+    return out
+
+
+def eval_g(s, x, y, x_on, y_on):
+    out = np.zeros(ncomp(s))
+    lib().orc_eval_g(C.byref(s), float(x), float(y), int(x_on), int(y_on), _p(out))
+    return out

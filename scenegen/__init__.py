@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the CSFD dense-SLAM frame step.
+
+This module only *generates inputs*: analytic scenes, depth frames rendered from
+them, depth noise and ground-truth camera trajectories.  It holds none of the
+SLAM method's arithmetic (no filtering, no fusion, no ray marching of a TSDF, no
+ICP), so both the CPU oracle and the GPU path can consume its output without
+sharing any of the method's code.
+
+The workloads stand in for the RGB-D sequences the paper evaluates on
+(Sec. 5.1: TUM RGB-D fr1/desk, fr1/xyz and ICL-NUIM), which are not available:
+640x480 depth at fx=fy=525 with noise growing as z^2, smooth hand-held-like
+trajectories at 30 Hz, and a room-sized scene made of a floor, spheres and
+boxes.  No dataset content is reproduced.
+
+Randomness: ``SeedSequence(seed)`` children ``(0,)`` scene, ``(1,)``
+trajectory, ``(2, k)`` the depth noise of frame ``k``; every stream is PCG64.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+__all__ = [
+    "Scene", "make_scene", "render_depth", "look_at", "circle_trajectory",
+    "spline_trajectory", "Sequence", "make_sequence", "PRESETS", "preset",
+]
+
+
+# --------------------------------------------------------------------------
+# Scene
+# --------------------------------------------------------------------------
+@dataclass
+class Scene:
+    L: float                       # cube edge in metres; world origin at cube centre
+    floor_y: float                 # floor plane y = floor_y (solid below)
+    spheres: np.ndarray            # (n, 4): cx, cy, cz, r
+    boxes: np.ndarray              # (n, 6): cx, cy, cz, hx, hy, hz
+
+    def sdf(self, p: np.ndarray) -> np.ndarray:
+        """Signed distance of points p (..., 3) to the union of primitives."""
+        p = np.asarray(p, dtype=np.float64)
+        d = p[..., 1] - self.floor_y
+        for cx, cy, cz, r in self.spheres:
+            ds = np.linalg.norm(p - np.array([cx, cy, cz]), axis=-1) - r
+            d = np.minimum(d, ds)
+        for cx, cy, cz, hx, hy, hz in self.boxes:
+            q = np.abs(p - np.array([cx, cy, cz])) - np.array([hx, hy, hz])
+            outside = np.linalg.norm(np.maximum(q, 0.0), axis=-1)
+            inside = np.minimum(np.max(q, axis=-1), 0.0)
+            d = np.minimum(d, outside + inside)
+        return d
+
+    def centroid(self) -> np.ndarray:
+        c = [s[:3] for s in self.spheres] + [b[:3] for b in self.boxes]
+        return np.mean(np.array(c), axis=0)
+
+
+def _children(seed: int):
+    return (np.random.SeedSequence(seed, spawn_key=(0,)),
+            np.random.SeedSequence(seed, spawn_key=(1,)))
+
+
+def noise_stream(seed: int, k: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(2, k))))
+
+
+def make_scene(seed: int, L: float, n_spheres: int = 3, n_boxes: int = 2,
+               centre_frac: float = 0.7) -> Scene:
+    """Floor at y=-0.3L, spheres r~U(0.2,0.5) m, boxes half-extents ~U(0.1,0.4) m,
+    all resting on the floor with non-overlapping xz footprints, centres
+    uniform over the central ``centre_frac`` of the cube in x and z."""
+    rng = np.random.Generator(np.random.PCG64(_children(seed)[0]))
+    floor_y = -0.3 * L
+    half = 0.5 * centre_frac * L
+    placed = []  # (x, z, footprint radius)
+    spheres, boxes = [], []
+    kinds = ["s"] * n_spheres + ["b"] * n_boxes
+    for kind in kinds:
+        for _ in range(100000):
+            if kind == "s":
+                r = rng.uniform(0.2, 0.5)
+                size = (r,)
+                foot = r
+            else:
+                hx, hy, hz = rng.uniform(0.1, 0.4, size=3)
+                size = (hx, hy, hz)
+                foot = float(np.hypot(hx, hz))
+            x, z = rng.uniform(-half, half, size=2)
+            if all(np.hypot(x - px, z - pz) > foot + pf + 0.05 for px, pz, pf in placed):
+                break
+        else:  # pragma: no cover - generator cannot place objects
+            raise RuntimeError("scene generator failed to place objects")
+        placed.append((x, z, foot))
+        if kind == "s":
+            spheres.append((x, floor_y + size[0], z, size[0]))
+        else:
+            boxes.append((x, floor_y + size[1], z, size[0], size[1], size[2]))
+    return Scene(L=L, floor_y=floor_y, spheres=np.array(spheres, dtype=np.float64).reshape(-1, 4),
+                 boxes=np.array(boxes, dtype=np.float64).reshape(-1, 6))
+
+
+# --------------------------------------------------------------------------
+# Rendering (analytic first hit of the union; exact equivalent of sphere tracing)
+# --------------------------------------------------------------------------
+def _rays(pose: np.ndarray, W: int, H: int, fx: float, fy: float, cx: float, cy: float):
+    xs = (np.arange(W, dtype=np.float64) - cx) / fx
+    ys = (np.arange(H, dtype=np.float64) - cy) / fy
+    dc = np.stack(np.broadcast_arrays(xs[None, :], ys[:, None], np.ones((1, 1))), axis=-1)  # (H,W,3), z=1
+    R = pose[:3, :3]
+    d = dc @ R.T
+    o = pose[:3, 3]
+    return o, d
+
+
+def render_depth(scene: Scene, pose: np.ndarray, W: int, H: int, fx: float, fy: float,
+                 cx: float, cy: float, max_range: float = 10.0) -> np.ndarray:
+    """Noise-free camera-z depth (FP64) of the first surface hit; 0 on a miss.
+    The ray through pixel u is o + t R K^-1 (u,1): t is the camera z depth."""
+    o, d = _rays(pose, W, H, fx, fy, cx, cy)
+    t = np.full(d.shape[:2], np.inf)
+    # floor: y = floor_y
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tf = (scene.floor_y - o[1]) / d[..., 1]
+    t = np.where((tf > 0) & np.isfinite(tf), np.minimum(t, tf), t)
+    a = np.einsum("hwi,hwi->hw", d, d)
+    for cx_, cy_, cz_, r in scene.spheres:
+        oc = o - np.array([cx_, cy_, cz_])
+        b = 2.0 * (d @ oc)
+        c = oc @ oc - r * r
+        disc = b * b - 4 * a * c
+        ok = disc >= 0
+        ts = np.where(ok, (-b - np.sqrt(np.where(ok, disc, 0.0))) / (2 * a), np.inf)
+        t = np.where((ts > 0) & ok, np.minimum(t, ts), t)
+    for cx_, cy_, cz_, hx, hy, hz in scene.boxes:
+        lo = np.array([cx_ - hx, cy_ - hy, cz_ - hz]) - o
+        hi = np.array([cx_ + hx, cy_ + hy, cz_ + hz]) - o
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1 = lo / d
+            t2 = hi / d
+        tn = np.nanmax(np.minimum(t1, t2), axis=-1)
+        tx = np.nanmin(np.maximum(t1, t2), axis=-1)
+        ok = (tn <= tx) & (tn > 0)
+        t = np.where(ok, np.minimum(t, tn), t)
+    t = np.where(np.isfinite(t) & (t <= max_range), t, 0.0)
+    return t
+
+
+def add_noise(z: np.ndarray, seed: int, k: int, sigma2: float = 0.0012):
+    """Returns (noisy depth, noise-scale tangent) with noise sigma2*z^2*n, n~N(0,1)."""
+    n = noise_stream(seed, k).standard_normal(z.shape)
+    tangent = np.where(z > 0, sigma2 * z * z * n, 0.0)
+    return np.where(z > 0, z + tangent, 0.0), tangent
+
+
+# --------------------------------------------------------------------------
+# Trajectories (camera-to-world 4x4; camera x right, y down, z forward)
+# --------------------------------------------------------------------------
+def look_at(eye, target, up=(0.0, 1.0, 0.0)) -> np.ndarray:
+    eye = np.asarray(eye, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - eye
+    f /= np.linalg.norm(f)
+    x = np.cross(f, np.asarray(up, dtype=np.float64))
+    x /= np.linalg.norm(x)
+    y = np.cross(f, x)
+    T = np.eye(4)
+    T[:3, 0], T[:3, 1], T[:3, 2], T[:3, 3] = x, y, f, eye
+    return T
+
+
+def _look_at_many(eye: np.ndarray, target: np.ndarray) -> np.ndarray:
+    f = target - eye
+    f /= np.linalg.norm(f, axis=-1, keepdims=True)
+    x = np.cross(f, np.array([0.0, 1.0, 0.0]))
+    x /= np.linalg.norm(x, axis=-1, keepdims=True)
+    y = np.cross(f, x)
+    return np.stack([x, y, f], axis=-1)
+
+
+def circle_trajectory(n_frames: int, radius: float, height: float = 0.0,
+                      deg_per_frame: float = 2.0) -> np.ndarray:
+    poses = []
+    for k in range(n_frames):
+        a = np.deg2rad(deg_per_frame * k)
+        eye = (radius * np.sin(a), height, -radius * np.cos(a))
+        poses.append(look_at(eye, (0.0, height, 0.0)))
+    return np.array(poses)
+
+
+def _catmull_rom(P: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Uniform Catmull-Rom through control points P (n,3) at parameters s in [0, n-1]."""
+    n = len(P)
+    Q = np.concatenate([P[:1], P, P[-1:]], axis=0)
+    i = np.clip(np.floor(s).astype(int), 0, n - 2)
+    t = (s - i)[:, None]
+    p0, p1, p2, p3 = Q[i], Q[i + 1], Q[i + 2], Q[i + 3]
+    return 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t ** 2
+                  + (-p0 + 3 * p1 - 3 * p2 + p3) * t ** 3)
+
+
+def _rot_angle(Ra: np.ndarray, Rb: np.ndarray) -> np.ndarray:
+    # ||Ra - Rb||_F = 2 sqrt(2) sin(theta/2): accurate for small angles too
+    f = np.sqrt(np.einsum("nij,nij->n", Ra - Rb, Ra - Rb))
+    return 2.0 * np.arcsin(np.clip(f / (2.0 * np.sqrt(2.0)), 0.0, 1.0))
+
+
+def spline_trajectory(seed: int, scene: Scene, n_frames: int, v_max: float = 0.5,
+                      w_max_deg: float = 30.0, fps: float = 30.0, n_ctrl: int = 8,
+                      clearance: float = 0.3) -> np.ndarray:
+    """Catmull-Rom position spline through ``n_ctrl`` points in the central 50% of
+    the cube, 0.8-1.8 m above the floor and >= ``clearance`` from every surface,
+    looking at a second spline through points near the object centroid; retimed
+    so speed <= v_max and angular rate <= w_max at ``fps``; ping-pongs along the
+    path if it is shorter than the requested number of frames."""
+    rng = np.random.Generator(np.random.PCG64(_children(seed)[1]))
+    L = scene.L
+    half = 0.25 * L
+    cen = scene.centroid()
+    for _attempt in range(200):
+        ctrl = []
+        while len(ctrl) < n_ctrl:
+            p = np.array([rng.uniform(-half, half), scene.floor_y + rng.uniform(0.8, 1.8),
+                          rng.uniform(-half, half)])
+            if scene.sdf(p[None])[0] >= clearance + 0.05:
+                ctrl.append(p)
+        ctrl = np.array(ctrl)
+        tgt = cen[None, :] + rng.uniform(-0.3, 0.3, size=(n_ctrl, 3))
+        s = np.linspace(0.0, n_ctrl - 1.0, 20001)
+        pos = _catmull_rom(ctrl, s)
+        if np.min(scene.sdf(pos)) < clearance:
+            continue
+        tg = _catmull_rom(tgt, s)
+        if np.min(np.linalg.norm(tg - pos, axis=-1)) < 0.5:
+            continue
+        break
+    else:  # pragma: no cover
+        raise RuntimeError("trajectory generator failed")
+    Rs = _look_at_many(pos, tg)
+    dl = np.linalg.norm(np.diff(pos, axis=0), axis=-1)
+    da = _rot_angle(Rs[:-1], Rs[1:])
+    # seconds per segment at the limits (5% margin for the within-segment nonlinearity)
+    cost = np.maximum(dl / (0.95 * v_max), da / np.deg2rad(0.95 * w_max_deg))
+    tcum = np.concatenate([[0.0], np.cumsum(cost)])
+    total = tcum[-1]
+    period = 2.0 * total
+    tk = (np.arange(n_frames) / fps) % period
+    tk = np.where(tk > total, period - tk, tk)
+    j = np.clip(np.searchsorted(tcum, tk, side="right") - 1, 0, len(s) - 2)
+    w = ((tk - tcum[j]) / np.maximum(cost[j], 1e-300))[:, None]
+    eye = (1 - w) * pos[j] + w * pos[j + 1]
+    tgt_k = (1 - w) * tg[j] + w * tg[j + 1]
+    poses = np.array([look_at(e, t) for e, t in zip(eye, tgt_k)])
+    # assert the motion limits (the spline sampling makes them hold to within the grid)
+    dpos = np.linalg.norm(np.diff(poses[:, :3, 3], axis=0), axis=-1) * fps
+    dang = np.rad2deg(_rot_angle(poses[:-1, :3, :3], poses[1:, :3, :3])) * fps
+    assert dpos.max(initial=0) <= v_max and dang.max(initial=0) <= w_max_deg
+    return poses
+
+
+# --------------------------------------------------------------------------
+# Sequences and presets
+# --------------------------------------------------------------------------
+@dataclass
+class Sequence:
+    scene: Scene
+    poses_gt: np.ndarray          # (K, 4, 4) FP64 camera-to-world
+    camera: dict                  # width, height, fx, fy, cx, cy
+    seed: int
+    depth_dtype: type = np.float32
+    sigma2: float = 0.0012
+    _cache: dict = field(default_factory=dict, repr=False)
+
+    def __len__(self):
+        return len(self.poses_gt)
+
+    def frame(self, k: int, noise: bool = True):
+        """Depth of frame k in ``depth_dtype`` and the noise-scale tangent."""
+        key = (k, noise)
+        if key not in self._cache:
+            c = self.camera
+            z = render_depth(self.scene, self.poses_gt[k], c["width"], c["height"],
+                             c["fx"], c["fy"], c["cx"], c["cy"])
+            if noise:
+                d, tan = add_noise(z, self.seed, k, self.sigma2)
+            else:
+                d, tan = z, np.zeros_like(z)
+            self._cache[key] = (d.astype(self.depth_dtype), tan.astype(self.depth_dtype))
+        return self._cache[key]
+
+    def depths(self, n: int | None = None, noise: bool = True) -> np.ndarray:
+        n = len(self) if n is None else n
+        return np.stack([self.frame(k, noise)[0] for k in range(n)])
+
+
+PRESETS = {
+    # 128^3 at 2 cm in a 2.56 m cube; 160x120; 20 frames on a circle; FP64-complex
+    "c0": dict(seed=0, L=2.56, dim=128, voxel=0.02, trunc=0.06, wcap=64.0,
+               camera=dict(width=160, height=120, fx=130.0, fy=130.0, cx=79.5, cy=59.5),
+               n_frames=20, traj="circle", radius=1.5, prec="c128",
+               icp=dict(iters=(10, 5, 4), dgate=0.1, agate_deg=20.0), h=1e-20),
+    # 512^3 at 1 cm in a 5.12 m cube; 640x480 at fx=fy=525; 500 frames on a spline; FP32-complex
+    "c1": dict(seed=1, L=5.12, dim=512, voxel=0.01, trunc=0.06, wcap=64.0,
+               camera=dict(width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5),
+               n_frames=500, traj="spline", prec="c64",
+               icp=dict(iters=(10, 5, 4), dgate=0.1, agate_deg=20.0), h=2.0 ** -20),
+    # 256^3 at 2 cm (config 1 generator), 300 frames
+    "c2": dict(seed=2, L=5.12, dim=256, voxel=0.02, trunc=0.06, wcap=64.0,
+               camera=dict(width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5),
+               n_frames=300, traj="spline", prec="c64",
+               icp=dict(iters=(10, 5, 4), dgate=0.1, agate_deg=20.0), h=2.0 ** -20),
+}
+
+
+def preset(name: str, **overrides) -> dict:
+    p = {**PRESETS[name]}
+    for k, v in overrides.items():
+        p[k] = v
+    return p
+
+
+def make_sequence(p: dict, n_frames: int | None = None) -> Sequence:
+    n = p["n_frames"] if n_frames is None else n_frames
+    scene = make_scene(p["seed"], p["L"])
+    if p["traj"] == "circle":
+        poses = circle_trajectory(n, p.get("radius", 1.5), 0.0, 2.0)
+    else:
+        poses = spline_trajectory(p["seed"], scene, n)
+    dt = np.float64 if p["prec"] == "c128" else np.float32
+    return Sequence(scene=scene, poses_gt=poses, camera=dict(p["camera"]), seed=p["seed"],
+                    depth_dtype=dt)
