@@ -415,10 +415,16 @@ template <class S> struct Normal {
 // Returns false if a tap is outside or invalid.
 template <class S> struct Lookup { V3<S> q, m; };
 
+// The tap row/column is floor(u + 1e-3): at the first iteration of a level
+// (T_j = T_{k-1}) every pixel re-projects onto its own integer coordinate up to
+// rounding, and a plain floor would pick the left or right cell by rounding
+// noise; the bias moves that tie a thousandth of a pixel away from the integers.
+const double kTapBias = 1e-3;
+
 template <class S>
 bool model_lookup(const Maps<S>& M, const S& ux, const S& uy, double delta, Lookup<S>& out) {
   double rx = re(ux), ry = re(uy);
-  double fx0 = std::floor(rx), fy0 = std::floor(ry);
+  double fx0 = std::floor(rx + kTapBias), fy0 = std::floor(ry + kTapBias);
   if (!(fx0 >= 0.0 && fy0 >= 0.0 && fx0 <= double(M.W - 2) && fy0 <= double(M.H - 2))) return false;
   int i0 = int(fx0), j0 = int(fy0);
   int t[4] = {j0 * M.W + i0, j0 * M.W + i0 + 1, (j0 + 1) * M.W + i0, (j0 + 1) * M.W + i0 + 1};

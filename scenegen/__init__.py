@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Scene", "make_scene", "render_depth", "look_at", "circle_trajectory",
+    "Scene", "make_scene", "render_depth", "render_maps", "look_at", "circle_trajectory",
     "spline_trajectory", "Sequence", "make_sequence", "PRESETS", "preset",
 ]
 
@@ -143,6 +143,39 @@ def render_depth(scene: Scene, pose: np.ndarray, W: int, H: int, fx: float, fy: 
         t = np.where(ok, np.minimum(t, tn), t)
     t = np.where(np.isfinite(t) & (t <= max_range), t, 0.0)
     return t
+
+
+def render_maps(scene: Scene, pose: np.ndarray, W: int, H: int, fx: float, fy: float,
+                cx: float, cy: float, max_range: float = 10.0):
+    """Noise-free analytic surface maps: camera-z depth (H,W), world hit points
+    (H,W,3) and outward surface normals (H,W,3); zeros on a miss."""
+    o, d = _rays(pose, W, H, fx, fy, cx, cy)
+    z = render_depth(scene, pose, W, H, fx, fy, cx, cy, max_range)
+    P = o + z[..., None] * d
+    N = np.zeros_like(P)
+    best = np.full(z.shape, np.inf)
+    # classify by the primitive whose signed distance is smallest in magnitude
+    cand = [("floor", None)] + [("s", s) for s in scene.spheres] + [("b", b) for b in scene.boxes]
+    for kind, prm in cand:
+        if kind == "floor":
+            dist = np.abs(P[..., 1] - scene.floor_y)
+            n = np.broadcast_to(np.array([0.0, 1.0, 0.0]), P.shape)
+        elif kind == "s":
+            q = P - prm[:3]
+            dist = np.abs(np.linalg.norm(q, axis=-1) - prm[3])
+            n = q / np.maximum(np.linalg.norm(q, axis=-1, keepdims=True), 1e-300)
+        else:
+            q = (P - prm[:3]) / prm[3:]
+            ax = np.argmax(np.abs(q), axis=-1)
+            n = np.zeros_like(P)
+            np.put_along_axis(n, ax[..., None], np.sign(np.take_along_axis(q, ax[..., None], -1)), -1)
+            qa = np.abs(P - prm[:3]) - prm[3:]
+            dist = np.abs(np.max(qa, axis=-1))
+        upd = dist < best
+        best = np.where(upd, dist, best)
+        N = np.where(upd[..., None], n, N)
+    hit = z > 0
+    return z, np.where(hit[..., None], P, 0.0), np.where(hit[..., None], N, 0.0)
 
 
 def add_noise(z: np.ndarray, seed: int, k: int, sigma2: float = 0.0012):
