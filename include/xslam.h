@@ -1,0 +1,199 @@
+/*
+ * xslam.h -- C ABI of the MI355X CSFD dense-SLAM frame step.
+ *
+ * The library evaluates the KinectFusion-style frame step of X-SLAM (Peng et
+ * al., ACM TOG 43(4) 2024; Sec. 4.1) -- surface measurement, projective
+ * point-to-plane ICP, TSDF fusion and raycasting -- with every quantity carried
+ * as a complex-step number x + i h x' (Sec. 3, eq. "csfd"), so that Im(f)/h is
+ * the derivative of poses, maps and the TSDF with respect to chosen SLAM
+ * parameters.  Products of two imaginary parts are dropped (Sec. 3, eqs.
+ * "csfd_simplify_multiplication"/"csfd_simplify_division"), which makes the
+ * arithmetic first-order dual numbers; second derivatives (Sec. 3, eqs.
+ * "mc_taylor", "csfd_hessian") are carried as the i1*i2 parts of hyper-dual
+ * numbers.  Many directions share one real part and run in one launch.
+ *
+ * Conventions
+ *  - Every call returns int: 0 OK, < 0 error, > 0 warning.  Arguments are
+ *    validated before anything is enqueued; no exception crosses the ABI.
+ *  - Calls are asynchronous on the HIP stream given at creation, except those
+ *    writing host memory (get, traj_err, step/track with pose_out), which
+ *    synchronise that stream.  Errors of asynchronous kernels surface at the
+ *    next synchronising call as XSLAM_ERR_HIP with text in xslam_last_error().
+ *  - One host thread per context.
+ *  - The caller owns all device memory: one workspace of
+ *    xslam_workspace_bytes() bytes (256-byte aligned) passed to xslam_create;
+ *    the context owns only its sub-allocation plan inside it.  Depth inputs are
+ *    device pointers owned by the caller, read before the call's work ends.
+ *  - World frame: origin at the volume centre, volume [-L/2, L/2]^3 with voxel
+ *    centres at (i + 1/2) s - L/2.  Camera: x right, y down, z forward; pixel
+ *    centres at integer coordinates.  Poses are camera-to-world, FP64,
+ *    row-major 4x4.
+ *  - A "component" of a scalar: 0 = real part, 1..D = the D first-order parts
+ *    (direction d carries h_d times its derivative), D+1 .. D+P = the P
+ *    second-order parts (pair (a,b) carries h_a h_b times the mixed derivative).
+ *    Arrays of scalars cross the ABI as component planes:
+ *    [re | tangent_0 .. tangent_{D-1} | second_0 .. second_{P-1}].
+ */
+#ifndef XSLAM_H
+#define XSLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xslam_ctx_s* xslam_ctx;
+
+enum xslam_status {
+  XSLAM_OK = 0,
+  XSLAM_WARN_TRACK_LOST = 1,   /* pose kept (the ICP initial pose), fusion skipped */
+  XSLAM_ERR_ARG = -1,
+  XSLAM_ERR_WORKSPACE = -2,
+  XSLAM_ERR_HIP = -3,
+  XSLAM_ERR_STATE = -4,
+  XSLAM_ERR_UNSUPPORTED = -5
+};
+
+/* arithmetic of the bulk of the frame step; the 6x6 solve, the SE(3)
+ * exponential, pose composition and the trajectory error are always FP64 */
+enum xslam_prec { XSLAM_C64 = 0 /* FP32 real + FP32 parts */, XSLAM_C128 = 1 /* FP64 */ };
+
+/* perturbable parameters (Sec. 4.1: depth eq. "csfd_depth", pose eq. "lie") */
+enum xslam_param {
+  XSLAM_P_PHI_X = 0, XSLAM_P_PHI_Y, XSLAM_P_PHI_Z,   /* initial pose, rotation, left-multiplied  */
+  XSLAM_P_RHO_X, XSLAM_P_RHO_Y, XSLAM_P_RHO_Z,       /* initial pose, translation, left-multiplied */
+  XSLAM_P_TRUNC = 6,    /* truncation distance mu                          */
+  XSLAM_P_WCAP = 7,     /* weight cap                                      */
+  XSLAM_P_DGATE = 8,    /* ICP distance gate (hard gate: derivative 0)     */
+  XSLAM_P_AGATE = 9,    /* ICP angle gate (hard gate: derivative 0)        */
+  XSLAM_P_ICPW0 = 10,   /* ICP step relaxation of level 0, 1, 2 (10..12)   */
+  XSLAM_P_FX = 13, XSLAM_P_FY = 14, XSLAM_P_CX = 15, XSLAM_P_CY = 16,
+  XSLAM_P_DEPTH = 17,   /* caller supplies dD/dtheta per frame (depth_dot)   */
+  XSLAM_P_COUNT = 18
+};
+
+/* one complex-step direction: parameter and step h (h > 0) */
+typedef struct { int32_t param; double h; } xslam_dir;
+/* one second-order pair: indices a <= b into the directions.  The set of
+ * pairs must be every (a, b) with a <= b < Q for some Q <= D (the Hessian over
+ * the first Q directions, listed in that row-major order). */
+typedef struct { int32_t a, b; } xslam_pair;
+typedef struct {
+  int32_t n_dirs; const xslam_dir* dirs;
+  int32_t n_pairs; const xslam_pair* pairs;
+} xslam_perturbation;
+
+typedef struct { int32_t width, height; double fx, fy, cx, cy; } xslam_camera;
+/* dims must be multiples of 8 (8^3 bricks) */
+typedef struct { int32_t dim[3]; double voxel; double trunc; double wcap; } xslam_volume;
+typedef struct {
+  int32_t iters[3];      /* per level, level 0 finest; levels run 2 -> 1 -> 0    */
+  double dgate;          /* metres                                               */
+  double agate_deg;      /* degrees                                              */
+  double level_w[3];     /* step relaxation per level (1 = plain Gauss-Newton)   */
+  double disc_delta;     /* depth discontinuity threshold of bilinear lookups (m)*/
+  int32_t init;          /* 0: previous pose, 1: constant velocity               */
+} xslam_icp;
+typedef struct {
+  int32_t prec;          /* enum xslam_prec                                       */
+  xslam_camera cam;      /* width, height multiples of 4                           */
+  xslam_volume vol;
+  xslam_icp icp;
+  int32_t bilateral_radius;        /* 0 disables the filter                        */
+  double bilateral_sigma_px, bilateral_sigma_m;
+  double near_m;                   /* raycast near plane                           */
+  int32_t max_frames;              /* capacity of the pose history                 */
+} xslam_config;
+
+/* get/set fields */
+enum xslam_field {
+  XSLAM_F_POSE = 0,      /* current pose: [NC][16] double                                    */
+  XSLAM_F_POSES = 1,     /* pose history: [frames][NC][16] double (get only)                 */
+  XSLAM_F_TSDF = 2,      /* F: [NC][N] in the context precision, N = dims product, x fastest */
+  XSLAM_F_WEIGHT = 3,    /* W: [NC][N] (only the re and weight-cap parts can be nonzero)     */
+  XSLAM_F_VMAP = 4,      /* model vertex map level 0 (world): [3][NC][H*W]                   */
+  XSLAM_F_NMAP = 5,      /* model normal map level 0 (world): [3][NC][H*W]                   */
+  XSLAM_F_ZMAP = 6,      /* model camera depth of the hits (real): [H*W]                     */
+  XSLAM_F_MVALID = 7,    /* model validity: uint8 [H*W]                                      */
+  XSLAM_F_MEAS_DEPTH = 8,/* filtered depth of levels 0,1,2 concatenated: [NC][n_l] per level */
+  XSLAM_F_MEAS_V = 9,    /* measured vertex maps (camera), levels 0,1,2: [3][NC][n_l] each   */
+  XSLAM_F_MEAS_N = 10,   /* measured normal maps (camera), levels 0,1,2                      */
+  XSLAM_F_MEAS_VALID = 11,/* measured validity, uint8, levels 0,1,2                          */
+  XSLAM_F_COUNTERS = 12, /* per frame int32[32]: lost, fused voxels, raycast hits,
+                            sum of ICP correspondences, last-pass correspondences,
+                            correspondences of every ICP pass (up to 24)                     */
+  XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
+  XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
+};
+
+/* number of components NC = 1 + D + P of a perturbation */
+int32_t xslam_components(const xslam_perturbation* pert);
+
+size_t xslam_workspace_bytes(const xslam_config* cfg, const xslam_perturbation* pert);
+
+/* Create a context.  dev_workspace: device memory of at least
+ * xslam_workspace_bytes(); stream: hipStream_t (NULL = default stream);
+ * T0: initial camera pose (host, FP64 row-major 4x4); pose directions are
+ * applied as exp(i h e_d) T0 (left multiplication).  The perturbation is
+ * copied; the TSDF starts empty (F = 0, W = 0). */
+int xslam_create(const xslam_config* cfg, const xslam_perturbation* pert, void* dev_workspace,
+                 size_t bytes, void* stream, const double T0[16], xslam_ctx* out);
+
+/* Surface measurement (Sec. 4.1 eq. "surface_measure"): promote the depth
+ * (eq. "csfd_depth"; depth_dot holds one H*W plane per XSLAM_P_DEPTH
+ * direction, in direction order, or NULL if there is none), bilateral filter,
+ * pyramid, vertex and normal maps.  depth: device, float (C64) or double (C128). */
+int xslam_measure(xslam_ctx ctx, const void* depth, const void* depth_dot);
+
+/* Surface update (Sec. 4.1 "Surface Update"): fuse the last measured frame
+ * into the TSDF at the current pose, or at `pose` (host FP64 4x4, zero
+ * tangents) if not NULL.  depth != NULL measures it first. */
+int xslam_integrate(xslam_ctx ctx, const void* depth, const void* depth_dot, const double* pose);
+
+/* Surface prediction (Sec. 4.1 eq. "surface_prediction"): raycast the TSDF at
+ * the current pose (or `pose`, host FP64 4x4) into the model maps (levels
+ * 0..2).  vmap/nmap, if not NULL, receive copies of level 0 (device,
+ * [3][NC][H*W] in the context precision). */
+int xslam_raycast(xslam_ctx ctx, const double* pose, void* vmap, void* nmap);
+
+/* Camera pose estimation (Sec. 4.1 eq. "icp"): measure `depth` and run the
+ * multi-level ICP against the current model maps.  The result becomes the
+ * current pose; pose_out (host, [NC][16]) if not NULL (synchronises). */
+int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out);
+
+/* Whole frame step: frame 0 fuses and raycasts at the initial pose; later
+ * frames measure, track against the previous model maps, fuse (skipped when
+ * tracking is lost) and raycast.  pose_out as in xslam_track. */
+int xslam_step(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out);
+
+/* One association + normal-equation pass (no solve) of ICP level `level`
+ * between the measured maps and the model maps of that level at the current
+ * pose (projection reference: XSLAM_F_PREV_POSE).  sums_out (host): [NC][27]
+ * doubles (21 upper-triangle entries of A row-major, then b), followed by
+ * 2 doubles: correspondence count and sum of squared real residuals. */
+int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out);
+
+/* Translational RMSE of the pose history against gt_poses (host, n x 16
+ * FP64), no alignment; out (host): NC doubles (value and its parts).  FP64. */
+int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out);
+
+/* host <-> context state copies (host buffers; synchronising) */
+int xslam_get(xslam_ctx ctx, int32_t field, void* dst, size_t bytes);
+int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
+
+/* Per-kernel timing with HIP events on the context stream (0 off, 1 on);
+ * xslam_kernel_times writes accumulated milliseconds and launch counts for
+ * kernel classes 0 measure, 1 icp, 2 fuse, 3 raycast, 4 other. */
+int xslam_set_timing(xslam_ctx ctx, int32_t on);
+int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]);
+
+int xslam_sync(xslam_ctx ctx);
+const char* xslam_last_error(xslam_ctx ctx);
+int xslam_destroy(xslam_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XSLAM_H */

@@ -1,0 +1,276 @@
+// C ABI of the frame step (declared in include/xslam.h): argument checks,
+// dispatch to the engine of the context's (precision, D, Q) shape, timing.
+#include <hip/hip_runtime.h>
+#include <string.h>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+#include "ctx.hpp"
+#include "combos.hpp"
+
+namespace xs {
+constexpr int kMaxDirsApi = 16;
+#define XS_DECL(T, D, Q, NAME)                                                      \
+  EngineBase* make_##NAME(xslam_ctx_s* ctx, const double T0[16], int* rc);          \
+  size_t bytes_##NAME(const xslam_config& c, int ndd, bool wtan);
+XS_COMBOS(XS_DECL)
+#undef XS_DECL
+
+struct Combo {
+  int prec, D, Q;
+  EngineBase* (*make)(xslam_ctx_s*, const double*, int*);
+  size_t (*bytes)(const xslam_config&, int, bool);
+};
+template <typename T> constexpr int prec_of();
+template <> constexpr int prec_of<float>() { return XSLAM_C64; }
+template <> constexpr int prec_of<double>() { return XSLAM_C128; }
+#define XS_ROW(T, D, Q, NAME) {prec_of<T>(), D, Q, &make_##NAME, &bytes_##NAME},
+static const Combo kCombos[] = {XS_COMBOS(XS_ROW)};
+#undef XS_ROW
+
+static const Combo* find_combo(int prec, int D, int Q) {
+  for (const Combo& c : kCombos)
+    if (c.prec == prec && c.D == D && c.Q == Q) return &c;
+  return nullptr;
+}
+
+// Validate config and perturbation; on success fill D, Q, ndepth, wcap flag.
+static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, int* Q, int* ndd, bool* wtan,
+                    std::string* err) {
+  auto bad = [&](const char* m) { *err = m; return XSLAM_ERR_ARG; };
+  if (!c) return bad("config is NULL");
+  if (c->prec != XSLAM_C64 && c->prec != XSLAM_C128) return bad("prec");
+  if (c->cam.width < 16 || c->cam.height < 16 || c->cam.width % 4 || c->cam.height % 4)
+    return bad("image size must be >= 16 and a multiple of 4");
+  if (!(c->cam.fx > 0 && c->cam.fy > 0)) return bad("focal lengths");
+  for (int a = 0; a < 3; ++a)
+    if (c->vol.dim[a] < 16 || c->vol.dim[a] % 8) return bad("volume dims must be >= 16 and multiples of 8");
+  if ((int64_t)c->vol.dim[0] * c->vol.dim[1] * c->vol.dim[2] > (int64_t(1) << 31)) return bad("volume too large");
+  if (!(c->vol.voxel > 0 && c->vol.trunc > 0 && c->vol.wcap >= 1)) return bad("volume parameters");
+  for (int l = 0; l < 3; ++l)
+    if (c->icp.iters[l] < 0 || c->icp.iters[l] > 64) return bad("icp iterations");
+  if (c->icp.iters[0] + c->icp.iters[1] + c->icp.iters[2] > 27) return bad("icp iterations: at most 27 passes");
+  if (!(c->icp.dgate > 0)) return bad("dgate");
+  if (c->icp.init != 0 && c->icp.init != 1) return bad("icp.init must be 0 or 1");
+  if (c->bilateral_radius < 0 || c->bilateral_radius > 4) return bad("bilateral radius must be 0..4");
+  if (c->bilateral_radius > 0 && !(c->bilateral_sigma_px > 0 && c->bilateral_sigma_m > 0)) return bad("bilateral sigmas");
+  if (!(c->bilateral_sigma_m > 0)) return bad("bilateral_sigma_m gates the pyramid and must be > 0");
+  if (c->max_frames < 1) return bad("max_frames");
+  int nd = p ? p->n_dirs : 0, np = p ? p->n_pairs : 0;
+  if (nd < 0 || nd > kMaxDirsApi) return bad("n_dirs must be 0..16");
+  if (nd > 0 && !p->dirs) return bad("dirs is NULL");
+  if (np > 0 && !p->pairs) return bad("pairs is NULL");
+  *ndd = 0;
+  *wtan = false;
+  int nw = 0;
+  for (int d = 0; d < nd; ++d) {
+    const xslam_dir& x = p->dirs[d];
+    if (x.param < 0 || x.param >= XSLAM_P_COUNT) return bad("direction parameter");
+    if (!(x.h > 0) || !std::isfinite(x.h)) return bad("direction step h must be > 0");
+    if (c->prec == XSLAM_C64 && (x.h < 1e-30 || x.h > 1.0)) return bad("FP32 step h must be in [1e-30, 1]");
+    if (x.param == XSLAM_P_DEPTH) ++*ndd;
+    if (x.param == XSLAM_P_WCAP) { ++nw; *wtan = true; }
+  }
+  if (nw > 1) return bad("at most one weight-cap direction");
+  // pairs: the full upper triangle over the first q directions, row-major
+  int q = 0;
+  while (q * (q + 1) / 2 < np) ++q;
+  if (q * (q + 1) / 2 != np || q > nd) return bad("pairs must be the upper triangle over the first Q directions");
+  int k = 0;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++k)
+      if (p->pairs[k].a != a || p->pairs[k].b != b) return bad("pairs must be listed as (a,b), a<=b<Q, row-major");
+  if (c->prec == XSLAM_C64)
+    for (int a = 0; a < q; ++a)
+      if (p->dirs[a].h < 1e-15) return bad("FP32 second-order steps need h >= 1e-15 (h^2 must stay normal)");
+  *D = nd;
+  *Q = q;
+  return XSLAM_OK;
+}
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+int32_t xslam_components(const xslam_perturbation* p) {
+  if (!p) return 1;
+  return 1 + p->n_dirs + p->n_pairs;
+}
+
+size_t xslam_workspace_bytes(const xslam_config* cfg, const xslam_perturbation* pert) {
+  int D, Q, ndd;
+  bool wtan;
+  std::string err;
+  if (validate(cfg, pert, &D, &Q, &ndd, &wtan, &err)) return 0;
+  const Combo* cb = find_combo(cfg->prec, D, Q);
+  if (!cb) return 0;
+  return cb->bytes(*cfg, ndd, wtan);
+}
+
+int xslam_create(const xslam_config* cfg, const xslam_perturbation* pert, void* dev_workspace, size_t bytes,
+                 void* stream, const double T0[16], xslam_ctx* out) {
+  if (!out) return XSLAM_ERR_ARG;
+  *out = nullptr;
+  int D, Q, ndd;
+  bool wtan;
+  std::string err;
+  int rc = validate(cfg, pert, &D, &Q, &ndd, &wtan, &err);
+  if (rc) return rc;
+  if (!T0) return XSLAM_ERR_ARG;
+  const Combo* cb = find_combo(cfg->prec, D, Q);
+  if (!cb) return XSLAM_ERR_UNSUPPORTED;
+  size_t need = cb->bytes(*cfg, ndd, wtan);
+  if (!dev_workspace || bytes < need || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return XSLAM_ERR_WORKSPACE;
+  xslam_ctx_s* c = new (std::nothrow) xslam_ctx_s();
+  if (!c) return XSLAM_ERR_ARG;
+  c->cfg = *cfg;
+  if (pert) {
+    c->dirs.assign(pert->dirs, pert->dirs + pert->n_dirs);
+    c->pairs.assign(pert->pairs, pert->pairs + pert->n_pairs);
+  }
+  c->D = D;
+  c->Q = Q;
+  c->NC = 1 + D + Q * (Q + 1) / 2;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->ws = static_cast<char*>(dev_workspace);
+  c->ws_bytes = bytes;
+  hipGetDevice(&c->device);
+  c->eng = cb->make(c, T0, &rc);
+  if (!c->eng) {
+    delete c;
+    return rc ? rc : XSLAM_ERR_HIP;
+  }
+  *out = c;
+  return XSLAM_OK;
+}
+
+#define XS_CTX_CHECK(ctx) \
+  if (!(ctx) || !(ctx)->eng) return XSLAM_ERR_ARG
+
+int xslam_measure(xslam_ctx ctx, const void* depth, const void* depth_dot) {
+  XS_CTX_CHECK(ctx);
+  return ctx->eng->measure(depth, depth_dot);
+}
+
+int xslam_integrate(xslam_ctx ctx, const void* depth, const void* depth_dot, const double* pose) {
+  XS_CTX_CHECK(ctx);
+  if (depth) {
+    int rc = ctx->eng->measure(depth, depth_dot);
+    if (rc) return rc;
+  }
+  return ctx->eng->integrate(pose);
+}
+
+int xslam_raycast(xslam_ctx ctx, const double* pose, void* vmap, void* nmap) {
+  XS_CTX_CHECK(ctx);
+  return ctx->eng->raycast(pose, vmap, nmap);
+}
+
+static int finish_pose(xslam_ctx ctx, double* pose_out) {
+  if (!pose_out) return XSLAM_OK;
+  int rc = ctx->eng->current_pose(pose_out);
+  if (rc) return rc;
+  int lost = 0;
+  rc = ctx->eng->frame_lost(&lost);
+  if (rc) return rc;
+  return lost ? XSLAM_WARN_TRACK_LOST : XSLAM_OK;
+}
+
+int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out) {
+  XS_CTX_CHECK(ctx);
+  int rc = ctx->eng->measure(depth, depth_dot);
+  if (rc) return rc;
+  rc = ctx->eng->track();
+  if (rc) return rc;
+  return finish_pose(ctx, pose_out);
+}
+
+int xslam_step(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out) {
+  XS_CTX_CHECK(ctx);
+  int rc = ctx->eng->step(depth, depth_dot);
+  if (rc) return rc;
+  return finish_pose(ctx, pose_out);
+}
+
+int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out) {
+  XS_CTX_CHECK(ctx);
+  if (!sums_out) return XSLAM_ERR_ARG;
+  return ctx->eng->icp_pass(level, sums_out);
+}
+
+int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out) {
+  XS_CTX_CHECK(ctx);
+  if (!gt_poses || !out) return XSLAM_ERR_ARG;
+  return ctx->eng->traj_err(gt_poses, n, out);
+}
+
+int xslam_get(xslam_ctx ctx, int32_t field, void* dst, size_t bytes) {
+  XS_CTX_CHECK(ctx);
+  if (!dst) return XSLAM_ERR_ARG;
+  return ctx->eng->get(field, dst, bytes);
+}
+
+int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes) {
+  XS_CTX_CHECK(ctx);
+  if (!src) return XSLAM_ERR_ARG;
+  return ctx->eng->set(field, src, bytes);
+}
+
+int xslam_set_timing(xslam_ctx ctx, int32_t on) {
+  XS_CTX_CHECK(ctx);
+  Timer& t = ctx->timer;
+  if (on && t.pool.empty()) {
+    t.pool.resize(8192);
+    for (auto& e : t.pool)
+      if (hipEventCreate(&e) != hipSuccess) return XSLAM_ERR_HIP;
+  }
+  t.on = on != 0;
+  return XSLAM_OK;
+}
+
+int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]) {
+  XS_CTX_CHECK(ctx);
+  Timer& t = ctx->timer;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return XSLAM_ERR_HIP;
+  for (auto& p : t.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.first, p.second.second) != hipSuccess) return XSLAM_ERR_HIP;
+    t.ms[p.first] += ms;
+    t.launches[p.first] += 1;
+  }
+  t.pending.clear();
+  t.next = 0;
+  for (int i = 0; i < 5; ++i) {
+    if (ms_out) ms_out[i] = t.ms[i];
+    if (launches_out) launches_out[i] = t.launches[i];
+  }
+  return XSLAM_OK;
+}
+
+int xslam_sync(xslam_ctx ctx) {
+  XS_CTX_CHECK(ctx);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->err = std::string("stream: ") + hipGetErrorString(e);
+    return XSLAM_ERR_HIP;
+  }
+  return XSLAM_OK;
+}
+
+const char* xslam_last_error(xslam_ctx ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+int xslam_destroy(xslam_ctx ctx) {
+  if (!ctx) return XSLAM_ERR_ARG;
+  hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->timer.pool) hipEventDestroy(e);
+  delete ctx->eng;
+  delete ctx;
+  return XSLAM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,10 @@
+// Supported (precision, directions D, Hessian size Q) shapes, one translation
+// unit each (inst.hip compiled once per line).
+#pragma once
+#define XS_COMBOS(X)              \
+  X(double, 0, 0, c128_d0_q0)     \
+  X(double, 1, 0, c128_d1_q0)     \
+  X(double, 6, 0, c128_d6_q0)     \
+  X(float, 0, 0, c64_d0_q0)       \
+  X(float, 1, 0, c64_d1_q0)       \
+  X(float, 6, 0, c64_d6_q0)

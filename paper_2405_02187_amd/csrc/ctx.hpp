@@ -1,0 +1,49 @@
+// Host-side context of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+#include "../../include/xslam.h"
+
+namespace xs {
+
+struct EngineBase {
+  virtual ~EngineBase() {}
+  virtual int measure(const void* depth, const void* ddot) = 0;
+  virtual int integrate(const double* pose) = 0;
+  virtual int raycast(const double* pose, void* vmap, void* nmap) = 0;
+  virtual int track() = 0;
+  virtual int step(const void* depth, const void* ddot) = 0;
+  virtual int icp_pass(int level, double* out) = 0;
+  virtual int traj_err(const double* gt, int n, double* out) = 0;
+  virtual int get(int field, void* dst, size_t bytes) = 0;
+  virtual int set(int field, const void* src, size_t bytes) = 0;
+  virtual int current_pose(double* out) = 0;
+  virtual int frame_lost(int* lost) = 0;
+};
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[5] = {0, 0, 0, 0, 0};
+  int64_t launches[5] = {0, 0, 0, 0, 0};
+};
+
+}  // namespace xs
+
+struct xslam_ctx_s {
+  xslam_config cfg;
+  std::vector<xslam_dir> dirs;
+  std::vector<xslam_pair> pairs;
+  int D = 0, Q = 0, NC = 1;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  xs::EngineBase* eng = nullptr;
+  xs::Timer timer;
+  int device = 0;
+};

@@ -1,0 +1,640 @@
+// Orchestration of the frame step for one (precision, directions, Hessian) shape.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <cmath>
+#include <string>
+#include <vector>
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+namespace xs {
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// sub-allocation of the caller's workspace
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(char* b) : base(b) {}
+  template <typename P> P* take(size_t count) {
+    size_t o = off;
+    off = align_up(off + count * sizeof(P));
+    return base ? reinterpret_cast<P*>(base + o) : nullptr;
+  }
+};
+
+template <typename T, int D, int Q>
+struct Engine : EngineBase {
+  using J = Jet<T, D, Q>;
+  using JD = Jet<double, D, Q>;
+  using T2 = typename Vec2<T>::type;
+  static constexpr int NC = J::N;
+  static constexpr int NS = IcpSize<D, Q>::NS;
+  static constexpr int64_t kStageElems = int64_t(1) << 22;
+
+  xslam_ctx_s* C;
+  KParams<T, D, Q> kp;
+  JD omega[3];
+  int W[3], H[3];
+  size_t npx[3];
+  int64_t nvox = 0;
+  int nbrick = 0;
+  int ndepth = 0;       // depth_dot planes
+  int frame = 0;        // host mirror of the processed-frame count
+  bool measured = false, have_model = false;
+
+  // device buffers
+  T2* rec = nullptr; T* Ftan = nullptr; T* Wtan = nullptr;
+  T* raw = nullptr; T* rawdot = nullptr;
+  T* Dl[3]; T* Vl[3]; T* Nl[3]; uint8_t* valid[3];
+  T* Vm[3]; T* Nm[3]; T* Zm[3]; uint8_t* mvalid[3];
+  T* partials = nullptr; unsigned* ticket = nullptr; int* lost = nullptr;
+  MPose<D, Q>* Pcur; MPose<D, Q>* Pprev; MPose<D, Q>* Pprev2; MPose<D, Q>* Pinit; MPose<D, Q>* hist;
+  KPose<T, D, Q>* Kcur; KPose<T, D, Q>* Kprev;
+  int32_t* counters = nullptr;
+  double* sums = nullptr; double* traj = nullptr; double* gt = nullptr;
+  T* stage = nullptr;
+
+  // ---- workspace plan ---------------------------------------------------
+  static size_t plan(const xslam_config& c, int ndd, bool wtan, Engine* e, char* base) {
+    Carver cv(base);
+    const int64_t nv = int64_t(c.vol.dim[0]) * c.vol.dim[1] * c.vol.dim[2];
+    const size_t n0 = size_t(c.cam.width) * c.cam.height;
+    T2* rec = cv.take<T2>(nv);
+    T* Ftan = NC > 1 ? cv.take<T>(size_t(NC - 1) * nv) : nullptr;
+    T* Wtan = wtan ? cv.take<T>(nv) : nullptr;
+    T* raw = cv.take<T>(n0);
+    T* rawdot = ndd ? cv.take<T>(size_t(ndd) * n0) : nullptr;
+    T *Dl[3], *Vl[3], *Nl[3], *Vm[3], *Nm[3], *Zm[3];
+    uint8_t *vl[3], *mv[3];
+    for (int l = 0; l < 3; ++l) {
+      size_t n = size_t(c.cam.width >> l) * (c.cam.height >> l);
+      Dl[l] = cv.take<T>(NC * n);
+      Vl[l] = cv.take<T>(3 * NC * n);
+      Nl[l] = cv.take<T>(3 * NC * n);
+      vl[l] = cv.take<uint8_t>(n);
+      Vm[l] = cv.take<T>(3 * NC * n);
+      Nm[l] = cv.take<T>(3 * NC * n);
+      Zm[l] = cv.take<T>(n);
+      mv[l] = cv.take<uint8_t>(n);
+    }
+    T* partials = cv.take<T>(size_t(kMaxIcpBlocks) * NS);
+    unsigned* ticket = cv.take<unsigned>(1);
+    int* lost = cv.take<int>(1);
+    MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
+    MPose<D, Q>* hist = cv.take<MPose<D, Q>>(c.max_frames);
+    KPose<T, D, Q>* K = cv.take<KPose<T, D, Q>>(2);
+    int32_t* counters = cv.take<int32_t>(size_t(kCounters) * c.max_frames);
+    double* sums = cv.take<double>(NS);
+    double* traj = cv.take<double>(NC);
+    double* gt = cv.take<double>(size_t(16) * c.max_frames);
+    T* stage = cv.take<T>(kStageElems);
+    if (e) {
+      e->rec = rec; e->Ftan = Ftan; e->Wtan = Wtan; e->raw = raw; e->rawdot = rawdot;
+      for (int l = 0; l < 3; ++l) {
+        e->Dl[l] = Dl[l]; e->Vl[l] = Vl[l]; e->Nl[l] = Nl[l]; e->valid[l] = vl[l];
+        e->Vm[l] = Vm[l]; e->Nm[l] = Nm[l]; e->Zm[l] = Zm[l]; e->mvalid[l] = mv[l];
+      }
+      e->partials = partials; e->ticket = ticket; e->lost = lost;
+      e->Pcur = P; e->Pprev = P + 1; e->Pprev2 = P + 2; e->Pinit = P + 3; e->hist = hist;
+      e->Kcur = K; e->Kprev = K + 1;
+      e->counters = counters; e->sums = sums; e->traj = traj; e->gt = gt; e->stage = stage;
+    }
+    return cv.off;
+  }
+
+  // ---- error helpers ----------------------------------------------------
+  int fail(int code, const std::string& msg) {
+    C->err = msg;
+    return code;
+  }
+  int check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(XSLAM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return XSLAM_OK;
+  }
+  int sync() {
+    hipError_t e = hipStreamSynchronize(C->stream);
+    if (e != hipSuccess) return fail(XSLAM_ERR_HIP, std::string("stream: ") + hipGetErrorString(e));
+    return XSLAM_OK;
+  }
+
+  // kernel launch with optional event timing; cls: 0 measure 1 icp 2 fuse 3 raycast 4 other
+  template <typename F> int launch(int cls, const char* what, F&& f) {
+    Timer& tm = C->timer;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm.on && tm.next + 2 <= tm.pool.size()) {
+      e0 = tm.pool[tm.next++];
+      e1 = tm.pool[tm.next++];
+      hipEventRecord(e0, C->stream);
+    }
+    f();
+    int rc = check(what);
+    if (e1) {
+      hipEventRecord(e1, C->stream);
+      tm.pending.push_back({cls, {e0, e1}});
+    }
+    return rc;
+  }
+
+  // ---- construction -----------------------------------------------------
+  int init(xslam_ctx_s* ctx, const double T0[16]) {
+    C = ctx;
+    const xslam_config& c = C->cfg;
+    for (int l = 0; l < 3; ++l) {
+      W[l] = c.cam.width >> l;
+      H[l] = c.cam.height >> l;
+      npx[l] = size_t(W[l]) * H[l];
+    }
+    nvox = int64_t(c.vol.dim[0]) * c.vol.dim[1] * c.vol.dim[2];
+    // parameter jets
+    auto pj = [&](double v, int param) {
+      JD r = jconst<JD>(v);
+      for (int d = 0; d < D; ++d)
+        if (C->dirs[d].param == param) r.v[1 + d] = C->dirs[d].h;
+      return r;
+    };
+    auto cast = [](const JD& x) { return jcast<T>(x); };
+    kp.fx = cast(pj(c.cam.fx, XSLAM_P_FX));
+    kp.fy = cast(pj(c.cam.fy, XSLAM_P_FY));
+    kp.cx = cast(pj(c.cam.cx, XSLAM_P_CX));
+    kp.cy = cast(pj(c.cam.cy, XSLAM_P_CY));
+    kp.mu = cast(pj(c.vol.trunc, XSLAM_P_TRUNC));
+    kp.wcap = cast(pj(c.vol.wcap, XSLAM_P_WCAP));
+    kp.dgate2 = T(c.icp.dgate * c.icp.dgate);
+    kp.cos_agate = T(std::cos(c.icp.agate_deg * M_PI / 180.0));
+    kp.disc_delta = T(c.icp.disc_delta);
+    kp.bil_is = T(1.0 / (2.0 * c.bilateral_sigma_px * c.bilateral_sigma_px));
+    kp.bil_ir = T(1.0 / (2.0 * c.bilateral_sigma_m * c.bilateral_sigma_m));
+    kp.pyr_gate = T(3.0 * c.bilateral_sigma_m);
+    kp.voxel = T(c.vol.voxel);
+    for (int a = 0; a < 3; ++a) {
+      kp.half[a] = T(0.5 * c.vol.dim[a] * c.vol.voxel);
+      kp.dim[a] = c.vol.dim[a];
+      kp.nbr[a] = c.vol.dim[a] / kBrick;
+    }
+    nbrick = kp.nbr[0] * kp.nbr[1] * kp.nbr[2];
+    kp.near_m = T(c.near_m);
+    kp.bil_radius = c.bilateral_radius;
+    kp.W = c.cam.width;
+    kp.H = c.cam.height;
+    kp.wcap_dir = -1;
+    ndepth = 0;
+    for (int d = 0; d < kMaxDirs; ++d) { kp.depth_plane[d] = -1; kp.depth_h[d] = T(0); }
+    for (int d = 0; d < D; ++d) {
+      if (C->dirs[d].param == XSLAM_P_WCAP) kp.wcap_dir = d;
+      if (C->dirs[d].param == XSLAM_P_DEPTH) { kp.depth_plane[d] = ndepth++; kp.depth_h[d] = T(C->dirs[d].h); }
+    }
+    for (int l = 0; l < 3; ++l) omega[l] = pj(c.icp.level_w[l], XSLAM_P_ICPW0 + l);
+    plan(c, ndepth, kp.wcap_dir >= 0, this, C->ws);
+    // empty volume and maps
+    int rc;
+    if ((rc = fill<T>(reinterpret_cast<T*>(rec), T(0), 2 * nvox))) return rc;
+    if (NC > 1 && (rc = fill<T>(Ftan, T(0), int64_t(NC - 1) * nvox))) return rc;
+    if (Wtan && (rc = fill<T>(Wtan, T(0), nvox))) return rc;
+    for (int l = 0; l < 3; ++l) {
+      if ((rc = fill<uint8_t>(mvalid[l], 0, npx[l]))) return rc;
+      if ((rc = fill<uint8_t>(valid[l], 0, npx[l]))) return rc;
+    }
+    if ((rc = fill<unsigned>(ticket, 0u, 1))) return rc;
+    if ((rc = fill<int>(lost, 0, 1))) return rc;
+    if ((rc = fill<int32_t>(counters, 0, int64_t(kCounters) * c.max_frames))) return rc;
+    // initial pose exp(xi_seed) T0, xi_seed = h on the pose directions
+    JD xi[6];
+    for (int a = 0; a < 6; ++a) xi[a] = pj(0.0, XSLAM_P_PHI_X + a);
+    MPose<D, Q> T0p;
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) T0p.m[r * 3 + q] = jconst<JD>(T0[r * 4 + q]);
+      T0p.m[9 + r] = jconst<JD>(T0[r * 4 + 3]);
+    }
+    MPose<D, Q> P0 = pose_mul(se3_exp<D, Q>(xi), T0p);
+    if ((rc = put_pose(Pcur, Kcur, P0))) return rc;
+    if ((rc = put_pose(Pprev, Kprev, P0))) return rc;
+    if ((rc = put_pose(Pprev2, nullptr, P0))) return rc;
+    if ((rc = put_pose(Pinit, nullptr, P0))) return rc;
+    return sync();
+  }
+
+  template <typename P> int fill(P* p, P v, int64_t n) {
+    if (n <= 0) return XSLAM_OK;
+    int blocks = int(std::min<int64_t>((n + 255) / 256, 4096));
+    return launch(4, "fill", [&] { hipLaunchKernelGGL(k_fill<P>, dim3(blocks), dim3(256), 0, C->stream, p, v, n); });
+  }
+
+  int put_pose(MPose<D, Q>* dst, KPose<T, D, Q>* kdst, const MPose<D, Q>& P) {
+    if (hipMemcpyAsync(dst, &P, sizeof(P), hipMemcpyHostToDevice, C->stream) != hipSuccess)
+      return check("pose upload");
+    if (kdst) {
+      KPose<T, D, Q> K = to_kpose<T, double>(P);
+      if (hipMemcpyAsync(kdst, &K, sizeof(K), hipMemcpyHostToDevice, C->stream) != hipSuccess)
+        return check("pose upload");
+    }
+    return sync();  // the host structs above are stack temporaries
+  }
+
+  // ---- stages -------------------------------------------------------------
+  int copy_inputs(const void* depth, const void* ddot) {
+    if (!depth) return fail(XSLAM_ERR_ARG, "depth is NULL");
+    if (ndepth > 0 && !ddot) return fail(XSLAM_ERR_ARG, "depth_dot required by a depth direction");
+    hipError_t e = hipMemcpyAsync(raw, depth, npx[0] * sizeof(T), hipMemcpyDeviceToDevice, C->stream);
+    if (e == hipSuccess && ndepth > 0)
+      e = hipMemcpyAsync(rawdot, ddot, size_t(ndepth) * npx[0] * sizeof(T), hipMemcpyDeviceToDevice, C->stream);
+    if (e != hipSuccess) return fail(XSLAM_ERR_HIP, std::string("input copy: ") + hipGetErrorString(e));
+    return XSLAM_OK;
+  }
+
+  int run_measure() {
+    int rc;
+    dim3 b(16, 16);
+    dim3 g0((W[0] + 15) / 16, (H[0] + 15) / 16);
+    if ((rc = launch(0, "bilateral", [&] {
+           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0]);
+         })))
+      return rc;
+    for (int l = 1; l < 3; ++l) {
+      dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
+      if ((rc = launch(0, "pyrdown", [&] {
+             hipLaunchKernelGGL((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l]);
+           })))
+        return rc;
+    }
+    for (int l = 0; l < 3; ++l) {
+      dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
+      if ((rc = launch(0, "vertex_normal", [&] {
+             hipLaunchKernelGGL((k_vertex_normal<T, D, Q>), g, b, 0, C->stream, kp, l, Dl[l], W[l], H[l], Vl[l],
+                                Nl[l], valid[l]);
+           })))
+        return rc;
+    }
+    measured = true;
+    return XSLAM_OK;
+  }
+
+  int32_t* counter_row() { return counters + size_t(kCounters) * std::min(frame, C->cfg.max_frames - 1); }
+
+  int run_icp_level(int l, int iter_slot, int do_solve) {
+    IcpArgs<T, D, Q> a;
+    a.V = Vl[l]; a.N = Nl[l]; a.valid = valid[l];
+    a.Vm = Vm[l]; a.Nm = Nm[l]; a.Zm = Zm[l]; a.validm = mvalid[l];
+    a.W = W[l]; a.H = H[l]; a.level = l; a.iter_slot = iter_slot; a.do_solve = do_solve;
+    a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l];
+    a.partials = partials; a.ticket = ticket; a.lost = lost; a.counters = counter_row(); a.sums_out = sums;
+    int blocks = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+    return launch(1, "icp", [&] {
+      hipLaunchKernelGGL((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
+    });
+  }
+
+  int run_track() {
+    int rc;
+    if (!measured) return fail(XSLAM_ERR_STATE, "track: no measured frame");
+    if (!have_model) return fail(XSLAM_ERR_STATE, "track: no model maps (raycast first)");
+    if ((rc = launch(4, "track_begin", [&] {
+           hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pprev, Pprev2, Pinit,
+                              Kcur, Kprev, lost, counter_row(), (C->cfg.icp.init == 1 && frame > 1) ? 1 : 0);
+         })))
+      return rc;
+    int slot = 0;
+    for (int l = 2; l >= 0; --l)
+      for (int it = 0; it < C->cfg.icp.iters[l]; ++it, ++slot)
+        if ((rc = run_icp_level(l, slot, 1))) return rc;
+    return launch(4, "track_end", [&] {
+      hipLaunchKernelGGL((k_track_end<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pinit, Kcur, lost);
+    });
+  }
+
+  int run_fuse() {
+    return launch(2, "fuse", [&] {
+      hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(nbrick), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
+                         Wtan, lost, counter_row(), nvox);
+    });
+  }
+
+  int run_raycast() {
+    MapsOut<T, D, Q> o;
+    for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
+    dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
+    int rc = launch(3, "raycast", [&] {
+      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, counter_row());
+    });
+    if (!rc) have_model = true;
+    return rc;
+  }
+
+  int store_pose() {
+    int f = std::min(frame, C->cfg.max_frames - 1);
+    return launch(4, "store_pose", [&] {
+      hipLaunchKernelGGL((k_store_pose<D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, hist, f);
+    });
+  }
+
+  int reset_frame_flags() {
+    int rc = fill<int>(lost, 0, 1);
+    if (!rc) rc = fill<int32_t>(counter_row(), 0, kCounters);
+    return rc;
+  }
+
+  // ---- EngineBase ---------------------------------------------------------
+  int measure(const void* depth, const void* ddot) override {
+    int rc = copy_inputs(depth, ddot);
+    return rc ? rc : run_measure();
+  }
+
+  int integrate(const double* pose) override {
+    int rc;
+    if (!measured) return fail(XSLAM_ERR_STATE, "integrate: no measured frame");
+    if (pose && (rc = set_real_pose(pose))) return rc;
+    if ((rc = fill<int>(lost, 0, 1))) return rc;
+    return run_fuse();
+  }
+
+  int raycast(const double* pose, void* vmap, void* nmap) override {
+    int rc;
+    if (pose && (rc = set_real_pose(pose))) return rc;
+    if ((rc = run_raycast())) return rc;
+    size_t bytes = size_t(3) * NC * npx[0] * sizeof(T);
+    if (vmap && hipMemcpyAsync(vmap, Vm[0], bytes, hipMemcpyDeviceToDevice, C->stream) != hipSuccess)
+      return check("vmap copy");
+    if (nmap && hipMemcpyAsync(nmap, Nm[0], bytes, hipMemcpyDeviceToDevice, C->stream) != hipSuccess)
+      return check("nmap copy");
+    return XSLAM_OK;
+  }
+
+  int track() override {
+    int rc = run_track();
+    if (rc) return rc;
+    return store_pose();
+  }
+
+  int step(const void* depth, const void* ddot) override {
+    int rc;
+    if (frame >= C->cfg.max_frames) return fail(XSLAM_ERR_STATE, "step: max_frames reached");
+    if ((rc = copy_inputs(depth, ddot))) return rc;
+    if ((rc = run_measure())) return rc;
+    if (frame == 0) {
+      if ((rc = reset_frame_flags())) return rc;
+    } else {
+      if ((rc = run_track())) return rc;
+    }
+    if ((rc = store_pose())) return rc;
+    if ((rc = run_fuse())) return rc;
+    if ((rc = run_raycast())) return rc;
+    frame += 1;
+    return XSLAM_OK;
+  }
+
+  int icp_pass(int level, double* out) override {
+    if (level < 0 || level > 2) return fail(XSLAM_ERR_ARG, "icp_pass: level");
+    int rc;
+    if ((rc = fill<int>(lost, 0, 1))) return rc;
+    if ((rc = run_icp_level(level, 0, 0))) return rc;
+    if (hipMemcpyAsync(out, sums, NS * sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+      return check("sums copy");
+    return sync();
+  }
+
+  int traj_err(const double* gtp, int n, double* out) override {
+    if (n <= 0 || n > frame || n > C->cfg.max_frames) return fail(XSLAM_ERR_ARG, "traj_err: n");
+    if (hipMemcpyAsync(gt, gtp, size_t(16) * n * sizeof(double), hipMemcpyHostToDevice, C->stream) != hipSuccess)
+      return check("gt upload");
+    int rc = launch(4, "traj_err", [&] {
+      hipLaunchKernelGGL((k_traj_err<D, Q>), dim3(1), dim3(64), 0, C->stream, hist, gt, n, traj);
+    });
+    if (rc) return rc;
+    if (hipMemcpyAsync(out, traj, NC * sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+      return check("traj copy");
+    return sync();
+  }
+
+  int frame_lost(int* l) override {
+    int32_t row[kCounters];
+    int f = std::min(frame - 1, C->cfg.max_frames - 1);
+    if (f < 0) { *l = 0; return XSLAM_OK; }
+    if (hipMemcpyAsync(row, counters + size_t(kCounters) * f, sizeof(row), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+      return check("counters copy");
+    int rc = sync();
+    *l = row[0];
+    return rc;
+  }
+
+  // ---- poses <-> host ----------------------------------------------------
+  static void pose_to_host(const MPose<D, Q>& P, double* out) {  // [NC][16]
+    for (int c = 0; c < NC; ++c) {
+      double* o = out + c * 16;
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) o[r * 4 + q] = P.m[r * 3 + q].v[c];
+        o[r * 4 + 3] = P.m[9 + r].v[c];
+      }
+      o[12] = o[13] = o[14] = 0.0;
+      o[15] = (c == 0) ? 1.0 : 0.0;
+    }
+  }
+  static MPose<D, Q> pose_from_host(const double* in) {
+    MPose<D, Q> P;
+    for (int c = 0; c < NC; ++c) {
+      const double* o = in + c * 16;
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) P.m[r * 3 + q].v[c] = o[r * 4 + q];
+        P.m[9 + r].v[c] = o[r * 4 + 3];
+      }
+    }
+    return P;
+  }
+  int set_real_pose(const double* T16) {
+    std::vector<double> buf(size_t(16) * NC, 0.0);
+    memcpy(buf.data(), T16, 16 * sizeof(double));
+    return put_pose(Pcur, Kcur, pose_from_host(buf.data()));
+  }
+  int current_pose(double* out) override {
+    MPose<D, Q> P;
+    if (hipMemcpyAsync(&P, Pcur, sizeof(P), hipMemcpyDeviceToHost, C->stream) != hipSuccess) return check("pose copy");
+    int rc = sync();
+    if (!rc) pose_to_host(P, out);
+    return rc;
+  }
+
+  // ---- get / set ----------------------------------------------------------
+  int vol_xfer(bool get, int kind, int comp, T* host) {
+    for (int64_t s0 = 0; s0 < nvox; s0 += kStageElems) {
+      int64_t cnt = std::min<int64_t>(kStageElems, nvox - s0);
+      int blocks = int((cnt + 255) / 256);
+      int rc;
+      if (get) {
+        if ((rc = launch(4, "vol_gather", [&] {
+               hipLaunchKernelGGL(k_vol_gather<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
+                                  nvox, kp.dim[0], kp.dim[1], kp.nbr[0], kp.nbr[1], s0, cnt, stage);
+             })))
+          return rc;
+        if (hipMemcpyAsync(host + s0, stage, cnt * sizeof(T), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+          return check("vol copy");
+        if ((rc = sync())) return rc;
+      } else {
+        if (hipMemcpyAsync(stage, host + s0, cnt * sizeof(T), hipMemcpyHostToDevice, C->stream) != hipSuccess)
+          return check("vol copy");
+        if ((rc = launch(4, "vol_scatter", [&] {
+               hipLaunchKernelGGL(k_vol_scatter<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
+                                  nvox, kp.dim[0], kp.dim[1], kp.nbr[0], kp.nbr[1], s0, cnt, stage);
+             })))
+          return rc;
+        if ((rc = sync())) return rc;
+      }
+    }
+    return XSLAM_OK;
+  }
+
+  int copy(bool get, void* host, const void* dev, size_t bytes) {
+    hipError_t e = get ? hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, C->stream)
+                       : hipMemcpyAsync(const_cast<void*>(dev), host, bytes, hipMemcpyHostToDevice, C->stream);
+    if (e != hipSuccess) return fail(XSLAM_ERR_HIP, std::string("copy: ") + hipGetErrorString(e));
+    return sync();
+  }
+
+  int xfer(bool get, int field, void* buf, size_t bytes) {
+    auto need = [&](size_t b) { return bytes == b; };
+    size_t tot3 = 0, tot1 = 0;
+    for (int l = 0; l < 3; ++l) { tot1 += npx[l]; tot3 += 3 * npx[l]; }
+    switch (field) {
+      case XSLAM_F_POSE:
+      case XSLAM_F_PREV_POSE: {
+        if (!need(size_t(NC) * 16 * sizeof(double))) return fail(XSLAM_ERR_ARG, "pose: size");
+        MPose<D, Q>* P = field == XSLAM_F_POSE ? Pcur : Pprev;
+        KPose<T, D, Q>* K = field == XSLAM_F_POSE ? Kcur : Kprev;
+        if (get) {
+          MPose<D, Q> h;
+          int rc = copy(true, &h, P, sizeof(h));
+          if (!rc) pose_to_host(h, static_cast<double*>(buf));
+          return rc;
+        }
+        return put_pose(P, K, pose_from_host(static_cast<const double*>(buf)));
+      }
+      case XSLAM_F_POSES: {
+        if (!get) return fail(XSLAM_ERR_ARG, "poses: get only");
+        int nf = std::min(frame, C->cfg.max_frames);
+        if (!need(size_t(nf) * NC * 16 * sizeof(double))) return fail(XSLAM_ERR_ARG, "poses: size");
+        std::vector<MPose<D, Q>> h(nf);
+        int rc = nf ? copy(true, h.data(), hist, nf * sizeof(MPose<D, Q>)) : 0;
+        for (int k = 0; k < nf && !rc; ++k) pose_to_host(h[k], static_cast<double*>(buf) + size_t(k) * NC * 16);
+        return rc;
+      }
+      case XSLAM_F_TSDF:
+      case XSLAM_F_WEIGHT: {
+        if (!need(size_t(NC) * nvox * sizeof(T))) return fail(XSLAM_ERR_ARG, "tsdf: size");
+        T* h = static_cast<T*>(buf);
+        bool isF = field == XSLAM_F_TSDF;
+        for (int c = 0; c < NC; ++c) {
+          T* plane = h + size_t(c) * nvox;
+          int rc;
+          if (c == 0) rc = vol_xfer(get, isF ? 0 : 1, 0, plane);
+          else if (isF) rc = vol_xfer(get, 2, c - 1, plane);
+          else if (c - 1 == kp.wcap_dir) rc = vol_xfer(get, 3, 0, plane);
+          else {
+            if (get) memset(plane, 0, nvox * sizeof(T));
+            rc = 0;
+          }
+          if (rc) return rc;
+        }
+        return XSLAM_OK;
+      }
+      case XSLAM_F_VMAP: case XSLAM_F_NMAP: {
+        size_t b = size_t(3) * NC * npx[0] * sizeof(T);
+        if (!need(b)) return fail(XSLAM_ERR_ARG, "map: size");
+        int rc = copy(get, buf, field == XSLAM_F_VMAP ? Vm[0] : Nm[0], b);
+        if (!rc && !get) rc = rebuild_model_pyramid();
+        return rc;
+      }
+      case XSLAM_F_ZMAP: {
+        if (!need(npx[0] * sizeof(T))) return fail(XSLAM_ERR_ARG, "zmap: size");
+        int rc = copy(get, buf, Zm[0], npx[0] * sizeof(T));
+        if (!rc && !get) rc = rebuild_model_pyramid();
+        return rc;
+      }
+      case XSLAM_F_MVALID: {
+        if (!need(npx[0])) return fail(XSLAM_ERR_ARG, "mvalid: size");
+        int rc = copy(get, buf, mvalid[0], npx[0]);
+        if (!rc && !get) { rc = rebuild_model_pyramid(); have_model = true; }
+        return rc;
+      }
+      case XSLAM_F_MEAS_DEPTH: case XSLAM_F_MEAS_V: case XSLAM_F_MEAS_N: case XSLAM_F_MEAS_VALID: {
+        size_t per = field == XSLAM_F_MEAS_DEPTH ? NC * sizeof(T) : field == XSLAM_F_MEAS_VALID ? 1 : 3 * NC * sizeof(T);
+        if (!need(tot1 * per)) return fail(XSLAM_ERR_ARG, "meas: size");
+        char* h = static_cast<char*>(buf);
+        for (int l = 0; l < 3; ++l) {
+          void* dev = field == XSLAM_F_MEAS_DEPTH ? (void*)Dl[l] : field == XSLAM_F_MEAS_V ? (void*)Vl[l]
+                    : field == XSLAM_F_MEAS_N ? (void*)Nl[l] : (void*)valid[l];
+          int rc = copy(get, h, dev, npx[l] * per);
+          if (rc) return rc;
+          h += npx[l] * per;
+        }
+        if (!get) measured = true;
+        return XSLAM_OK;
+      }
+      case XSLAM_F_COUNTERS: {
+        if (!get) return fail(XSLAM_ERR_ARG, "counters: get only");
+        int nf = std::min(frame, C->cfg.max_frames);
+        if (!need(size_t(nf) * kCounters * sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "counters: size");
+        return nf ? copy(true, buf, counters, bytes) : XSLAM_OK;
+      }
+      case XSLAM_F_FRAME: {
+        if (!need(sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "frame: size");
+        if (get) { *static_cast<int32_t*>(buf) = frame; return XSLAM_OK; }
+        int f = *static_cast<const int32_t*>(buf);
+        if (f < 0 || f > C->cfg.max_frames) return fail(XSLAM_ERR_ARG, "frame: range");
+        frame = f;
+        return XSLAM_OK;
+      }
+    }
+    return fail(XSLAM_ERR_ARG, "unknown field");
+  }
+
+  // after a host write of level-0 model maps: levels 1, 2 by subsampling
+  int rebuild_model_pyramid() {
+    std::vector<T> V(3 * NC * npx[0]), N(3 * NC * npx[0]), Z(npx[0]);
+    std::vector<uint8_t> M(npx[0]);
+    int rc;
+    if ((rc = copy(true, V.data(), Vm[0], V.size() * sizeof(T)))) return rc;
+    if ((rc = copy(true, N.data(), Nm[0], N.size() * sizeof(T)))) return rc;
+    if ((rc = copy(true, Z.data(), Zm[0], Z.size() * sizeof(T)))) return rc;
+    if ((rc = copy(true, M.data(), mvalid[0], M.size()))) return rc;
+    for (int l = 1; l < 3; ++l) {
+      size_t nl = npx[l];
+      std::vector<T> Vl_(3 * NC * nl), Nl_(3 * NC * nl), Zl(nl);
+      std::vector<uint8_t> Ml(nl);
+      for (int y = 0; y < H[l]; ++y)
+        for (int x = 0; x < W[l]; ++x) {
+          size_t s = size_t(y << l) * W[0] + (x << l), d = size_t(y) * W[l] + x;
+          for (int c = 0; c < 3 * NC; ++c) {
+            Vl_[c * nl + d] = V[c * npx[0] + s];
+            Nl_[c * nl + d] = N[c * npx[0] + s];
+          }
+          Zl[d] = Z[s];
+          Ml[d] = M[s];
+        }
+      if ((rc = copy(false, Vl_.data(), Vm[l], Vl_.size() * sizeof(T)))) return rc;
+      if ((rc = copy(false, Nl_.data(), Nm[l], Nl_.size() * sizeof(T)))) return rc;
+      if ((rc = copy(false, Zl.data(), Zm[l], Zl.size() * sizeof(T)))) return rc;
+      if ((rc = copy(false, Ml.data(), mvalid[l], Ml.size()))) return rc;
+    }
+    return XSLAM_OK;
+  }
+
+  int get(int field, void* dst, size_t bytes) override { return xfer(true, field, dst, bytes); }
+  int set(int field, const void* src, size_t bytes) override {
+    return xfer(false, field, const_cast<void*>(src), bytes);
+  }
+};
+
+template <typename T, int D, int Q>
+EngineBase* make_engine(xslam_ctx_s* ctx, const double T0[16], int* rc) {
+  auto* e = new Engine<T, D, Q>();
+  *rc = e->init(ctx, T0);
+  if (*rc) { delete e; return nullptr; }
+  return e;
+}
+template <typename T, int D, int Q>
+size_t engine_bytes(const xslam_config& c, int ndd, bool wtan) {
+  return Engine<T, D, Q>::plan(c, ndd, wtan, nullptr, nullptr);
+}
+
+}  // namespace xs

@@ -1,0 +1,806 @@
+// HIP kernels of the CSFD frame step (X-SLAM Sec. 4.1), templated over the
+// kernel precision T (float: FP32-complex, double: FP64-complex), the number of
+// directions D and the Hessian size Q.  Decisions (validity, floors, gates,
+// crossings, update masks) are taken on real parts evaluated with the same
+// operations as a real run; the imaginary parts ride along.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.hpp"
+
+namespace xs {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { typedef float2 type; };
+template <> struct Vec2<double> { typedef double2 type; };
+
+// ---------------------------------------------------------------------------
+// A1. depth promotion (eq. "csfd_depth") and bilateral filter
+// ---------------------------------------------------------------------------
+template <typename T, int D, int Q>
+__device__ __forceinline__ Jet<T, D, Q> promote_depth(const KParams<T, D, Q>& kp, const T* __restrict__ depth,
+                                                      const T* __restrict__ ddot, size_t n, size_t i) {
+  Jet<T, D, Q> r = jzero<Jet<T, D, Q>>();
+  T d = depth[i];
+  if (!(d > T(0) && isfinite(d))) return r;
+  r.v[0] = d;
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    if (kp.depth_plane[k] >= 0) r.v[1 + k] = kp.depth_h[k] * ddot[size_t(kp.depth_plane[k]) * n + i];
+  return r;
+}
+
+// Bilateral filter (Sec. 4.1 "Surface measurement"): normalised weighted sum
+// over the valid pixels of a (2r+1)^2 window with weights
+// exp(-|u-u'|^2/(2 s_px^2) - (D(u)-D(u'))^2/(2 s_m^2)), complex through D.
+// The raw depth of a 16x16 tile plus its halo is staged in LDS (real parts and
+// the depth tangents), one thread per output pixel.
+constexpr int kBilTile = 16;
+constexpr int kBilMaxR = 4;
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T* __restrict__ depth,
+                                                   const T* __restrict__ ddot, T* __restrict__ Dout) {
+  using J = Jet<T, D, Q>;
+  constexpr int S = kBilTile + 2 * kBilMaxR;
+  __shared__ J tile[S * S];
+  const int W = kp.W, H = kp.H, r = kp.bil_radius;
+  const size_t n = size_t(W) * H;
+  const int x0 = blockIdx.x * kBilTile - kBilMaxR, y0 = blockIdx.y * kBilTile - kBilMaxR;
+  const int tid = threadIdx.y * kBilTile + threadIdx.x;
+  for (int q = tid; q < S * S; q += kBilTile * kBilTile) {
+    int xx = x0 + q % S, yy = y0 + q / S;
+    J v = jzero<J>();
+    if (xx >= 0 && yy >= 0 && xx < W && yy < H) v = promote_depth(kp, depth, ddot, n, size_t(yy) * W + xx);
+    tile[q] = v;
+  }
+  __syncthreads();
+  const int x = blockIdx.x * kBilTile + threadIdx.x, y = blockIdx.y * kBilTile + threadIdx.y;
+  if (x >= W || y >= H) return;
+  const size_t i = size_t(y) * W + x;
+  const J c = tile[(threadIdx.y + kBilMaxR) * S + threadIdx.x + kBilMaxR];
+  if (!(c.re() > T(0)) || r <= 0) {
+    jstore(Dout, n, i, c);
+    return;
+  }
+  J num = jzero<J>(), den = jzero<J>();
+  for (int dy = -r; dy <= r; ++dy)
+    for (int dx = -r; dx <= r; ++dx) {
+      int xx = x + dx, yy = y + dy;
+      if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+      const J d = tile[(threadIdx.y + kBilMaxR + dy) * S + threadIdx.x + kBilMaxR + dx];
+      if (!(d.re() > T(0))) continue;
+      J dd = c - d;
+      J arg = jconst<J>(T(dx * dx + dy * dy) * kp.bil_is) + (dd * dd) * kp.bil_ir;
+      J w = jexp(-arg);
+      num = num + w * d;
+      den = den + w;
+    }
+  jstore(Dout, n, i, num / den);
+}
+
+// Coarser level (Sec. 4.1: "Gaussian smoothing", the perturbation smoothed
+// alike): 5x5 binomial (1,4,6,4,1)^2 centred on (2x,2y) over valid taps within
+// 3 s_m of the centre, renormalised; real weights.
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* __restrict__ Din, int Wi, int Hi,
+                                                 T* __restrict__ Dout) {
+  using J = Jet<T, D, Q>;
+  const int Wo = Wi / 2, Ho = Hi / 2;
+  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  if (x >= Wo || y >= Ho) return;
+  const size_t ni = size_t(Wi) * Hi, no = size_t(Wo) * Ho, o = size_t(y) * Wo + x;
+  const T c = Din[size_t(2 * y) * Wi + 2 * x];
+  if (!(c > T(0))) {
+    jstore(Dout, no, o, jzero<J>());
+    return;
+  }
+  const int g[5] = {1, 4, 6, 4, 1};
+  J num = jzero<J>();
+  T den = 0;
+  for (int j = -2; j <= 2; ++j)
+    for (int i = -2; i <= 2; ++i) {
+      int xx = 2 * x + i, yy = 2 * y + j;
+      if (xx < 0 || yy < 0 || xx >= Wi || yy >= Hi) continue;
+      size_t q = size_t(yy) * Wi + xx;
+      T d = Din[q];
+      if (!(d > T(0))) continue;
+      if (fabs(d - c) > kp.pyr_gate) continue;
+      T w = T(g[i + 2] * g[j + 2]);
+      num = num + w * jload<J>(Din, ni, q);
+      den += w;
+    }
+  jstore(Dout, no, o, num / den);
+}
+
+// ---------------------------------------------------------------------------
+// A2. vertex and normal maps (eqs. "vertex", "normal"), level l with K / 2^l.
+// N = normalize((V(u_y+) - V(u)) x (V(u_x+) - V(u))) faces the camera.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int level, const T* __restrict__ Dl,
+                                                       int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
+                                                       uint8_t* __restrict__ valid) {
+  using J = Jet<T, D, Q>;
+  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  if (x >= Wl || y >= Hl) return;
+  const size_t n = size_t(Wl) * Hl, i = size_t(y) * Wl + x;
+  const T sc = T(1) / T(1 << level);
+  const J fx = kp.fx * sc, fy = kp.fy * sc, cx = kp.cx * sc, cy = kp.cy * sc;
+  auto vert = [&](int xx, int yy, bool& ok) -> V3<J> {
+    J d = jload<J>(Dl, n, size_t(yy) * Wl + xx);
+    ok = d.re() > T(0);
+    J rx = (jconst<J>(T(xx)) - cx) / fx;
+    J ry = (jconst<J>(T(yy)) - cy) / fy;
+    return {d * rx, d * ry, d};
+  };
+  bool ok0;
+  V3<J> v0 = vert(x, y, ok0);
+  const J z = jzero<J>();
+  vstore(Vout, n, i, ok0 ? v0 : V3<J>{z, z, z});
+  bool okn = false;
+  V3<J> nn = {z, z, z};
+  if (ok0 && x + 1 < Wl && y + 1 < Hl) {
+    bool ok1, ok2;
+    V3<J> v1 = vert(x + 1, y, ok1);
+    V3<J> v2 = vert(x, y + 1, ok2);
+    if (ok1 && ok2) {
+      V3<J> a = vsub(v1, v0), b = vsub(v2, v0);
+      V3<J> c = vcross(b, a);
+      J cc = vdot(c, c);
+      if (cc.re() > T(0)) {
+        J inv = jconst<J>(T(1)) / jsqrt(cc);
+        nn = vscale(inv, c);
+        okn = true;
+      }
+    }
+  }
+  vstore(Nout, n, i, nn);
+  valid[i] = okn ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// A3-A5. projective association, point-to-plane residual and Jacobian, the
+// 6x6 normal equations, and (last block) the FP64 solve and SE(3) update.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int Q>
+struct IcpArgs {
+  const T* V; const T* N; const uint8_t* valid;               // current level (camera frame)
+  const T* Vm; const T* Nm; const T* Zm; const uint8_t* validm;  // model level (world frame)
+  int W, H, level, iter_slot, do_solve;
+  KPose<T, D, Q>* Kcur;        // current estimate (kernel precision), updated by the last block
+  const KPose<T, D, Q>* Kprev; // projection reference T_{k-1}
+  MPose<D, Q>* Pcur;           // current estimate (FP64 master)
+  Jet<double, D, Q> omega;     // step relaxation of this level
+  T* partials;                 // [blocks][NS]
+  unsigned* ticket;
+  int* lost;
+  int32_t* counters;           // row of the current frame
+  double* sums_out;            // icp_pass: [NS] FP64 sums
+};
+
+template <int D, int Q> struct IcpSize {
+  static constexpr int NC = Jet<float, D, Q>::N;
+  static constexpr int NS = 27 * NC + 2;
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// 6x6 symmetric solve with a real LDL^T factorisation of the real part and
+// first/second-order parts from A x = -b differentiated (no conjugation).
+template <int D, int Q>
+__device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
+  constexpr int NC = Jet<double, D, Q>::N;
+  double A0[6][6], L[6][6], dd[6];
+  int k = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b, ++k) { A0[a][b] = sums[k * NC]; A0[b][a] = sums[k * NC]; }
+  double dmax = 0.0;
+  for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A0[a][a]);
+  for (int j = 0; j < 6; ++j) {
+    double s = A0[j][j];
+    for (int q = 0; q < j; ++q) s -= L[j][q] * L[j][q] * dd[q];
+    if (!(s > 1e-12 * dmax)) return false;
+    dd[j] = s;
+    L[j][j] = 1.0;
+    for (int i = j + 1; i < 6; ++i) {
+      double t = A0[i][j];
+      for (int q = 0; q < j; ++q) t -= L[i][q] * L[j][q] * dd[q];
+      L[i][j] = t / s;
+    }
+  }
+  auto solve = [&](const double rhs[6], double x[6]) {
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+      double t = rhs[i];
+      for (int q = 0; q < i; ++q) t -= L[i][q] * y[q];
+      y[i] = t;
+    }
+    for (int i = 5; i >= 0; --i) {
+      double t = y[i] / dd[i];
+      for (int q = i + 1; q < 6; ++q) t -= L[q][i] * x[q];
+      x[i] = t;
+    }
+  };
+  // component c of the symmetric matrix / vector
+  auto Amul = [&](int c, const double v[6], double out[6]) {
+    for (int a = 0; a < 6; ++a) out[a] = 0.0;
+    int kk = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b, ++kk) {
+        double m = sums[kk * NC + c];
+        out[a] += m * v[b];
+        if (b != a) out[b] += m * v[a];
+      }
+  };
+  double X[NC][6];
+  double rhs[6], t1[6], t2[6];
+  for (int a = 0; a < 6; ++a) rhs[a] = -sums[(21 + a) * NC];
+  solve(rhs, X[0]);
+  for (int d = 1; d <= D; ++d) {
+    Amul(d, X[0], t1);
+    for (int a = 0; a < 6; ++a) rhs[a] = -(sums[(21 + a) * NC + d] + t1[a]);
+    solve(rhs, X[d]);
+  }
+  int p = 1 + D;
+  for (int a = 0; a < Q; ++a)
+    for (int b = a; b < Q; ++b, ++p) {
+      Amul(p, X[0], t1);
+      for (int i = 0; i < 6; ++i) rhs[i] = -(sums[(21 + i) * NC + p] + t1[i]);
+      Amul(1 + a, X[1 + b], t1);
+      Amul(1 + b, X[1 + a], t2);
+      for (int i = 0; i < 6; ++i) rhs[i] -= t1[i] + t2[i];
+      solve(rhs, X[p]);
+    }
+  for (int a = 0; a < 6; ++a)
+    for (int c = 0; c < NC; ++c) dx[a].v[c] = X[c][a];
+  return true;
+}
+
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
+  using J = Jet<T, D, Q>;
+  constexpr int NC = J::N;
+  constexpr int NS = IcpSize<D, Q>::NS;
+  __shared__ T red[kIcpThreads / 64][NS];
+  __shared__ double fin[NS];
+  __shared__ unsigned is_last;
+  if (*g.lost) return;   // set by an earlier launch: every block leaves, no ticket taken
+
+  const KPose<T, D, Q> Tc = *g.Kcur;
+  const KPose<T, D, Q> Tp = *g.Kprev;
+  const T sc = T(1) / T(1 << g.level);
+  const J fx = kp.fx * sc, fy = kp.fy * sc, cx = kp.cx * sc, cy = kp.cy * sc;
+  const int W = g.W, H = g.H;
+  const size_t n = size_t(W) * H;
+
+  T acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0;
+
+  for (size_t i = size_t(blockIdx.x) * kIcpThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kIcpThreads) {
+    if (!g.valid[i]) continue;
+    const V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+    const V3<J> p = pose_apply(Tc, v);
+    const V3<J> nr = pose_rotate(Tc, nv);
+    const V3<J> xc = pose_apply_inv(Tp, p);
+    if (!(xc.z.re() > T(0))) continue;
+    const J ux = fx * xc.x / xc.z + cx;
+    const J uy = fy * xc.y / xc.z + cy;
+    // tap choice floor(u + 1e-3): at the first pass of a level every pixel
+    // re-projects onto its own integer coordinate up to rounding
+    const T rx = ux.re(), ry = uy.re();
+    const T fx0 = floor(rx + T(kTapBias)), fy0 = floor(ry + T(kTapBias));
+    if (!(fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2))) continue;
+    const int i0 = int(fx0), j0 = int(fy0);
+    const size_t t0 = size_t(j0) * W + i0, t1 = t0 + 1, t2 = t0 + W, t3 = t2 + 1;
+    if (!(g.validm[t0] && g.validm[t1] && g.validm[t2] && g.validm[t3])) continue;
+    const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
+    const size_t tn = size_t(jn) * W + in;
+    const T zn = g.Zm[tn];
+    const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
+    V3<J> q, m;
+    if (disc >= kp.disc_delta) {
+      q = vload<J>(g.Vm, n, tn);
+      m = vload<J>(g.Nm, n, tn);
+    } else {
+      const J a = ux - fx0, b = uy - fy0;
+      const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
+      const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+      const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+      q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
+      const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+      const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+      V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
+      m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
+    }
+    const V3<J> d = vsub(p, q);
+    if (!(vdot(d, d).re() <= kp.dgate2)) continue;
+    if (!(vdot(nr, m).re() >= kp.cos_agate)) continue;
+    const J r = vdot(d, m);
+    const V3<J> pm = vcross(p, m);
+    const J jac[6] = {pm.x, pm.y, pm.z, m.x, m.y, m.z};
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a; b < 6; ++b, ++k) {
+        const J prod = jac[a] * jac[b];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[k * NC + c] += prod.v[c];
+      }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const J prod = jac[a] * r;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[(21 + a) * NC + c] += prod.v[c];
+    }
+    acc[27 * NC] += T(1);
+    acc[27 * NC + 1] += r.re() * r.re();
+  }
+
+  // block reduction: wave butterflies, then the 4 waves in fixed order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    T s = wave_sum(acc[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  T* part = g.partials + size_t(blockIdx.x) * NS;
+  for (int k = threadIdx.x; k < NS; k += kIcpThreads) {
+    T s = red[0][k];
+#pragma unroll
+    for (int w = 1; w < kIcpThreads / 64; ++w) s += red[w][k];
+    part[k] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(g.ticket, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+
+  // last block: fixed-order FP64 sum over blocks
+  for (int k = threadIdx.x; k < NS; k += kIcpThreads) {
+    double s = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) s += double(__builtin_nontemporal_load(g.partials + size_t(b) * NS + k));
+    fin[k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  *g.ticket = 0u;
+  const int cnt = int(fin[27 * NC]);
+  if (!g.do_solve) {
+    for (int k = 0; k < NS; ++k) g.sums_out[k] = fin[k];
+    return;
+  }
+  g.counters[3] += cnt;
+  g.counters[4] = cnt;
+  if (g.iter_slot < kCounters - 5) g.counters[5 + g.iter_slot] = cnt;
+  Jet<double, D, Q> dx[6];
+  if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
+    *g.lost = 1;
+    g.counters[0] = 1;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) dx[a] = g.omega * dx[a];
+  MPose<D, Q> E = se3_exp<D, Q>(dx);
+  MPose<D, Q> Pn = pose_mul(E, *g.Pcur);
+  *g.Pcur = Pn;
+  *g.Kcur = to_kpose<T, double>(Pn);
+}
+
+// start of tracking for frame k >= 1: shift the pose history and set the
+// initial estimate (previous pose, or constant velocity T1 T2^-1 T1)
+template <typename T, int D, int Q>
+__global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>* Pprev2, MPose<D, Q>* Pinit,
+                              KPose<T, D, Q>* Kcur, KPose<T, D, Q>* Kprev, int* lost, int32_t* counters,
+                              int const_vel) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *Pprev2 = *Pprev;
+  *Pprev = *Pcur;
+  MPose<D, Q> init = *Pprev;
+  if (const_vel) init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
+  *Pinit = init;
+  *Pcur = init;
+  *Kcur = to_kpose<T, double>(init);
+  *Kprev = to_kpose<T, double>(*Pprev);
+  *lost = 0;
+  for (int i = 0; i < kCounters; ++i) counters[i] = 0;
+}
+
+// end of tracking: a lost frame keeps its initial estimate
+template <typename T, int D, int Q>
+__global__ void k_track_end(MPose<D, Q>* Pcur, const MPose<D, Q>* Pinit, KPose<T, D, Q>* Kcur, const int* lost) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (*lost) {
+    *Pcur = *Pinit;
+    *Kcur = to_kpose<T, double>(*Pinit);
+  }
+}
+
+template <int D, int Q>
+__global__ void k_store_pose(const MPose<D, Q>* Pcur, MPose<D, Q>* history, int frame) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) history[frame] = *Pcur;
+}
+
+// ---------------------------------------------------------------------------
+// A6. TSDF fusion (Sec. 4.1 "Surface Update"), one workgroup per 8^3 brick.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int Q>
+__device__ __forceinline__ void voxel_centre(const KParams<T, D, Q>& kp, int i, int j, int k, T c[3]) {
+  const double s = double(kp.voxel);
+  c[0] = T((i + 0.5) * s - 0.5 * kp.dim[0] * s);
+  c[1] = T((j + 0.5) * s - 0.5 * kp.dim[1] * s);
+  c[2] = T((k + 0.5) * s - 0.5 * kp.dim[2] * s);
+}
+
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                    const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
+                                                    T* __restrict__ Ftan, T* __restrict__ Wtan,
+                                                    const int* __restrict__ lost, int32_t* __restrict__ counters,
+                                                    int64_t nvox) {
+  using J = Jet<T, D, Q>;
+  using R0 = Jet<T, 0, 0>;
+  if (*lost) return;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
+  const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
+  const int64_t vi = int64_t(b) * kBrickVox + t;
+  const int W = kp.W, H = kp.H;
+  const size_t n = size_t(W) * H;
+  T cc[3];
+  voxel_centre(kp, i, j, k, cc);
+
+  // ---- decisions on real parts
+  const KPose<T, D, Q>& P = *Kk;
+  KPose<T, 0, 0> Pr;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Pr.R[q].v[0] = P.R[q].re();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Pr.t[q].v[0] = P.t[q].re();
+  const V3<R0> cr = {jconst<R0>(cc[0]), jconst<R0>(cc[1]), jconst<R0>(cc[2])};
+  const V3<R0> xr = pose_apply_inv(Pr, cr);
+  bool upd = false;
+  int i0 = 0, j0 = 0;
+  bool nearest = false;
+  size_t tn = 0;
+  T ux_r = 0, uy_r = 0;
+  if (xr.z.re() > T(0)) {
+    ux_r = kp.fx.re() * xr.x.re() / xr.z.re() + kp.cx.re();
+    uy_r = kp.fy.re() * xr.y.re() / xr.z.re() + kp.cy.re();
+    const T fx0 = floor(ux_r), fy0 = floor(uy_r);
+    if (fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2)) {
+      i0 = int(fx0);
+      j0 = int(fy0);
+      const size_t t0 = size_t(j0) * W + i0;
+      const T d0 = Df[t0], d1 = Df[t0 + 1], d2 = Df[t0 + W], d3 = Df[t0 + W + 1];
+      if (d0 > T(0) && d1 > T(0) && d2 > T(0) && d3 > T(0)) {
+        const int in = int(floor(ux_r + T(0.5))), jn = int(floor(uy_r + T(0.5)));
+        tn = size_t(jn) * W + in;
+        const T dn = Df[tn];
+        const T disc = fabs(d0 - dn) + fabs(d1 - dn) + fabs(d2 - dn) + fabs(d3 - dn);
+        T L;
+        if (disc >= kp.disc_delta) {
+          nearest = true;
+          L = dn;
+        } else {
+          const T a = ux_r - fx0, bb = uy_r - fy0;
+          const T a1 = T(1) - a, b1 = T(1) - bb;
+          L = b1 * (a1 * d0 + a * d1) + bb * (a1 * d2 + a * d3);
+        }
+        const T eta = L - xr.z.re();
+        upd = !(eta < -kp.mu.re());
+      }
+    }
+  }
+  // updated-voxel count: one atomic per wave
+  const unsigned long long bal = __ballot(upd);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(counters + 1, int(__popcll(bal)));
+  if (!upd) return;
+
+  // ---- the update in complex-step arithmetic
+  const V3<J> c = {jconst<J>(cc[0]), jconst<J>(cc[1]), jconst<J>(cc[2])};
+  const V3<J> x = pose_apply_inv(P, c);
+  const J ux = kp.fx * x.x / x.z + kp.cx;
+  const J uy = kp.fy * x.y / x.z + kp.cy;
+  J L;
+  if (nearest) {
+    L = jload<J>(Df, n, tn);
+  } else {
+    const size_t t0 = size_t(j0) * W + i0;
+    const J a = ux - T(i0), bb = uy - T(j0);
+    const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - bb;
+    L = b1 * (a1 * jload<J>(Df, n, t0) + a * jload<J>(Df, n, t0 + 1)) +
+        bb * (a1 * jload<J>(Df, n, t0 + W) + a * jload<J>(Df, n, t0 + W + 1));
+  }
+  const J eta = L - x.z;
+  const J Fd = (eta.re() >= kp.mu.re()) ? jconst<J>(T(1)) : eta / kp.mu;
+  auto r = rec[vi];
+  J F, Wj;
+  F.v[0] = r.x;
+#pragma unroll
+  for (int q = 1; q < J::N; ++q) F.v[q] = Ftan[size_t(q - 1) * nvox + vi];
+  Wj = jconst<J>(r.y);
+  if (Wtan != nullptr) {
+    const T wt = Wtan[vi];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (q == kp.wcap_dir) Wj.v[1 + q] = wt;
+  }
+  const J Fn = (Wj * F + Fd) / (Wj + T(1));
+  const J Wn = (Wj.re() + T(1) < kp.wcap.re()) ? Wj + T(1) : kp.wcap;
+  r.x = Fn.v[0];
+  r.y = Wn.v[0];
+  rec[vi] = r;
+#pragma unroll
+  for (int q = 1; q < J::N; ++q) Ftan[size_t(q - 1) * nvox + vi] = Fn.v[q];
+  if (Wtan != nullptr) {
+    T wt = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (q == kp.wcap_dir) wt = Wn.v[1 + q];
+    Wtan[vi] = wt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A7. raycast (Sec. 4.1 "Ray casting", eq. "surface_prediction") and the
+// model-map pyramid (level l = level 0 sampled at (2^l x, 2^l y)).
+// ---------------------------------------------------------------------------
+template <typename T, int D, int Q>
+struct MapsOut {
+  T* V[3]; T* N[3]; T* Z[3]; uint8_t* valid[3];
+};
+
+// trilinear TSDF at a real point; valid iff all 8 corners observed (W > 0)
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
+                                             const T v[3], T& out) {
+  int i0[3];
+  T f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T ga = (v[a] + kp.half[a]) / kp.voxel - T(0.5);
+    const T fl = floor(ga);
+    if (!(fl >= T(0) && fl <= T(kp.dim[a] - 2))) return false;
+    i0[a] = int(fl);
+    f[a] = ga - fl;
+  }
+  T c[8];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const auto r = rec[vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr)];
+        if (!(r.y > T(0))) return false;
+        c[dz * 4 + dy * 2 + dx] = r.x;
+      }
+  const T fx1 = T(1) - f[0], fy1 = T(1) - f[1], fz1 = T(1) - f[2];
+  const T c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
+  const T c01 = fx1 * c[4] + f[0] * c[5], c11 = fx1 * c[6] + f[0] * c[7];
+  const T c0 = fy1 * c00 + f[1] * c10, c1 = fy1 * c01 + f[1] * c11;
+  out = fz1 * c0 + f[2] * c1;
+  return true;
+}
+
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool trilinear_jet(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
+                                              const T* __restrict__ Ftan, int64_t nvox, const V3<Jet<T, D, Q>>& v,
+                                              Jet<T, D, Q>& out) {
+  using J = Jet<T, D, Q>;
+  const J* g3[3] = {&v.x, &v.y, &v.z};
+  int i0[3];
+  J f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const J ga = (*g3[a] + kp.half[a]) / kp.voxel - T(0.5);
+    const T fl = floor(ga.re());
+    if (!(fl >= T(0) && fl <= T(kp.dim[a] - 2))) return false;
+    i0[a] = int(fl);
+    f[a] = ga - fl;
+  }
+  J c[8];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int64_t id = vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr);
+        const auto r = rec[id];
+        if (!(r.y > T(0))) return false;
+        J& cj = c[dz * 4 + dy * 2 + dx];
+        cj.v[0] = r.x;
+#pragma unroll
+        for (int q = 1; q < J::N; ++q) cj.v[q] = Ftan[size_t(q - 1) * nvox + id];
+      }
+  const J one = jconst<J>(T(1));
+  const J fx1 = one - f[0], fy1 = one - f[1], fz1 = one - f[2];
+  const J c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
+  const J c01 = fx1 * c[4] + f[0] * c[5], c11 = fx1 * c[6] + f[0] * c[7];
+  const J c0 = fy1 * c00 + f[1] * c10, c1 = fy1 * c01 + f[1] * c11;
+  out = fz1 * c0 + f[2] * c1;
+  return true;
+}
+
+// The ray o + alpha R K^-1 (u,1) is marched on real parts only: half a voxel
+// while the last sample is observed and inside the band (F < 0.999), else
+// 0.8 mu; from max(near, entry) to the exit of the volume shrunk by one voxel.
+// F_m > 0 > F_{m+1} between consecutive valid samples is a hit (then both
+// samples are re-evaluated in complex-step arithmetic); - to + stops the ray.
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                 const typename Vec2<T>::type* __restrict__ rec,
+                                                 const T* __restrict__ Ftan, int64_t nvox, MapsOut<T, D, Q> out,
+                                                 int32_t* __restrict__ counters) {
+  using J = Jet<T, D, Q>;
+  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  const int W = kp.W, H = kp.H;
+  const bool inside = x < W && y < H;
+  bool ok = false;
+  const J z = jzero<J>();
+  V3<J> Vg = {z, z, z}, Ng = {z, z, z};
+  T zhit = 0;
+  if (inside) {
+    const KPose<T, D, Q>& P = *Kk;
+    const V3<J> dh = {(jconst<J>(T(x)) - kp.cx) / kp.fx, (jconst<J>(T(y)) - kp.cy) / kp.fy, jconst<J>(T(1))};
+    const V3<J> dir = pose_rotate(P, dh);
+    const V3<J> o = {P.t[0], P.t[1], P.t[2]};
+    const T orr[3] = {o.x.re(), o.y.re(), o.z.re()};
+    const T dr[3] = {dir.x.re(), dir.y.re(), dir.z.re()};
+    const T nrm = sqrt(dh.x.re() * dh.x.re() + dh.y.re() * dh.y.re() + T(1));
+    const T s = kp.voxel;
+    T tmin = T(-1e30), tmax = T(1e30);
+    bool miss = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T lo = -kp.half[a] + s, hi = kp.half[a] - s;
+      if (dr[a] != T(0)) {
+        const T t1 = (lo - orr[a]) / dr[a], t2 = (hi - orr[a]) / dr[a];
+        tmin = fmax(tmin, fmin(t1, t2));
+        tmax = fmin(tmax, fmax(t1, t2));
+      } else if (orr[a] < lo || orr[a] > hi) {
+        miss = true;
+      }
+    }
+    T alpha = fmax(kp.near_m, tmin);
+    const T mu = kp.mu.re();
+    const T small = T(0.5) * s / nrm, big = T(0.8) * mu / nrm;
+    bool prev_ok = false;
+    T a_prev = 0, f_prev = 0;
+    for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it) {
+      const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
+      T f;
+      const bool okf = trilinear_re(kp, rec, v, f);
+      if (!okf) f = 0;
+      if (okf && prev_ok) {
+        if (f_prev > T(0) && f < T(0)) {
+          J F0, F1;
+          const V3<J> v0 = vadd(o, vscale(jconst<J>(a_prev), dir));
+          const V3<J> v1 = vadd(o, vscale(jconst<J>(alpha), dir));
+          bool ok0 = trilinear_jet(kp, rec, Ftan, nvox, v0, F0);
+          bool ok1 = trilinear_jet(kp, rec, Ftan, nvox, v1, F1);
+          if (ok0 && ok1) {
+            const J a0 = jconst<J>(a_prev) - jconst<J>(alpha - a_prev) * F0 / (F1 - F0);
+            const V3<J> V = vadd(o, vscale(a0, dir));
+            J gr[3];
+            bool okg = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              V3<J> vp = V, vm = V;
+              if (a == 0) { vp.x = V.x + s; vm.x = V.x - s; }
+              if (a == 1) { vp.y = V.y + s; vm.y = V.y - s; }
+              if (a == 2) { vp.z = V.z + s; vm.z = V.z - s; }
+              J fp, fm;
+              okg = okg && trilinear_jet(kp, rec, Ftan, nvox, vp, fp) && trilinear_jet(kp, rec, Ftan, nvox, vm, fm);
+              if (okg) gr[a] = fp - fm;
+            }
+            if (okg) {
+              const V3<J> gv = {gr[0], gr[1], gr[2]};
+              const J gg = vdot(gv, gv);
+              if (gg.re() > T(0)) {
+                ok = true;
+                Vg = V;
+                Ng = vscale(jconst<J>(T(1)) / jsqrt(gg), gv);
+                zhit = a0.re();
+              }
+            }
+          }
+          break;
+        }
+        if (f_prev < T(0) && f > T(0)) break;
+      }
+      const T step = (okf && f < T(0.999)) ? small : big;
+      prev_ok = okf;
+      a_prev = alpha;
+      f_prev = f;
+      alpha = alpha + step;
+    }
+  }
+  const unsigned long long bal = __ballot(ok);
+  if ((threadIdx.y * 16 + threadIdx.x) % 64 == 0 && bal) atomicAdd(counters + 2, int(__popcll(bal)));
+  if (!inside) return;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if ((x & ((1 << l) - 1)) || (y & ((1 << l) - 1))) break;
+    const int Wl = W >> l, Hl = H >> l;
+    const size_t nl = size_t(Wl) * Hl, il = size_t(y >> l) * Wl + (x >> l);
+    vstore(out.V[l], nl, il, Vg);
+    vstore(out.N[l], nl, il, Ng);
+    out.Z[l][il] = zhit;
+    out.valid[l][il] = ok ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// trajectory error (translational RMSE, no alignment), FP64
+// ---------------------------------------------------------------------------
+template <int D, int Q>
+__global__ void k_traj_err(const MPose<D, Q>* hist, const double* gt, int n, double* out) {
+  using J = Jet<double, D, Q>;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  J acc = jzero<J>();
+  for (int k = 0; k < n; ++k)
+    for (int r = 0; r < 3; ++r) {
+      J d = hist[k].m[9 + r] - gt[k * 16 + r * 4 + 3];
+      acc = acc + d * d;
+    }
+  J e = jsqrt(acc / double(n));
+  for (int c = 0; c < J::N; ++c) out[c] = e.v[c];
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion between bricks and x-fastest linear order (get/set)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_vol_gather(const typename Vec2<T>::type* rec, const T* Ftan, const T* Wtan, int comp_kind,
+                             int comp, int64_t nvox, int nx, int ny, int nbx, int nby, int64_t start, int64_t count,
+                             T* dst) {
+  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  int64_t li = start + q;
+  int i = int(li % nx), j = int((li / nx) % ny), k = int(li / (int64_t(nx) * ny));
+  int nbr[3] = {nbx, nby, 0};
+  int64_t vi = vox_index(i, j, k, nbr);
+  T v;
+  if (comp_kind == 0) v = rec[vi].x;                       // F real
+  else if (comp_kind == 1) v = rec[vi].y;                  // W real
+  else if (comp_kind == 2) v = Ftan[size_t(comp) * nvox + vi];
+  else v = Wtan ? Wtan[vi] : T(0);                         // W weight-cap part
+  dst[q] = v;
+}
+
+template <typename T>
+__global__ void k_vol_scatter(typename Vec2<T>::type* rec, T* Ftan, T* Wtan, int comp_kind, int comp, int64_t nvox,
+                              int nx, int ny, int nbx, int nby, int64_t start, int64_t count, const T* src) {
+  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  int64_t li = start + q;
+  int i = int(li % nx), j = int((li / nx) % ny), k = int(li / (int64_t(nx) * ny));
+  int nbr[3] = {nbx, nby, 0};
+  int64_t vi = vox_index(i, j, k, nbr);
+  T v = src[q];
+  if (comp_kind == 0) rec[vi].x = v;
+  else if (comp_kind == 1) rec[vi].y = v;
+  else if (comp_kind == 2) Ftan[size_t(comp) * nvox + vi] = v;
+  else if (Wtan) Wtan[vi] = v;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace xs

@@ -1,0 +1,323 @@
+"""ctypes binding of libxslam.so (include/xslam.h): argument marshalling only.
+
+Every step of the frame runs in the library's HIP kernels; PyTorch provides the
+device memory (one uint8 workspace tensor, input depth tensors) and the stream.
+If the library is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxslam.so")
+
+# status codes
+OK, WARN_TRACK_LOST = 0, 1
+ERR_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+C64, C128 = 0, 1
+(P_PHI_X, P_PHI_Y, P_PHI_Z, P_RHO_X, P_RHO_Y, P_RHO_Z, P_TRUNC, P_WCAP, P_DGATE, P_AGATE,
+ P_ICPW0, P_ICPW1, P_ICPW2, P_FX, P_FY, P_CX, P_CY, P_DEPTH) = range(18)
+(F_POSE, F_POSES, F_TSDF, F_WEIGHT, F_VMAP, F_NMAP, F_ZMAP, F_MVALID, F_MEAS_DEPTH, F_MEAS_V,
+ F_MEAS_N, F_MEAS_VALID, F_COUNTERS, F_PREV_POSE, F_FRAME) = range(15)
+N_COUNTERS = 32
+
+
+class xslam_dir(C.Structure):
+    _fields_ = [("param", C.c_int32), ("h", C.c_double)]
+
+
+class xslam_pair(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32)]
+
+
+class xslam_perturbation(C.Structure):
+    _fields_ = [("n_dirs", C.c_int32), ("dirs", C.POINTER(xslam_dir)),
+                ("n_pairs", C.c_int32), ("pairs", C.POINTER(xslam_pair))]
+
+
+class xslam_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class xslam_volume(C.Structure):
+    _fields_ = [("dim", C.c_int32 * 3), ("voxel", C.c_double), ("trunc", C.c_double), ("wcap", C.c_double)]
+
+
+class xslam_icp(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 3), ("dgate", C.c_double), ("agate_deg", C.c_double),
+                ("level_w", C.c_double * 3), ("disc_delta", C.c_double), ("init", C.c_int32)]
+
+
+class xslam_config(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("cam", xslam_camera), ("vol", xslam_volume), ("icp", xslam_icp),
+                ("bilateral_radius", C.c_int32), ("bilateral_sigma_px", C.c_double),
+                ("bilateral_sigma_m", C.c_double), ("near_m", C.c_double), ("max_frames", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libxslam.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2405_02187_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        cfgp, pertp = C.POINTER(xslam_config), C.POINTER(xslam_perturbation)
+        sig = {
+            "xslam_components": (C.c_int32, [pertp]),
+            "xslam_workspace_bytes": (C.c_size_t, [cfgp, pertp]),
+            "xslam_create": (C.c_int, [cfgp, pertp, vp, C.c_size_t, vp, dp, C.POINTER(vp)]),
+            "xslam_measure": (C.c_int, [vp, vp, vp]),
+            "xslam_integrate": (C.c_int, [vp, vp, vp, dp]),
+            "xslam_raycast": (C.c_int, [vp, dp, vp, vp]),
+            "xslam_track": (C.c_int, [vp, vp, vp, dp]),
+            "xslam_step": (C.c_int, [vp, vp, vp, dp]),
+            "xslam_icp_pass": (C.c_int, [vp, C.c_int32, dp]),
+            "xslam_traj_err": (C.c_int, [vp, dp, C.c_int32, dp]),
+            "xslam_get": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
+            "xslam_set": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
+            "xslam_set_timing": (C.c_int, [vp, C.c_int32]),
+            "xslam_kernel_times": (C.c_int, [vp, dp, i64p]),
+            "xslam_sync": (C.c_int, [vp]),
+            "xslam_last_error": (C.c_char_p, [vp]),
+            "xslam_destroy": (C.c_int, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+EXPORTS = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
+           "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
+           "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
+           "xslam_destroy"]
+
+
+class XslamError(RuntimeError):
+    pass
+
+
+# --------------------------------------------------------------------------
+def make_config(prec=C64, width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5, dim=(512, 512, 512),
+                voxel=0.01, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
+                level_w=(1.0, 1.0, 1.0), disc_delta=0.1, init=0, bilateral_radius=3, sigma_px=4.5, sigma_m=0.03,
+                near_m=0.1, max_frames=512) -> xslam_config:
+    c = xslam_config()
+    c.prec = prec
+    c.cam = xslam_camera(width, height, fx, fy, cx, cy)
+    c.vol.dim[:] = list(dim)
+    c.vol.voxel, c.vol.trunc, c.vol.wcap = voxel, trunc, wcap
+    c.icp.iters[:] = list(iters)
+    c.icp.dgate, c.icp.agate_deg = dgate, agate_deg
+    c.icp.level_w[:] = list(level_w)
+    c.icp.disc_delta, c.icp.init = disc_delta, init
+    c.bilateral_radius, c.bilateral_sigma_px, c.bilateral_sigma_m = bilateral_radius, sigma_px, sigma_m
+    c.near_m, c.max_frames = near_m, max_frames
+    return c
+
+
+def config_from_preset(p: dict, prec=None, **kw) -> xslam_config:
+    cam = p["camera"]
+    args = dict(prec=(C128 if p["prec"] == "c128" else C64) if prec is None else prec,
+                width=cam["width"], height=cam["height"], fx=cam["fx"], fy=cam["fy"], cx=cam["cx"], cy=cam["cy"],
+                dim=(p["dim"],) * 3, voxel=p["voxel"], trunc=p["trunc"], wcap=p["wcap"],
+                iters=tuple(p["icp"]["iters"]), dgate=p["icp"]["dgate"], agate_deg=p["icp"]["agate_deg"],
+                max_frames=p["n_frames"])
+    args.update(kw)
+    return make_config(**args)
+
+
+class Perturbation:
+    """Directions [(param, h), ...] and Hessian size q (pairs over the first q)."""
+
+    def __init__(self, dirs=(), q: int = 0):
+        self.dirs = list(dirs)
+        self.q = q
+        self._d = (xslam_dir * max(1, len(self.dirs)))(*[xslam_dir(p, h) for p, h in self.dirs])
+        pairs = [(a, b) for a in range(q) for b in range(a, q)]
+        self._p = (xslam_pair * max(1, len(pairs)))(*[xslam_pair(a, b) for a, b in pairs])
+        self.c = xslam_perturbation(len(self.dirs), self._d, len(pairs), self._p)
+
+    @property
+    def ncomp(self) -> int:
+        return 1 + len(self.dirs) + self.q * (self.q + 1) // 2
+
+
+def workspace_bytes(cfg: xslam_config, pert: Perturbation) -> int:
+    return lib().xslam_workspace_bytes(C.byref(cfg), C.byref(pert.c))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Slam:
+    """One context: workspace from torch, calls on torch's current stream."""
+
+    def __init__(self, cfg: xslam_config, pert: Perturbation, T0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.cfg, self.pert = cfg, pert
+        self.nc = pert.ncomp
+        self.dtype = torch.float32 if cfg.prec == C64 else torch.float64
+        self.np_dtype = np.float32 if cfg.prec == C64 else np.float64
+        nbytes = workspace_bytes(cfg, pert)
+        if nbytes == 0:
+            raise XslamError("unsupported or invalid configuration / perturbation")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(device)
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).reshape(16)
+        h = C.c_void_p()
+        self._check(lib().xslam_create(C.byref(cfg), C.byref(pert.c), _ptr(self.ws), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream),
+                                       T0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)), None)
+        self.h = h
+        W, H = cfg.cam.width, cfg.cam.height
+        self.npx = [(W >> l) * (H >> l) for l in range(3)]
+        self.nvox = cfg.vol.dim[0] * cfg.vol.dim[1] * cfg.vol.dim[2]
+
+    def _check(self, rc, h="self", allow_warn=True):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            msg = lib().xslam_last_error(self.h if h == "self" else None)
+            raise XslamError(f"xslam error {rc}: {msg.decode() if msg else ''}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().xslam_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- calls -------------------------------------------------------------
+    def _dd(self, depth_dot):
+        return _ptr(depth_dot)
+
+    def measure(self, depth, depth_dot=None):
+        return self._check(lib().xslam_measure(self.h, _ptr(depth), self._dd(depth_dot)))
+
+    def integrate(self, depth=None, depth_dot=None, pose=None):
+        pp = None if pose is None else np.ascontiguousarray(pose, np.float64).reshape(16)
+        return self._check(lib().xslam_integrate(self.h, _ptr(depth), self._dd(depth_dot),
+                                                 None if pp is None else pp.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def raycast(self, pose=None):
+        pp = None if pose is None else np.ascontiguousarray(pose, np.float64).reshape(16)
+        return self._check(lib().xslam_raycast(self.h, None if pp is None else pp.ctypes.data_as(C.POINTER(C.c_double)),
+                                               None, None))
+
+    def track(self, depth, depth_dot=None, want_pose=True):
+        out = np.zeros((self.nc, 16)) if want_pose else None
+        rc = self._check(lib().xslam_track(self.h, _ptr(depth), self._dd(depth_dot),
+                                           None if out is None else out.ctypes.data_as(C.POINTER(C.c_double))))
+        return rc, out
+
+    def step(self, depth, depth_dot=None, want_pose=False):
+        out = np.zeros((self.nc, 16)) if want_pose else None
+        rc = self._check(lib().xslam_step(self.h, _ptr(depth), self._dd(depth_dot),
+                                          None if out is None else out.ctypes.data_as(C.POINTER(C.c_double))))
+        return rc, out
+
+    def icp_pass(self, level):
+        ns = 27 * self.nc + 2
+        out = np.zeros(ns)
+        self._check(lib().xslam_icp_pass(self.h, level, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out[:27 * self.nc].reshape(27, self.nc), out[27 * self.nc], out[27 * self.nc + 1]
+
+    def traj_err(self, gt):
+        gt = np.ascontiguousarray(gt, np.float64).reshape(-1, 16)
+        out = np.zeros(self.nc)
+        self._check(lib().xslam_traj_err(self.h, gt.ctypes.data_as(C.POINTER(C.c_double)), len(gt),
+                                         out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def sync(self):
+        return self._check(lib().xslam_sync(self.h))
+
+    def set_timing(self, on=True):
+        return self._check(lib().xslam_set_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        self._check(lib().xslam_kernel_times(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                             n.ctypes.data_as(C.POINTER(C.c_int64))))
+        return ms, n
+
+    # ---- state -------------------------------------------------------------
+    def _field_shape(self, field):
+        nc, n0 = self.nc, self.npx[0]
+        tot = sum(self.npx)
+        fl = self.np_dtype
+        if field in (F_POSE, F_PREV_POSE):
+            return (nc, 4, 4), np.float64
+        if field == F_POSES:
+            return (self.frame(), nc, 4, 4), np.float64
+        if field in (F_TSDF, F_WEIGHT):
+            return (nc, self.nvox), fl
+        if field in (F_VMAP, F_NMAP):
+            return (3, nc, n0), fl
+        if field == F_ZMAP:
+            return (n0,), fl
+        if field == F_MVALID:
+            return (n0,), np.uint8
+        if field == F_MEAS_DEPTH:
+            return (nc * tot,), fl
+        if field in (F_MEAS_V, F_MEAS_N):
+            return (3 * nc * tot,), fl
+        if field == F_MEAS_VALID:
+            return (tot,), np.uint8
+        if field == F_COUNTERS:
+            return (min(self.frame(), self.cfg.max_frames), N_COUNTERS), np.int32
+        raise ValueError(field)
+
+    def frame(self):
+        v = np.zeros(1, np.int32)
+        self._check(lib().xslam_get(self.h, F_FRAME, v.ctypes.data_as(C.c_void_p), 4))
+        return int(v[0])
+
+    def get(self, field):
+        shape, dt = self._field_shape(field)
+        out = np.zeros(shape, dtype=dt)
+        self._check(lib().xslam_get(self.h, field, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def set(self, field, value):
+        shape, dt = self._field_shape(field)
+        v = np.ascontiguousarray(value, dtype=dt).reshape(shape)
+        self._check(lib().xslam_set(self.h, field, v.ctypes.data_as(C.c_void_p), v.nbytes))
+
+    def set_frame(self, k):
+        v = np.array([k], np.int32)
+        self._check(lib().xslam_set(self.h, F_FRAME, v.ctypes.data_as(C.c_void_p), 4))
+
+    def measured(self):
+        """-> per level dict(D (nc,H,W), V (3,nc,H,W), N, valid (H,W))."""
+        W, H = self.cfg.cam.width, self.cfg.cam.height
+        D = self.get(F_MEAS_DEPTH)
+        V = self.get(F_MEAS_V)
+        N = self.get(F_MEAS_N)
+        M = self.get(F_MEAS_VALID)
+        out, o1, o3 = [], 0, 0
+        for l in range(3):
+            n, h, w = self.npx[l], H >> l, W >> l
+            out.append(dict(D=D[o1 * self.nc:(o1 + n) * self.nc].reshape(self.nc, h, w),
+                            V=V[o3 * self.nc:(o3 + 3 * n) * self.nc].reshape(3, self.nc, h, w),
+                            N=N[o3 * self.nc:(o3 + 3 * n) * self.nc].reshape(3, self.nc, h, w),
+                            valid=M[o1:o1 + n].reshape(h, w)))
+            o1 += n
+            o3 += 3 * n
+        return out

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP frame step (through the C ABI) against the CPU oracle.
+
+FP64-complex: validity masks and counts bit-exact, values within 1e-10
+relative.  FP32-complex: poses and derivatives within 1e-5 relative.  Every
+input is seeded (scenegen) and identical on both sides.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as sg
+from gpu_util import gpu_map_to_oracle, gpu_pose_to_oracle, log, oracle_map_to_gpu, relerr, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_02187_amd import xslam as X  # noqa: E402
+
+H20 = 1e-20
+
+
+def c0_seq(n=None):
+    p = sg.preset("c0")
+    seq = sg.make_sequence(p, n_frames=n)
+    return p, seq
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_c0(param, n, depths, T0, p):
+    key = (param, n, depths.dtype.str)
+    if key not in _ORACLE_CACHE:
+        log("oracle c0", key)
+        _ORACLE_CACHE[key] = O.run_sequence(O.config(p), O.seed(1, param, h=H20), depths.astype(np.float64), T0)
+    return _ORACLE_CACHE[key]
+
+
+def run_gpu_sequence(p, depths, T0, prec, dirs, ddots=None):
+    cfg = X.config_from_preset(p, prec=prec, max_frames=len(depths))
+    slam = X.Slam(cfg, X.Perturbation(dirs), T0)
+    dt = np.float64 if prec == X.C128 else np.float32
+    dev = torch_dev(depths, dt)
+    ddev = None if ddots is None else torch_dev(ddots, dt)
+    for k in range(len(depths)):
+        slam.step(dev[k], None if ddev is None else ddev[k])
+    slam.sync()
+    return slam
+
+
+@pytest.mark.parametrize("param", [O.P_TRUNC, O.P_RHO_Y])
+def test_c0_fp64_sequence_matches_oracle(param):
+    """BASELINE config 0 (20 frames, 128^3, 160x120, FP64-complex) end to end."""
+    p, seq = c0_seq()
+    depths = seq.depths()
+    T0 = seq.poses_gt[0]
+    log("gpu c0 fp64", param)
+    slam = run_gpu_sequence(p, depths, T0, X.C128, [(param, H20)])
+    P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    cnt = slam.get(X.F_COUNTERS)
+    ref = oracle_c0(param, len(depths), depths, T0, p)
+    st = ref["stats"]
+    # decisions: per-frame counts of fused voxels, raycast hits, ICP correspondences
+    assert np.array_equal(cnt[:, 0], st[:, 0].astype(int))
+    assert np.array_equal(cnt[:, 1], st[:, 3].astype(int)), (cnt[:, 1], st[:, 3])
+    assert np.array_equal(cnt[:, 2], st[:, 4].astype(int)), (cnt[:, 2], st[:, 4])
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int)), (cnt[:, 3], st[:, 5])
+    e_re = relerr(P[..., 0], ref["poses"][..., 0])
+    e_im = relerr(P[..., 1], ref["poses"][..., 1])
+    log("c0 fp64 pose rel err", e_re, "derivative rel err", e_im)
+    assert e_re <= 1e-10 and e_im <= 1e-10
+    # final volume
+    F = slam.get(X.F_TSDF)
+    Wt = slam.get(X.F_WEIGHT)
+    refv = O.run_sequence(O.config(p), O.seed(1, param, h=H20), depths, T0, want_volume=True)
+    assert np.array_equal(Wt[0] > 0, refv["W"][:, 0] > 0)
+    assert relerr(F[0], refv["F"][:, 0]) <= 1e-10
+    assert relerr(F[1], refv["F"][:, 1]) <= 1e-10
+    slam.close()
+
+
+def test_c0_fp32_sequence_within_1e5():
+    p, seq = c0_seq()
+    depths = seq.depths().astype(np.float32)
+    T0 = seq.poses_gt[0]
+    h32 = 2.0 ** -20
+    slam = run_gpu_sequence(p, depths, T0, X.C64, [(X.P_TRUNC, h32)])
+    P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    ref = oracle_c0(O.P_TRUNC, len(depths), depths, T0, p)
+    e_re = relerr(P[..., 0], ref["poses"][..., 0])
+    e_im = relerr(P[..., 1] / h32, ref["poses"][..., 1] / H20)
+    log("c0 fp32 pose rel err", e_re, "derivative rel err", e_im)
+    assert e_re <= 1e-5 and e_im <= 1e-5
+    slam.close()
+
+
+def test_measure_stage_fp64():
+    p, seq = c0_seq(2)
+    d, tan = seq.frame(1)
+    cfg = X.config_from_preset(p, prec=X.C128, max_frames=4)
+    for dirs, seed, ddot in [([(X.P_DEPTH, H20)], O.seed(1, O.P_DEPTH, h=H20), tan),
+                             ([(X.P_FX, H20)], O.seed(1, O.P_FX, h=H20), None)]:
+        slam = X.Slam(cfg, X.Perturbation(dirs), seq.poses_gt[0])
+        slam.measure(torch_dev(d, np.float64), None if ddot is None else torch_dev(ddot[None], np.float64))
+        got = slam.measured()
+        ref = O.measure(O.config(p), seed, d, ddot)
+        for l in range(3):
+            assert np.array_equal(got[l]["valid"], ref[l]["valid"]), l
+            gD = np.moveaxis(got[l]["D"], 0, -1)
+            assert relerr(gD[..., 0], ref[l]["D"][..., 0]) <= 1e-12
+            assert relerr(gD[..., 1], ref[l]["D"][..., 1]) <= 1e-10
+            Hl, Wl = ref[l]["valid"].shape
+            gV = got[l]["V"].transpose(2, 3, 0, 1)
+            gN = got[l]["N"].transpose(2, 3, 0, 1)
+            for c in range(2):
+                assert relerr(gV[..., c], ref[l]["V"][..., c]) <= 1e-10, (l, c)
+                assert relerr(gN[..., c], ref[l]["N"][..., c]) <= 1e-10, (l, c)
+        slam.close()
+
+
+def _oracle_state_after(p, depths, T0, nframes, param):
+    """Oracle volume after n frames plus the pose of the last frame."""
+    s = O.seed(1, param, h=H20)
+    r = O.run_sequence(O.config(p), s, depths[:nframes], T0, want_volume=True)
+    return r, s
+
+
+def test_fuse_and_raycast_stages_fp64():
+    p, seq = c0_seq(4)
+    depths = seq.depths()
+    T0 = seq.poses_gt[0]
+    r, s = _oracle_state_after(p, depths, T0, 3, O.P_TRUNC)
+    cfg = X.config_from_preset(p, prec=X.C128, max_frames=8)
+    slam = X.Slam(cfg, X.Perturbation([(X.P_TRUNC, H20)]), T0)
+    nv = r["F"].shape[0]
+    slam.set(X.F_TSDF, r["F"].T)
+    slam.set(X.F_WEIGHT, r["W"].T)
+    Tk = r["poses"][2]                                  # (4,4,2)
+    slam.set(X.F_POSE, np.moveaxis(Tk, -1, 0))
+    # raycast at T_k
+    slam.raycast()
+    slam.sync()
+    H, W = p["camera"]["height"], p["camera"]["width"]
+    ref = O.raycast(O.config(p), s, r["F"], r["W"], Tk)
+    gv = slam.get(X.F_MVALID).reshape(H, W)
+    assert np.array_equal(gv, ref["valid"])
+    ok = ref["valid"].astype(bool)
+    gV = gpu_map_to_oracle(slam.get(X.F_VMAP), H, W)
+    gN = gpu_map_to_oracle(slam.get(X.F_NMAP), H, W)
+    gZ = slam.get(X.F_ZMAP).reshape(H, W)
+    assert relerr(gZ[ok], ref["Z"][ok]) <= 1e-12
+    for c in range(2):
+        assert relerr(gV[ok][..., c], ref["V"][ok][..., c]) <= 1e-10
+        assert relerr(gN[ok][..., c], ref["N"][ok][..., c]) <= 1e-10
+    # fusion of frame 3's measured depth at a perturbed pose
+    d3 = depths[3]
+    slam.measure(torch_dev(d3, np.float64))
+    Df = np.moveaxis(slam.measured()[0]["D"], 0, -1)   # (H, W, 2)
+    refD = O.measure(O.config(p), s, d3)[0]["D"]
+    assert relerr(Df[..., 0], refD[..., 0]) <= 1e-12
+    slam.integrate()
+    F = slam.get(X.F_TSDF)
+    Wt = slam.get(X.F_WEIGHT)
+    F2, W2, n2 = O.fuse(O.config(p), s, r["F"], r["W"], refD, Tk)
+    assert np.array_equal(Wt[0], W2[:, 0])
+    assert relerr(F[0], F2[:, 0]) <= 1e-10 and relerr(F[1], F2[:, 1]) <= 1e-10
+    slam.close()
+
+
+def test_icp_pass_stage_fp64():
+    p, seq = c0_seq(4)
+    depths = seq.depths()
+    T0 = seq.poses_gt[0]
+    r, s = _oracle_state_after(p, depths, T0, 3, O.P_TRUNC)
+    Tprev = r["poses"][2]
+    H, W = p["camera"]["height"], p["camera"]["width"]
+    model = O.raycast(O.config(p), s, r["F"], r["W"], Tprev)
+    cfg = X.config_from_preset(p, prec=X.C128, max_frames=8)
+    slam = X.Slam(cfg, X.Perturbation([(X.P_TRUNC, H20)]), T0)
+    slam.set(X.F_VMAP, oracle_map_to_gpu(model["V"]))
+    slam.set(X.F_NMAP, oracle_map_to_gpu(model["N"]))
+    slam.set(X.F_ZMAP, model["Z"].reshape(-1))
+    slam.set(X.F_MVALID, model["valid"].reshape(-1))
+    slam.set(X.F_PREV_POSE, np.moveaxis(Tprev, -1, 0))
+    slam.measure(torch_dev(depths[3], np.float64))
+    meas = O.measure(O.config(p), s, depths[3])
+    # a pose a little away from T_{k-1}
+    xi = O.lift(np.array([0.004, -0.003, 0.002, 0.01, -0.005, 0.008]), s)
+    xi[0, 1] = 1e-20
+    Tj = _cmul(O.se3_exp(s, xi), Tprev)
+    slam.set(X.F_POSE, np.moveaxis(Tj, -1, 0))
+    for l in range(3):
+        sub = 2 ** l
+        mod_l = dict(V=model["V"][::sub, ::sub], N=model["N"][::sub, ::sub], Z=model["Z"][::sub, ::sub],
+                     valid=model["valid"][::sub, ::sub])
+        A, b, cnt, r2 = O.icp_reduce(O.config(p), s, l, meas[l], mod_l, Tprev, Tj)
+        gs, gcnt, gr2 = slam.icp_pass(l)
+        assert int(gcnt) == cnt, (l, gcnt, cnt)
+        assert relerr(gs[:21, 0], A[:, 0]) <= 1e-10 and relerr(gs[21:, 0], b[:, 0]) <= 1e-10
+        assert relerr(gs[:21, 1], A[:, 1]) <= 1e-10 and relerr(gs[21:, 1], b[:, 1]) <= 1e-10
+        assert abs(gr2 - r2) <= 1e-10 * max(r2, 1e-30)
+    slam.close()
+
+
+def _cmul(A, B):
+    """Complex 4x4 product of (4,4,2) arrays (re, im) -- test-side composition."""
+    a = A[..., 0] + 1j * A[..., 1]
+    b = B[..., 0] + 1j * B[..., 1]
+    c = a @ b
+    return np.stack([c.real, c.imag], -1)

@@ -1,0 +1,57 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, and sizes workspaces / rejects bad arguments without a GPU."""
+import os
+import re
+
+import pytest
+
+import scenegen as sg
+from paper_2405_02187_amd import xslam as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "xslam.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xslam_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = X.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(X.EXPORTS)
+
+
+def test_workspace_sizes():
+    p1 = sg.preset("c1")
+    c = X.config_from_preset(p1)
+    b0 = X.workspace_bytes(c, X.Perturbation([]))
+    b1 = X.workspace_bytes(c, X.Perturbation([(X.P_TRUNC, 2 ** -20)]))
+    b6 = X.workspace_bytes(c, X.Perturbation([(X.P_RHO_X + i % 3, 2 ** -20) for i in range(6)]))
+    nv = 512 ** 3
+    assert b0 >= nv * 8 and b1 - b0 >= nv * 4 and b6 - b1 >= 5 * nv * 4
+    assert b1 < 2e9
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width=642), dict(dim=(500, 512, 512)), dict(voxel=0.0), dict(iters=(20, 10, 0)),
+    dict(bilateral_radius=9), dict(init=2),
+])
+def test_invalid_configs_size_to_zero(bad):
+    p1 = sg.preset("c1")
+    c = X.config_from_preset(p1, **bad)
+    assert X.workspace_bytes(c, X.Perturbation([(X.P_TRUNC, 2 ** -20)])) == 0
+
+
+def test_invalid_perturbations():
+    c = X.config_from_preset(sg.preset("c0"))
+    assert X.workspace_bytes(c, X.Perturbation([(99, 1e-20)])) == 0
+    assert X.workspace_bytes(c, X.Perturbation([(X.P_TRUNC, -1.0)])) == 0
+    assert X.workspace_bytes(c, X.Perturbation([(X.P_WCAP, 1e-20), (X.P_WCAP, 1e-20)])) == 0
+    c32 = X.config_from_preset(sg.preset("c0"), prec=X.C64)
+    assert X.workspace_bytes(c32, X.Perturbation([(X.P_TRUNC, 1e-40)])) == 0
+    assert X.lib().xslam_components(X.Perturbation([(0, 1.0)] * 4, q=2).c) == 1 + 4 + 3
