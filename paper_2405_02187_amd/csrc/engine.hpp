@@ -50,12 +50,14 @@ struct Engine : EngineBase {
   T* raw = nullptr; T* rawdot = nullptr;
   T* Dl[3]; T* Vl[3]; T* Nl[3]; uint8_t* valid[3];
   T* Vm[3]; T* Nm[3]; T* Zm[3]; uint8_t* mvalid[3];
-  T* partials = nullptr; unsigned* ticket = nullptr; int* lost = nullptr;
+  double* partials = nullptr; unsigned* ticket = nullptr; int* lost = nullptr;
   MPose<D, Q>* Pcur; MPose<D, Q>* Pprev; MPose<D, Q>* Pprev2; MPose<D, Q>* Pinit; MPose<D, Q>* hist;
   KPose<T, D, Q>* Kcur; KPose<T, D, Q>* Kprev;
   int32_t* counters = nullptr;
   double* sums = nullptr; double* traj = nullptr; double* gt = nullptr;
   T* stage = nullptr;
+  int* blist = nullptr; int* bcount = nullptr; uint8_t* bflags = nullptr;
+  typename ZBits<T>::type* zmax = nullptr;
 
   // ---- workspace plan ---------------------------------------------------
   static size_t plan(const xslam_config& c, int ndd, bool wtan, Engine* e, char* base) {
@@ -80,7 +82,7 @@ struct Engine : EngineBase {
       Zm[l] = cv.take<T>(n);
       mv[l] = cv.take<uint8_t>(n);
     }
-    T* partials = cv.take<T>(size_t(kMaxIcpBlocks) * NS);
+    double* partials = cv.take<double>(size_t(kMaxIcpBlocks) * NS);
     unsigned* ticket = cv.take<unsigned>(1);
     int* lost = cv.take<int>(1);
     MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
@@ -91,7 +93,13 @@ struct Engine : EngineBase {
     double* traj = cv.take<double>(NC);
     double* gt = cv.take<double>(size_t(16) * c.max_frames);
     T* stage = cv.take<T>(kStageElems);
+    const int nb = (c.vol.dim[0] / kBrick) * (c.vol.dim[1] / kBrick) * (c.vol.dim[2] / kBrick);
+    int* blist = cv.take<int>(nb);
+    int* bcount = cv.take<int>(1);
+    uint8_t* bflags = cv.take<uint8_t>(nb);
+    typename ZBits<T>::type* zmax = cv.take<typename ZBits<T>::type>(1);
     if (e) {
+      e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->zmax = zmax;
       e->rec = rec; e->Ftan = Ftan; e->Wtan = Wtan; e->raw = raw; e->rawdot = rawdot;
       for (int l = 0; l < 3; ++l) {
         e->Dl[l] = Dl[l]; e->Vl[l] = Vl[l]; e->Nl[l] = Nl[l]; e->valid[l] = vl[l];
@@ -199,6 +207,7 @@ struct Engine : EngineBase {
       if ((rc = fill<uint8_t>(valid[l], 0, npx[l]))) return rc;
     }
     if ((rc = fill<unsigned>(ticket, 0u, 1))) return rc;
+    if ((rc = fill<uint8_t>(bflags, 0, nbrick))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
     if ((rc = fill<int32_t>(counters, 0, int64_t(kCounters) * c.max_frames))) return rc;
     // initial pose exp(xi_seed) T0, xi_seed = h on the pose directions
@@ -305,11 +314,40 @@ struct Engine : EngineBase {
     });
   }
 
+  // fusion: depth bound, brick culling, list-driven update, brick flags
   int run_fuse() {
-    return launch(2, "fuse", [&] {
-      hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(nbrick), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
-                         Wtan, lost, counter_row(), nvox);
+    int rc;
+    if ((rc = launch(4, "fuse_prep", [&] {
+           hipLaunchKernelGGL(k_fuse_prep<T>, dim3(1), dim3(64), 0, C->stream, bcount, zmax);
+         })))
+      return rc;
+    if ((rc = launch(2, "zmax", [&] {
+           hipLaunchKernelGGL(k_zmax<T>, dim3(256), dim3(256), 0, C->stream, Dl[0], npx[0], zmax);
+         })))
+      return rc;
+    if ((rc = launch(2, "brick_cull", [&] {
+           hipLaunchKernelGGL((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
+                              zmax, nbrick, blist, bcount, lost);
+         })))
+      return rc;
+    const int g = std::min(nbrick, 4096);
+    if ((rc = launch(2, "fuse", [&] {
+           hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
+                              Wtan, lost, counter_row(), nvox, blist, bcount);
+         })))
+      return rc;
+    return launch(2, "brick_flags", [&] {
+      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick);
     });
+  }
+
+  int all_brick_flags() {
+    const int g = std::min(nbrick, 4096);
+    int rc = launch(4, "brick_flags_all", [&] {
+      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, nullptr, nullptr,
+                         nbrick);
+    });
+    return rc ? rc : sync();
   }
 
   int run_raycast() {
@@ -317,7 +355,8 @@ struct Engine : EngineBase {
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
     dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
     int rc = launch(3, "raycast", [&] {
-      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, counter_row());
+      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, counter_row(),
+                         bflags);
     });
     if (!rc) have_model = true;
     return rc;
@@ -535,7 +574,7 @@ struct Engine : EngineBase {
           }
           if (rc) return rc;
         }
-        return XSLAM_OK;
+        return get ? XSLAM_OK : all_brick_flags();
       }
       case XSLAM_F_VMAP: case XSLAM_F_NMAP: {
         size_t b = size_t(3) * NC * npx[0] * sizeof(T);

@@ -171,7 +171,7 @@ struct IcpArgs {
   const KPose<T, D, Q>* Kprev; // projection reference T_{k-1}
   MPose<D, Q>* Pcur;           // current estimate (FP64 master)
   Jet<double, D, Q> omega;     // step relaxation of this level
-  T* partials;                 // [blocks][NS]
+  double* partials;            // [blocks][NS]
   unsigned* ticket;
   int* lost;
   int32_t* counters;           // row of the current frame
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   using J = Jet<T, D, Q>;
   constexpr int NC = J::N;
   constexpr int NS = IcpSize<D, Q>::NS;
-  __shared__ T red[kIcpThreads / 64][NS];
+  __shared__ double red[kIcpThreads / 64][NS];
   __shared__ double fin[NS];
   __shared__ unsigned is_last;
   if (*g.lost) return;   // set by an earlier launch: every block leaves, no ticket taken
@@ -343,17 +343,20 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
     acc[27 * NC + 1] += r.re() * r.re();
   }
 
-  // block reduction: wave butterflies, then the 4 waves in fixed order
+  // block reduction in FP64: wave butterflies, then the 4 waves in fixed
+  // order.  The tangent sums cancel strongly (the derivative of a converged
+  // pose is a small difference of large per-pixel terms), so only the
+  // per-thread sums over a few pixels stay in T.
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    T s = wave_sum(acc[k]);
+    double s = wave_sum(double(acc[k]));
     if (lane == 0) red[wv][k] = s;
   }
   __syncthreads();
-  T* part = g.partials + size_t(blockIdx.x) * NS;
+  double* part = g.partials + size_t(blockIdx.x) * NS;
   for (int k = threadIdx.x; k < NS; k += kIcpThreads) {
-    T s = red[0][k];
+    double s = red[0][k];
 #pragma unroll
     for (int w = 1; w < kIcpThreads / 64; ++w) s += red[w][k];
     part[k] = s;
@@ -365,13 +368,37 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   if (!is_last) return;
   __threadfence();
 
-  // last block: fixed-order FP64 sum over blocks
-  for (int k = threadIdx.x; k < NS; k += kIcpThreads) {
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) s += double(__builtin_nontemporal_load(g.partials + size_t(b) * NS + k));
-    fin[k] = s;
+  // last block: fixed-order FP64 sum over blocks.  G threads per component,
+  // each summing every G-th block with 8 independent accumulators (loads in
+  // flight), then the G partial sums in order.
+  {
+    constexpr int G = (NS >= kIcpThreads) ? 1 : kIcpThreads / NS;
+    const unsigned B = gridDim.x;
+    for (int k0 = 0; k0 < NS; k0 += (NS >= kIcpThreads ? kIcpThreads : NS)) {
+      const int t = threadIdx.x;
+      const int k = k0 + (NS >= kIcpThreads ? t : t % NS);
+      const int grp = NS >= kIcpThreads ? 0 : t / NS;
+      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (grp < G && k < NS) {
+        unsigned b = grp;
+        for (; b + 7 * G < B; b += 8 * G) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
+        }
+        for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
+      }
+      const double s8 = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+      __shared__ double gsum[kIcpThreads];
+      gsum[t] = s8;
+      __syncthreads();
+      if (t < NS && k0 + t < NS) {
+        double s = 0.0;
+        for (int q = 0; q < G; ++q) s += gsum[q * (NS >= kIcpThreads ? kIcpThreads : NS) + t];
+        fin[k0 + t] = s;
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
   if (threadIdx.x != 0) return;
   *g.ticket = 0u;
   const int cnt = int(fin[27 * NC]);
@@ -441,16 +468,76 @@ __device__ __forceinline__ void voxel_centre(const KParams<T, D, Q>& kp, int i, 
   c[2] = T((k + 0.5) * s - 0.5 * kp.dim[2] * s);
 }
 
+// Largest filtered depth of the frame (bound of every L(x) used by fusion).
+template <typename T> struct ZBits;
+template <> struct ZBits<float> { typedef int type; };
+template <> struct ZBits<double> { typedef unsigned long long type; };
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zmax(const T* __restrict__ D0, size_t n, typename ZBits<T>::type* zmax) {
+  T m = 0;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
+    const T d = D0[i];
+    if (d > m) m = d;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) { T v = __shfl_xor(m, o, 64); m = v > m ? v : m; }
+  typedef typename ZBits<T>::type B;
+  if ((threadIdx.x & 63) == 0 && m > T(0)) {
+    B bits;
+    memcpy(&bits, &m, sizeof(B));
+    atomicMax(zmax, bits);   // positive IEEE values order like their bit patterns
+  }
+}
+
+// Bricks that may hold an updated voxel: in front of the camera, within
+// zmax + mu in depth and intersecting the four frustum planes of the pixel
+// range that admits a bilinear depth lookup (a conservative sphere test).
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                    const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
-                                                    T* __restrict__ Ftan, T* __restrict__ Wtan,
-                                                    const int* __restrict__ lost, int32_t* __restrict__ counters,
-                                                    int64_t nvox) {
+__global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                    const typename ZBits<T>::type* zmax_bits, int nbrick,
+                                                    int* __restrict__ list, int* __restrict__ count,
+                                                    const int* __restrict__ lost) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  bool keep = false;
+  if (b < nbrick && !*lost) {
+    T zm;
+    memcpy(&zm, zmax_bits, sizeof(T));
+    const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
+    const double s = double(kp.voxel);
+    const double c[3] = {(bx * 8 + 4) * s - 0.5 * kp.dim[0] * s, (by * 8 + 4) * s - 0.5 * kp.dim[1] * s,
+                         (bz * 8 + 4) * s - 0.5 * kp.dim[2] * s};
+    const double r = 4.0 * 1.7320508075688772 * s * 1.01;
+    const KPose<T, D, Q>& P = *Kk;
+    double d[3], x[3];
+    for (int a = 0; a < 3; ++a) d[a] = c[a] - double(P.t[a].re());
+    for (int a = 0; a < 3; ++a)
+      x[a] = double(P.R[0 + a].re()) * d[0] + double(P.R[3 + a].re()) * d[1] + double(P.R[6 + a].re()) * d[2];
+    const double fx = kp.fx.re(), fy = kp.fy.re(), cx = kp.cx.re(), cy = kp.cy.re();
+    const double n[4][3] = {{fx, 0, cx}, {-fx, 0, double(kp.W - 1) - cx}, {0, fy, cy}, {0, -fy, double(kp.H - 1) - cy}};
+    keep = x[2] + r > 0.0 && x[2] - r <= double(zm) + double(kp.mu.re()) * 1.01 && zm > T(0);
+    for (int q = 0; q < 4 && keep; ++q) {
+      const double dn = n[q][0] * x[0] + n[q][1] * x[1] + n[q][2] * x[2];
+      const double nn = sqrt(n[q][0] * n[q][0] + n[q][1] * n[q][1] + n[q][2] * n[q][2]);
+      keep = dn >= -r * nn;
+    }
+  }
+  const unsigned long long bal = __ballot(keep);
+  int base = 0;
+  const int lane = threadIdx.x & 63;
+  if (lane == 0 && bal) base = atomicAdd(count, int(__popcll(bal)));
+  base = __shfl(base, 0, 64);
+  if (keep) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+}
+
+template <typename T, int D, int Q>
+__device__ __forceinline__ void fuse_brick(const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                           const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
+                                           T* __restrict__ Ftan, T* __restrict__ Wtan, int32_t* __restrict__ counters,
+                                           int64_t nvox, int b) {
   using J = Jet<T, D, Q>;
   using R0 = Jet<T, 0, 0>;
-  if (*lost) return;
-  const int b = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
   const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
   const int64_t vi = int64_t(b) * kBrickVox + t;
@@ -551,6 +638,40 @@ __global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const K
   }
 }
 
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                    const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
+                                                    T* __restrict__ Ftan, T* __restrict__ Wtan,
+                                                    const int* __restrict__ lost, int32_t* __restrict__ counters,
+                                                    int64_t nvox, const int* __restrict__ list,
+                                                    const int* __restrict__ count) {
+  if (*lost) return;
+  const int nact = *count;
+  for (int q = blockIdx.x; q < nact; q += gridDim.x) fuse_brick(kp, Kk, Df, rec, Ftan, Wtan, counters, nvox, list[q]);
+}
+
+// Per-brick summary for the raycast: bit 0 = some voxel observed (W > 0),
+// bit 1 = every voxel observed with F exactly 1 (free space).  Recomputed for
+// the bricks fusion visited (list) or for all bricks (list == nullptr).
+template <typename T>
+__global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T>::type* __restrict__ rec,
+                                                           uint8_t* __restrict__ flags, const int* __restrict__ list,
+                                                           const int* __restrict__ count, int nbrick) {
+  const int nact = list ? *count : nbrick;
+  for (int q = blockIdx.x; q < nact; q += gridDim.x) {
+    const int b = list ? list[q] : q;
+    const auto r = rec[int64_t(b) * kBrickVox + threadIdx.x];
+    const int obs = __syncthreads_or(r.y > T(0));
+    const int fre = __syncthreads_and(r.y > T(0) && r.x == T(1));
+    if (threadIdx.x == 0) flags[b] = uint8_t((obs ? 1 : 0) | (fre ? 2 : 0));
+  }
+}
+
+template <typename T>
+__global__ void k_fuse_prep(int* count, typename ZBits<T>::type* zmax) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) { *count = 0; *zmax = 0; }
+}
+
 // ---------------------------------------------------------------------------
 // A7. raycast (Sec. 4.1 "Ray casting", eq. "surface_prediction") and the
 // model-map pyramid (level l = level 0 sampled at (2^l x, 2^l y)).
@@ -561,9 +682,13 @@ struct MapsOut {
 };
 
 // trilinear TSDF at a real point; valid iff all 8 corners observed (W > 0)
+// The brick flags only skip loads: a cell whose first corner lies in a brick
+// with no observed voxel is invalid (that corner has W = 0), and a cell inside
+// an all-free brick has eight corners equal to 1 -- the same interpolation is
+// then evaluated without loading them, so every sample value is unchanged.
 template <typename T, int D, int Q>
 __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
-                                             const T v[3], T& out) {
+                                             const uint8_t* __restrict__ flags, const T v[3], T& out) {
   int i0[3];
   T f[3];
 #pragma unroll
@@ -574,17 +699,24 @@ __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const t
     i0[a] = int(fl);
     f[a] = ga - fl;
   }
+  const uint8_t bf = flags[(int64_t(i0[2] >> 3) * kp.nbr[1] + (i0[1] >> 3)) * kp.nbr[0] + (i0[0] >> 3)];
+  if (!(bf & 1)) return false;
   T c[8];
+  if ((bf & 2) && (i0[0] & 7) != 7 && (i0[1] & 7) != 7 && (i0[2] & 7) != 7) {
 #pragma unroll
-  for (int dz = 0; dz < 2; ++dz)
+    for (int q = 0; q < 8; ++q) c[q] = T(1);
+  } else {
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
+    for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-      for (int dx = 0; dx < 2; ++dx) {
-        const auto r = rec[vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr)];
-        if (!(r.y > T(0))) return false;
-        c[dz * 4 + dy * 2 + dx] = r.x;
-      }
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const auto r = rec[vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr)];
+          if (!(r.y > T(0))) return false;
+          c[dz * 4 + dy * 2 + dx] = r.x;
+        }
+  }
   const T fx1 = T(1) - f[0], fy1 = T(1) - f[1], fz1 = T(1) - f[2];
   const T c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
   const T c01 = fx1 * c[4] + f[0] * c[5], c11 = fx1 * c[6] + f[0] * c[7];
@@ -642,7 +774,7 @@ template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
                                                  const typename Vec2<T>::type* __restrict__ rec,
                                                  const T* __restrict__ Ftan, int64_t nvox, MapsOut<T, D, Q> out,
-                                                 int32_t* __restrict__ counters) {
+                                                 int32_t* __restrict__ counters, const uint8_t* __restrict__ flags) {
   using J = Jet<T, D, Q>;
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   const int W = kp.W, H = kp.H;
@@ -681,7 +813,7 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
     for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it) {
       const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
       T f;
-      const bool okf = trilinear_re(kp, rec, v, f);
+      const bool okf = trilinear_re(kp, rec, flags, v, f);
       if (!okf) f = 0;
       if (okf && prev_ok) {
         if (f_prev > T(0) && f < T(0)) {
