@@ -89,7 +89,8 @@ typedef struct { int32_t width, height; double fx, fy, cx, cy; } xslam_camera;
 /* dims must be multiples of 8 (8^3 bricks) */
 typedef struct { int32_t dim[3]; double voxel; double trunc; double wcap; } xslam_volume;
 typedef struct {
-  int32_t iters[3];      /* per level, level 0 finest; levels run 2 -> 1 -> 0    */
+  int32_t iters[3];      /* per level, level 0 finest; levels run 2 -> 1 -> 0;
+                            at most 25 passes in total                           */
   double dgate;          /* metres                                               */
   double agate_deg;      /* degrees                                              */
   double level_w[3];     /* step relaxation per level (1 = plain Gauss-Newton)   */
@@ -121,9 +122,10 @@ enum xslam_field {
   XSLAM_F_MEAS_V = 9,    /* measured vertex maps (camera), levels 0,1,2: [3][NC][n_l] each   */
   XSLAM_F_MEAS_N = 10,   /* measured normal maps (camera), levels 0,1,2                      */
   XSLAM_F_MEAS_VALID = 11,/* measured validity, uint8, levels 0,1,2                          */
-  XSLAM_F_COUNTERS = 12, /* per frame int32[32]: lost, fused voxels, raycast hits,
-                            sum of ICP correspondences, last-pass correspondences,
-                            correspondences of every ICP pass (up to 24)                     */
+  XSLAM_F_COUNTERS = 12, /* per frame int32[32]: 0 lost, 1 fused voxels, 2 raycast hits,
+                            3 sum of ICP correspondences, 4 last-pass correspondences,
+                            5..29 correspondences of every ICP pass, 30 bricks visited by
+                            fusion, 31 raycast samples                                      */
   XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
   XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
 };

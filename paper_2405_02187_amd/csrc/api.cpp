@@ -50,7 +50,7 @@ static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, 
   if (!(c->vol.voxel > 0 && c->vol.trunc > 0 && c->vol.wcap >= 1)) return bad("volume parameters");
   for (int l = 0; l < 3; ++l)
     if (c->icp.iters[l] < 0 || c->icp.iters[l] > 64) return bad("icp iterations");
-  if (c->icp.iters[0] + c->icp.iters[1] + c->icp.iters[2] > 27) return bad("icp iterations: at most 27 passes");
+  if (c->icp.iters[0] + c->icp.iters[1] + c->icp.iters[2] > 25) return bad("icp iterations: at most 25 passes");
   if (!(c->icp.dgate > 0)) return bad("dgate");
   if (c->icp.init != 0 && c->icp.init != 1) return bad("icp.init must be 0 or 1");
   if (c->bilateral_radius < 0 || c->bilateral_radius > 4) return bad("bilateral radius must be 0..4");

@@ -4,7 +4,11 @@
 #define XS_COMBOS(X)              \
   X(double, 0, 0, c128_d0_q0)     \
   X(double, 1, 0, c128_d1_q0)     \
+  X(double, 2, 2, c128_d2_q2)     \
   X(double, 6, 0, c128_d6_q0)     \
   X(float, 0, 0, c64_d0_q0)       \
   X(float, 1, 0, c64_d1_q0)       \
-  X(float, 6, 0, c64_d6_q0)
+  X(float, 2, 2, c64_d2_q2)       \
+  X(float, 4, 4, c64_d4_q4)       \
+  X(float, 6, 0, c64_d6_q0)       \
+  X(float, 16, 0, c64_d16_q0)

@@ -33,6 +33,7 @@ struct Engine : EngineBase {
   static constexpr int NC = J::N;
   static constexpr int NS = IcpSize<D, Q>::NS;
   static constexpr int64_t kStageElems = int64_t(1) << 22;
+  static constexpr int kFuseBlocks = 4096;
 
   xslam_ctx_s* C;
   KParams<T, D, Q> kp;
@@ -50,14 +51,18 @@ struct Engine : EngineBase {
   T* raw = nullptr; T* rawdot = nullptr;
   T* Dl[3]; T* Vl[3]; T* Nl[3]; uint8_t* valid[3];
   T* Vm[3]; T* Nm[3]; T* Zm[3]; uint8_t* mvalid[3];
-  double* partials = nullptr; unsigned* ticket = nullptr; int* lost = nullptr;
+  double* partials = nullptr; int* lost = nullptr;
   MPose<D, Q>* Pcur; MPose<D, Q>* Pprev; MPose<D, Q>* Pprev2; MPose<D, Q>* Pinit; MPose<D, Q>* hist;
   KPose<T, D, Q>* Kcur; KPose<T, D, Q>* Kprev;
   int32_t* counters = nullptr;
   double* sums = nullptr; double* traj = nullptr; double* gt = nullptr;
   T* stage = nullptr;
   int* blist = nullptr; int* bcount = nullptr; uint8_t* bflags = nullptr;
-  typename ZBits<T>::type* zmax = nullptr;
+  int* fcounts = nullptr; int* rhits = nullptr; int* rsamples = nullptr;
+  T* tzmax = nullptr; int* dframe = nullptr;
+  int ntiles = 0;
+  hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
 
   // ---- workspace plan ---------------------------------------------------
   static size_t plan(const xslam_config& c, int ndd, bool wtan, Engine* e, char* base) {
@@ -83,7 +88,6 @@ struct Engine : EngineBase {
       mv[l] = cv.take<uint8_t>(n);
     }
     double* partials = cv.take<double>(size_t(kMaxIcpBlocks) * NS);
-    unsigned* ticket = cv.take<unsigned>(1);
     int* lost = cv.take<int>(1);
     MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
     MPose<D, Q>* hist = cv.take<MPose<D, Q>>(c.max_frames);
@@ -97,15 +101,23 @@ struct Engine : EngineBase {
     int* blist = cv.take<int>(nb);
     int* bcount = cv.take<int>(1);
     uint8_t* bflags = cv.take<uint8_t>(nb);
-    typename ZBits<T>::type* zmax = cv.take<typename ZBits<T>::type>(1);
+    const int nt = ((c.cam.width + kTile - 1) / kTile) * ((c.cam.height + kTile - 1) / kTile);
+    T* tzmax = cv.take<T>(nt);
+    const int nrb = ((c.cam.width + 15) / 16) * ((c.cam.height + 15) / 16);
+    int* fcounts = cv.take<int>(kFuseBlocks);
+    int* rhits = cv.take<int>(nrb);
+    int* rsamples = cv.take<int>(nrb);
+    int* dframe = cv.take<int>(1);
     if (e) {
-      e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->zmax = zmax;
+      e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->dframe = dframe;
+      e->ntiles = nt;
+      e->fcounts = fcounts; e->rhits = rhits; e->rsamples = rsamples;
       e->rec = rec; e->Ftan = Ftan; e->Wtan = Wtan; e->raw = raw; e->rawdot = rawdot;
       for (int l = 0; l < 3; ++l) {
         e->Dl[l] = Dl[l]; e->Vl[l] = Vl[l]; e->Nl[l] = Nl[l]; e->valid[l] = vl[l];
         e->Vm[l] = Vm[l]; e->Nm[l] = Nm[l]; e->Zm[l] = Zm[l]; e->mvalid[l] = mv[l];
       }
-      e->partials = partials; e->ticket = ticket; e->lost = lost;
+      e->partials = partials; e->lost = lost;
       e->Pcur = P; e->Pprev = P + 1; e->Pprev2 = P + 2; e->Pinit = P + 3; e->hist = hist;
       e->Kcur = K; e->Kprev = K + 1;
       e->counters = counters; e->sums = sums; e->traj = traj; e->gt = gt; e->stage = stage;
@@ -206,8 +218,9 @@ struct Engine : EngineBase {
       if ((rc = fill<uint8_t>(mvalid[l], 0, npx[l]))) return rc;
       if ((rc = fill<uint8_t>(valid[l], 0, npx[l]))) return rc;
     }
-    if ((rc = fill<unsigned>(ticket, 0u, 1))) return rc;
     if ((rc = fill<uint8_t>(bflags, 0, nbrick))) return rc;
+    if ((rc = fill<int>(dframe, 0, 1))) return rc;
+    if ((rc = fill<int>(bcount, 0, 1))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
     if ((rc = fill<int32_t>(counters, 0, int64_t(kCounters) * c.max_frames))) return rc;
     // initial pose exp(xi_seed) T0, xi_seed = h on the pose directions
@@ -281,7 +294,7 @@ struct Engine : EngineBase {
     return XSLAM_OK;
   }
 
-  int32_t* counter_row() { return counters + size_t(kCounters) * std::min(frame, C->cfg.max_frames - 1); }
+  int32_t* host_counter_row() { return counters + size_t(kCounters) * std::min(frame, C->cfg.max_frames - 1); }
 
   int run_icp_level(int l, int iter_slot, int do_solve) {
     IcpArgs<T, D, Q> a;
@@ -289,10 +302,15 @@ struct Engine : EngineBase {
     a.Vm = Vm[l]; a.Nm = Nm[l]; a.Zm = Zm[l]; a.validm = mvalid[l];
     a.W = W[l]; a.H = H[l]; a.level = l; a.iter_slot = iter_slot; a.do_solve = do_solve;
     a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l];
-    a.partials = partials; a.ticket = ticket; a.lost = lost; a.counters = counter_row(); a.sums_out = sums;
+    a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums;
+    a.frame = dframe; a.max_frames = C->cfg.max_frames;
     int blocks = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
-    return launch(1, "icp", [&] {
+    int rc = launch(1, "icp", [&] {
       hipLaunchKernelGGL((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
+    });
+    if (rc) return rc;
+    return launch(1, "icp_finish", [&] {
+      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kIcpThreads), 0, C->stream, a, blocks);
     });
   }
 
@@ -302,41 +320,51 @@ struct Engine : EngineBase {
     if (!have_model) return fail(XSLAM_ERR_STATE, "track: no model maps (raycast first)");
     if ((rc = launch(4, "track_begin", [&] {
            hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pprev, Pprev2, Pinit,
-                              Kcur, Kprev, lost, counter_row(), (C->cfg.icp.init == 1 && frame > 1) ? 1 : 0);
+                              Kcur, Kprev, lost, counters, dframe, C->cfg.max_frames,
+                              C->cfg.icp.init == 1 ? 1 : 0);
          })))
       return rc;
     int slot = 0;
     for (int l = 2; l >= 0; --l)
       for (int it = 0; it < C->cfg.icp.iters[l]; ++it, ++slot)
         if ((rc = run_icp_level(l, slot, 1))) return rc;
-    return launch(4, "track_end", [&] {
-      hipLaunchKernelGGL((k_track_end<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pinit, Kcur, lost);
+    return XSLAM_OK;
+  }
+
+  // lost fallback + pose history (tracked frames), reset of the brick list
+  int post_track(bool tracked, bool store) {
+    return launch(4, "post_track", [&] {
+      hipLaunchKernelGGL((k_post_track<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pinit, Kcur,
+                         tracked ? lost : nullptr, store ? hist : nullptr, dframe, C->cfg.max_frames, bcount);
     });
   }
 
-  // fusion: depth bound, brick culling, list-driven update, brick flags
+  // fusion: per-tile depth bound, brick culling, list-driven update, brick
+  // flags (the brick count must have been reset by post_track)
   int run_fuse() {
     int rc;
-    if ((rc = launch(4, "fuse_prep", [&] {
-           hipLaunchKernelGGL(k_fuse_prep<T>, dim3(1), dim3(64), 0, C->stream, bcount, zmax);
+    const int ntx = (W[0] + kTile - 1) / kTile, nty = (H[0] + kTile - 1) / kTile;
+    if ((rc = launch(4, "tile_zmax", [&] {
+           hipLaunchKernelGGL(k_tile_zmax<T>, dim3(ntx, nty), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax);
          })))
       return rc;
-    if ((rc = launch(2, "zmax", [&] {
-           hipLaunchKernelGGL(k_zmax<T>, dim3(256), dim3(256), 0, C->stream, Dl[0], npx[0], zmax);
-         })))
-      return rc;
-    if ((rc = launch(2, "brick_cull", [&] {
+    if ((rc = launch(4, "brick_cull", [&] {
            hipLaunchKernelGGL((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
-                              zmax, nbrick, blist, bcount, lost);
+                              tzmax, nbrick, blist, bcount, lost);
          })))
       return rc;
-    const int g = std::min(nbrick, 4096);
+    const int g = std::min(nbrick, kFuseBlocks);
     if ((rc = launch(2, "fuse", [&] {
            hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
-                              Wtan, lost, counter_row(), nvox, blist, bcount);
+                              Wtan, lost, nvox, blist, bcount, fcounts);
          })))
       return rc;
-    return launch(2, "brick_flags", [&] {
+    if ((rc = launch(4, "sum_counts", [&] {
+           hipLaunchKernelGGL(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, fcounts, g, nullptr, 0, counters,
+                              dframe, C->cfg.max_frames, 1, 0, bcount, 30);
+         })))
+      return rc;
+    return launch(4, "brick_flags", [&] {
       hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick);
     });
   }
@@ -355,24 +383,40 @@ struct Engine : EngineBase {
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
     dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
     int rc = launch(3, "raycast", [&] {
-      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, counter_row(),
+      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, rhits, rsamples,
                          bflags);
+    });
+    if (rc) return rc;
+    const int nrb = int(g.x * g.y);
+    rc = launch(4, "sum_counts", [&] {
+      hipLaunchKernelGGL(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, rsamples, nrb, counters,
+                         dframe, C->cfg.max_frames, 2, 31, nullptr, 0);
     });
     if (!rc) have_model = true;
     return rc;
   }
 
-  int store_pose() {
-    int f = std::min(frame, C->cfg.max_frames - 1);
-    return launch(4, "store_pose", [&] {
-      hipLaunchKernelGGL((k_store_pose<D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, hist, f);
+  int frame_end() {
+    return launch(4, "frame_end", [&] {
+      hipLaunchKernelGGL(k_frame_end<T>, dim3(1), dim3(64), 0, C->stream, dframe);
     });
   }
 
   int reset_frame_flags() {
     int rc = fill<int>(lost, 0, 1);
-    if (!rc) rc = fill<int32_t>(counter_row(), 0, kCounters);
+    if (!rc) rc = fill<int32_t>(host_counter_row(), 0, kCounters);
     return rc;
+  }
+
+  // the device work of one tracked frame (captured once into a graph)
+  int enqueue_tracked_frame() {
+    int rc;
+    if ((rc = run_measure())) return rc;
+    if ((rc = run_track())) return rc;
+    if ((rc = post_track(true, true))) return rc;
+    if ((rc = run_fuse())) return rc;
+    if ((rc = run_raycast())) return rc;
+    return frame_end();
   }
 
   // ---- EngineBase ---------------------------------------------------------
@@ -386,6 +430,7 @@ struct Engine : EngineBase {
     if (!measured) return fail(XSLAM_ERR_STATE, "integrate: no measured frame");
     if (pose && (rc = set_real_pose(pose))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
+    if ((rc = post_track(false, false))) return rc;
     return run_fuse();
   }
 
@@ -404,24 +449,70 @@ struct Engine : EngineBase {
   int track() override {
     int rc = run_track();
     if (rc) return rc;
-    return store_pose();
+    return post_track(true, true);
   }
 
   int step(const void* depth, const void* ddot) override {
     int rc;
     if (frame >= C->cfg.max_frames) return fail(XSLAM_ERR_STATE, "step: max_frames reached");
     if ((rc = copy_inputs(depth, ddot))) return rc;
-    if ((rc = run_measure())) return rc;
     if (frame == 0) {
       if ((rc = reset_frame_flags())) return rc;
+      if ((rc = run_measure())) return rc;
+      if ((rc = post_track(false, true))) return rc;
+      if ((rc = run_fuse())) return rc;
+      if ((rc = run_raycast())) return rc;
+      if ((rc = frame_end())) return rc;
     } else {
-      if ((rc = run_track())) return rc;
+      if (!have_model) return fail(XSLAM_ERR_STATE, "step: no model maps");
+      measured = true;
+      if (use_graph && !C->timer.on) {
+        if (!gexec) {
+          if ((rc = capture())) return rc;
+        }
+        if (gexec) {
+          if (hipGraphLaunch(gexec, C->stream) != hipSuccess) return check("graph launch");
+        } else if ((rc = enqueue_tracked_frame())) {
+          return rc;
+        }
+      } else if ((rc = enqueue_tracked_frame())) {
+        return rc;
+      }
     }
-    if ((rc = store_pose())) return rc;
-    if ((rc = run_fuse())) return rc;
-    if ((rc = run_raycast())) return rc;
     frame += 1;
     return XSLAM_OK;
+  }
+
+  // capture the tracked-frame work into a graph; on failure keep eager launches
+  int capture() {
+    if (hipStreamBeginCapture(C->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      hipGetLastError();
+      use_graph = false;
+      return XSLAM_OK;
+    }
+    int rc = enqueue_tracked_frame();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(C->stream, &g);
+    if (rc || e != hipSuccess || !g) {
+      hipGetLastError();
+      if (g) hipGraphDestroy(g);
+      use_graph = false;
+      return rc;
+    }
+    if (hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      hipGetLastError();
+      hipGraphDestroy(g);
+      gexec = nullptr;
+      use_graph = false;
+      return XSLAM_OK;
+    }
+    graph = g;
+    return XSLAM_OK;
+  }
+
+  ~Engine() override {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
   }
 
   int icp_pass(int level, double* out) override {
@@ -621,7 +712,8 @@ struct Engine : EngineBase {
         int f = *static_cast<const int32_t*>(buf);
         if (f < 0 || f > C->cfg.max_frames) return fail(XSLAM_ERR_ARG, "frame: range");
         frame = f;
-        return XSLAM_OK;
+        int rc = fill<int>(dframe, f, 1);
+        return rc ? rc : sync();
       }
     }
     return fail(XSLAM_ERR_ARG, "unknown field");

@@ -172,9 +172,10 @@ struct IcpArgs {
   MPose<D, Q>* Pcur;           // current estimate (FP64 master)
   Jet<double, D, Q> omega;     // step relaxation of this level
   double* partials;            // [blocks][NS]
-  unsigned* ticket;
   int* lost;
-  int32_t* counters;           // row of the current frame
+  int32_t* counters;           // counter rows (base)
+  const int* frame;            // device frame index
+  int max_frames;
   double* sums_out;            // icp_pass: [NS] FP64 sums
 };
 
@@ -182,6 +183,14 @@ template <int D, int Q> struct IcpSize {
   static constexpr int NC = Jet<float, D, Q>::N;
   static constexpr int NS = 27 * NC + 2;
 };
+
+// per-frame counter row: 0 lost, 1 fused voxels, 2 raycast hits, 3 sum of ICP
+// correspondences, 4 last-pass correspondences, 5..29 per-pass correspondences,
+// 30 active bricks, 31 raycast samples
+constexpr int kMaxPasses = 25;
+__device__ __forceinline__ int32_t* counter_row(int32_t* base, const int* frame, int max_frames) {
+  return base + kCounters * min(*frame, max_frames - 1);
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -261,97 +270,148 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
   return true;
 }
 
+// Association, gates, residual and Jacobian of one current pixel; false if
+// the pixel gives no correspondence.
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g,
+                                          const KPose<T, D, Q>& Tc, const KPose<T, D, Q>& Tp,
+                                          const Jet<T, D, Q>& fx, const Jet<T, D, Q>& fy, const Jet<T, D, Q>& cx,
+                                          const Jet<T, D, Q>& cy, size_t n, size_t i, Jet<T, D, Q> jac[6],
+                                          Jet<T, D, Q>& r) {
+  using J = Jet<T, D, Q>;
+  const int W = g.W, H = g.H;
+  if (!g.valid[i]) return false;
+  const V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+  const V3<J> p = pose_apply(Tc, v);
+  const V3<J> nr = pose_rotate(Tc, nv);
+  const V3<J> xc = pose_apply_inv(Tp, p);
+  if (!(xc.z.re() > T(0))) return false;
+  const J ux = fx * xc.x / xc.z + cx;
+  const J uy = fy * xc.y / xc.z + cy;
+  // tap choice floor(u + 1e-3): at the first pass of a level every pixel
+  // re-projects onto its own integer coordinate up to rounding
+  const T rx = ux.re(), ry = uy.re();
+  const T fx0 = floor(rx + T(kTapBias)), fy0 = floor(ry + T(kTapBias));
+  if (!(fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2))) return false;
+  const int i0 = int(fx0), j0 = int(fy0);
+  const size_t t0 = size_t(j0) * W + i0, t1 = t0 + 1, t2 = t0 + W, t3 = t2 + 1;
+  if (!(g.validm[t0] && g.validm[t1] && g.validm[t2] && g.validm[t3])) return false;
+  const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
+  const size_t tn = size_t(jn) * W + in;
+  const T zn = g.Zm[tn];
+  const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
+  V3<J> q, m;
+  if (disc >= kp.disc_delta) {
+    q = vload<J>(g.Vm, n, tn);
+    m = vload<J>(g.Nm, n, tn);
+  } else {
+    const J a = ux - fx0, b = uy - fy0;
+    const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
+    const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+    const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+    q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
+    const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+    const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+    V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
+    m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
+  }
+  const V3<J> d = vsub(p, q);
+  if (!(vdot(d, d).re() <= kp.dgate2)) return false;
+  if (!(vdot(nr, m).re() >= kp.cos_agate)) return false;
+  r = vdot(d, m);
+  const V3<J> pm = vcross(p, m);
+  jac[0] = pm.x; jac[1] = pm.y; jac[2] = pm.z; jac[3] = m.x; jac[4] = m.y; jac[5] = m.z;
+  return true;
+}
+
+// Per-block sums of the normal equations of one ICP pass (21 entries of
+// A = sum J J^T, 6 of b = sum J r, each with NC components; count; sum r^2).
+// Few components: per-thread sums over a few pixels, then an FP64 block tree.
+// Many components: every pixel's terms are reduced across the wave at once
+// (FP64) into per-wave LDS accumulators, so no thread holds 27 NC sums.
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
   using J = Jet<T, D, Q>;
   constexpr int NC = J::N;
   constexpr int NS = IcpSize<D, Q>::NS;
+  constexpr bool kRegAcc = NS <= 192;
   __shared__ double red[kIcpThreads / 64][NS];
-  __shared__ double fin[NS];
-  __shared__ unsigned is_last;
-  if (*g.lost) return;   // set by an earlier launch: every block leaves, no ticket taken
+  if (*g.lost) return;   // set by an earlier pass of this frame
 
   const KPose<T, D, Q> Tc = *g.Kcur;
   const KPose<T, D, Q> Tp = *g.Kprev;
   const T sc = T(1) / T(1 << g.level);
   const J fx = kp.fx * sc, fy = kp.fy * sc, cx = kp.cx * sc, cy = kp.cy * sc;
-  const int W = g.W, H = g.H;
-  const size_t n = size_t(W) * H;
-
-  T acc[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) acc[k] = 0;
-
-  for (size_t i = size_t(blockIdx.x) * kIcpThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kIcpThreads) {
-    if (!g.valid[i]) continue;
-    const V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
-    const V3<J> p = pose_apply(Tc, v);
-    const V3<J> nr = pose_rotate(Tc, nv);
-    const V3<J> xc = pose_apply_inv(Tp, p);
-    if (!(xc.z.re() > T(0))) continue;
-    const J ux = fx * xc.x / xc.z + cx;
-    const J uy = fy * xc.y / xc.z + cy;
-    // tap choice floor(u + 1e-3): at the first pass of a level every pixel
-    // re-projects onto its own integer coordinate up to rounding
-    const T rx = ux.re(), ry = uy.re();
-    const T fx0 = floor(rx + T(kTapBias)), fy0 = floor(ry + T(kTapBias));
-    if (!(fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2))) continue;
-    const int i0 = int(fx0), j0 = int(fy0);
-    const size_t t0 = size_t(j0) * W + i0, t1 = t0 + 1, t2 = t0 + W, t3 = t2 + 1;
-    if (!(g.validm[t0] && g.validm[t1] && g.validm[t2] && g.validm[t3])) continue;
-    const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
-    const size_t tn = size_t(jn) * W + in;
-    const T zn = g.Zm[tn];
-    const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
-    V3<J> q, m;
-    if (disc >= kp.disc_delta) {
-      q = vload<J>(g.Vm, n, tn);
-      m = vload<J>(g.Nm, n, tn);
-    } else {
-      const J a = ux - fx0, b = uy - fy0;
-      const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
-      const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-      const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
-      q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
-      const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-      const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
-      V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
-      m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
-    }
-    const V3<J> d = vsub(p, q);
-    if (!(vdot(d, d).re() <= kp.dgate2)) continue;
-    if (!(vdot(nr, m).re() >= kp.cos_agate)) continue;
-    const J r = vdot(d, m);
-    const V3<J> pm = vcross(p, m);
-    const J jac[6] = {pm.x, pm.y, pm.z, m.x, m.y, m.z};
-    int k = 0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-      for (int b = a; b < 6; ++b, ++k) {
-        const J prod = jac[a] * jac[b];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[k * NC + c] += prod.v[c];
-      }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const J prod = jac[a] * r;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[(21 + a) * NC + c] += prod.v[c];
-    }
-    acc[27 * NC] += T(1);
-    acc[27 * NC + 1] += r.re() * r.re();
-  }
-
-  // block reduction in FP64: wave butterflies, then the 4 waves in fixed
-  // order.  The tangent sums cancel strongly (the derivative of a converged
-  // pose is a small difference of large per-pixel terms), so only the
-  // per-thread sums over a few pixels stay in T.
+  const size_t n = size_t(g.W) * g.H;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  if constexpr (kRegAcc) {
+    T acc[NS];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double s = wave_sum(double(acc[k]));
-    if (lane == 0) red[wv][k] = s;
+    for (int k = 0; k < NS; ++k) acc[k] = 0;
+    for (size_t i = size_t(blockIdx.x) * kIcpThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kIcpThreads) {
+      J jac[6], r;
+      if (!icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r)) continue;
+      int k = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b, ++k) {
+          const J prod = jac[a] * jac[b];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[k * NC + c] += prod.v[c];
+        }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const J prod = jac[a] * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[(21 + a) * NC + c] += prod.v[c];
+      }
+      acc[27 * NC] += T(1);
+      acc[27 * NC + 1] += r.re() * r.re();
+    }
+    // block reduction in FP64: wave butterflies, then the 4 waves in fixed
+    // order.  The tangent sums cancel strongly (the derivative of a converged
+    // pose is a small difference of large per-pixel terms), so only the
+    // per-thread sums over a few pixels stay in T.
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s = wave_sum(double(acc[k]));
+      if (lane == 0) red[wv][k] = s;
+    }
+  } else {
+    for (int k = lane; k < NS; k += 64) red[wv][k] = 0.0;
+    for (size_t base = size_t(blockIdx.x) * kIcpThreads; base < n; base += size_t(gridDim.x) * kIcpThreads) {
+      const size_t i = base + threadIdx.x;
+      J jac[6], r;
+      bool ok = i < n && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
+      if (!ok) {
+        r = jzero<J>();
+#pragma unroll
+        for (int a = 0; a < 6; ++a) jac[a] = jzero<J>();
+      }
+      int k = 0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b, ++k) {
+          const J prod = jac[a] * jac[b];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double sv = wave_sum(double(prod.v[c]));
+            if (lane == 0) red[wv][k * NC + c] += sv;
+          }
+        }
+      for (int a = 0; a < 6; ++a) {
+        const J prod = jac[a] * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double sv = wave_sum(double(prod.v[c]));
+          if (lane == 0) red[wv][(21 + a) * NC + c] += sv;
+        }
+      }
+      const double sc1 = wave_sum(ok ? 1.0 : 0.0);
+      const double sr2 = wave_sum(ok ? double(r.re()) * double(r.re()) : 0.0);
+      if (lane == 0) { red[wv][27 * NC] += sc1; red[wv][27 * NC + 1] += sr2; }
+    }
   }
   __syncthreads();
   double* part = g.partials + size_t(blockIdx.x) * NS;
@@ -361,19 +421,21 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
     for (int w = 1; w < kIcpThreads / 64; ++w) s += red[w][k];
     part[k] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(g.ticket, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
 
-  // last block: fixed-order FP64 sum over blocks.  G threads per component,
-  // each summing every G-th block with 8 independent accumulators (loads in
-  // flight), then the G partial sums in order.
+// One block: fixed-order FP64 sum of the per-block partials, then (unless
+// only the sums are wanted) the FP64 solve, relaxation, SE(3) update.
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(kIcpThreads) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
+  constexpr int NC = Jet<T, D, Q>::N;
+  constexpr int NS = IcpSize<D, Q>::NS;
+  __shared__ double fin[NS];
+  if (*g.lost) return;
+  // G threads per component, each summing every G-th block with 8
+  // independent accumulators (loads in flight), then the G sums in order.
   {
     constexpr int G = (NS >= kIcpThreads) ? 1 : kIcpThreads / NS;
-    const unsigned B = gridDim.x;
+    const unsigned B = nblocks;
     for (int k0 = 0; k0 < NS; k0 += (NS >= kIcpThreads ? kIcpThreads : NS)) {
       const int t = threadIdx.x;
       const int k = k0 + (NS >= kIcpThreads ? t : t % NS);
@@ -400,19 +462,19 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
     }
   }
   if (threadIdx.x != 0) return;
-  *g.ticket = 0u;
   const int cnt = int(fin[27 * NC]);
+  int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
   if (!g.do_solve) {
     for (int k = 0; k < NS; ++k) g.sums_out[k] = fin[k];
     return;
   }
-  g.counters[3] += cnt;
-  g.counters[4] = cnt;
-  if (g.iter_slot < kCounters - 5) g.counters[5 + g.iter_slot] = cnt;
+  crow[3] += cnt;
+  crow[4] = cnt;
+  if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
   Jet<double, D, Q> dx[6];
   if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
     *g.lost = 1;
-    g.counters[0] = 1;
+    crow[0] = 1;
     return;
   }
 #pragma unroll
@@ -427,34 +489,20 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 // initial estimate (previous pose, or constant velocity T1 T2^-1 T1)
 template <typename T, int D, int Q>
 __global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>* Pprev2, MPose<D, Q>* Pinit,
-                              KPose<T, D, Q>* Kcur, KPose<T, D, Q>* Kprev, int* lost, int32_t* counters,
-                              int const_vel) {
+                              KPose<T, D, Q>* Kcur, KPose<T, D, Q>* Kprev, int* lost, int32_t* counter_base,
+                              const int* frame, int max_frames, int const_vel) {
+  int32_t* counters = counter_row(counter_base, frame, max_frames);
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   *Pprev2 = *Pprev;
   *Pprev = *Pcur;
   MPose<D, Q> init = *Pprev;
-  if (const_vel) init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
+  if (const_vel && *frame > 1) init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
   *Pinit = init;
   *Pcur = init;
   *Kcur = to_kpose<T, double>(init);
   *Kprev = to_kpose<T, double>(*Pprev);
   *lost = 0;
   for (int i = 0; i < kCounters; ++i) counters[i] = 0;
-}
-
-// end of tracking: a lost frame keeps its initial estimate
-template <typename T, int D, int Q>
-__global__ void k_track_end(MPose<D, Q>* Pcur, const MPose<D, Q>* Pinit, KPose<T, D, Q>* Kcur, const int* lost) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (*lost) {
-    *Pcur = *Pinit;
-    *Kcur = to_kpose<T, double>(*Pinit);
-  }
-}
-
-template <int D, int Q>
-__global__ void k_store_pose(const MPose<D, Q>* Pcur, MPose<D, Q>* history, int frame) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) history[frame] = *Pcur;
 }
 
 // ---------------------------------------------------------------------------
@@ -468,41 +516,39 @@ __device__ __forceinline__ void voxel_centre(const KParams<T, D, Q>& kp, int i, 
   c[2] = T((k + 0.5) * s - 0.5 * kp.dim[2] * s);
 }
 
-// Largest filtered depth of the frame (bound of every L(x) used by fusion).
-template <typename T> struct ZBits;
-template <> struct ZBits<float> { typedef int type; };
-template <> struct ZBits<double> { typedef unsigned long long type; };
-
+// Largest filtered depth per 16x16 tile of level 0 (bound of every L(x)
+// whose bilinear taps fall in that tile).
+constexpr int kTile = 16;
 template <typename T>
-__global__ __launch_bounds__(256) void k_zmax(const T* __restrict__ D0, size_t n, typename ZBits<T>::type* zmax) {
+__global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax) {
+  const int x = blockIdx.x * kTile + threadIdx.x % kTile, y = blockIdx.y * kTile + threadIdx.x / kTile;
   T m = 0;
-  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
-    const T d = D0[i];
+  if (x < W && y < H) {
+    const T d = D0[size_t(y) * W + x];
     if (d > m) m = d;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) { T v = __shfl_xor(m, o, 64); m = v > m ? v : m; }
-  typedef typename ZBits<T>::type B;
-  if ((threadIdx.x & 63) == 0 && m > T(0)) {
-    B bits;
-    memcpy(&bits, &m, sizeof(B));
-    atomicMax(zmax, bits);   // positive IEEE values order like their bit patterns
+  __shared__ T wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T a = wm[0] > wm[1] ? wm[0] : wm[1], b = wm[2] > wm[3] ? wm[2] : wm[3];
+    tmax[blockIdx.y * gridDim.x + blockIdx.x] = a > b ? a : b;
   }
 }
 
-// Bricks that may hold an updated voxel: in front of the camera, within
-// zmax + mu in depth and intersecting the four frustum planes of the pixel
-// range that admits a bilinear depth lookup (a conservative sphere test).
+// Bricks that may hold an updated voxel (a conservative sphere test): in
+// front of the camera, intersecting the four frustum planes of the pixel range
+// that admits a bilinear depth lookup, and not farther than mu behind the
+// largest depth over the tiles its projection (plus one pixel) covers.
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                    const typename ZBits<T>::type* zmax_bits, int nbrick,
-                                                    int* __restrict__ list, int* __restrict__ count,
-                                                    const int* __restrict__ lost) {
+                                                    const T* __restrict__ tmax, int nbrick, int* __restrict__ list,
+                                                    int* __restrict__ count, const int* __restrict__ lost) {
   const int b = blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
   if (b < nbrick && !*lost) {
-    T zm;
-    memcpy(&zm, zmax_bits, sizeof(T));
     const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
     const double s = double(kp.voxel);
     const double c[3] = {(bx * 8 + 4) * s - 0.5 * kp.dim[0] * s, (by * 8 + 4) * s - 0.5 * kp.dim[1] * s,
@@ -515,11 +561,27 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
       x[a] = double(P.R[0 + a].re()) * d[0] + double(P.R[3 + a].re()) * d[1] + double(P.R[6 + a].re()) * d[2];
     const double fx = kp.fx.re(), fy = kp.fy.re(), cx = kp.cx.re(), cy = kp.cy.re();
     const double n[4][3] = {{fx, 0, cx}, {-fx, 0, double(kp.W - 1) - cx}, {0, fy, cy}, {0, -fy, double(kp.H - 1) - cy}};
-    keep = x[2] + r > 0.0 && x[2] - r <= double(zm) + double(kp.mu.re()) * 1.01 && zm > T(0);
+    keep = x[2] + r > 0.0;
     for (int q = 0; q < 4 && keep; ++q) {
       const double dn = n[q][0] * x[0] + n[q][1] * x[1] + n[q][2] * x[2];
       const double nn = sqrt(n[q][0] * n[q][0] + n[q][1] * n[q][1] + n[q][2] * n[q][2]);
       keep = dn >= -r * nn;
+    }
+    if (keep) {
+      const int ntx = (kp.W + kTile - 1) / kTile, nty = (kp.H + kTile - 1) / kTile;
+      int tx0 = 0, tx1 = ntx - 1, ty0 = 0, ty1 = nty - 1;
+      const double z0 = x[2] - r, z1 = x[2] + r;
+      if (z0 > 1e-3) {
+        const double ul = cx + fx * fmin((x[0] - r) / z0, (x[0] - r) / z1), uh = cx + fx * fmax((x[0] + r) / z0, (x[0] + r) / z1);
+        const double vl = cy + fy * fmin((x[1] - r) / z0, (x[1] - r) / z1), vh = cy + fy * fmax((x[1] + r) / z0, (x[1] + r) / z1);
+        const int pxl = int(fmax(floor(ul) - 1.0, 0.0)), pxh = int(fmin(floor(uh) + 2.0, double(kp.W - 1)));
+        const int pyl = int(fmax(floor(vl) - 1.0, 0.0)), pyh = int(fmin(floor(vh) + 2.0, double(kp.H - 1)));
+        tx0 = pxl / kTile; tx1 = pxh / kTile; ty0 = pyl / kTile; ty1 = pyh / kTile;
+      }
+      double zm = 0.0;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) zm = fmax(zm, double(tmax[ty * ntx + tx]));
+      keep = zm > 0.0 && z0 <= zm + double(kp.mu.re()) * 1.01 + 1e-6;
     }
   }
   const unsigned long long bal = __ballot(keep);
@@ -531,10 +593,9 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
 }
 
 template <typename T, int D, int Q>
-__device__ __forceinline__ void fuse_brick(const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                           const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
-                                           T* __restrict__ Ftan, T* __restrict__ Wtan, int32_t* __restrict__ counters,
-                                           int64_t nvox, int b) {
+__device__ __forceinline__ int fuse_brick(const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                          const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
+                                          T* __restrict__ Ftan, T* __restrict__ Wtan, int64_t nvox, int b) {
   using J = Jet<T, D, Q>;
   using R0 = Jet<T, 0, 0>;
   const int t = threadIdx.x;
@@ -588,10 +649,8 @@ __device__ __forceinline__ void fuse_brick(const KParams<T, D, Q>& kp, const KPo
       }
     }
   }
-  // updated-voxel count: one atomic per wave
-  const unsigned long long bal = __ballot(upd);
-  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(counters + 1, int(__popcll(bal)));
-  if (!upd) return;
+  const int nupd = __syncthreads_count(upd);
+  if (!upd) return nupd;
 
   // ---- the update in complex-step arithmetic
   const V3<J> c = {jconst<J>(cc[0]), jconst<J>(cc[1]), jconst<J>(cc[2])};
@@ -636,18 +695,57 @@ __device__ __forceinline__ void fuse_brick(const KParams<T, D, Q>& kp, const KPo
       if (q == kp.wcap_dir) wt = Wn.v[1 + q];
     Wtan[vi] = wt;
   }
+  return nupd;
 }
 
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
                                                     const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
                                                     T* __restrict__ Ftan, T* __restrict__ Wtan,
-                                                    const int* __restrict__ lost, int32_t* __restrict__ counters,
-                                                    int64_t nvox, const int* __restrict__ list,
-                                                    const int* __restrict__ count) {
-  if (*lost) return;
-  const int nact = *count;
-  for (int q = blockIdx.x; q < nact; q += gridDim.x) fuse_brick(kp, Kk, Df, rec, Ftan, Wtan, counters, nvox, list[q]);
+                                                    const int* __restrict__ lost, int64_t nvox,
+                                                    const int* __restrict__ list, const int* __restrict__ count,
+                                                    int* __restrict__ block_counts) {
+  int total = 0;
+  if (!*lost) {
+    const int nact = *count;
+    for (int q = blockIdx.x; q < nact; q += gridDim.x)
+      total += fuse_brick(kp, Kk, Df, rec, Ftan, Wtan, nvox, list[q]);
+  }
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = total;   // summed by k_sum_counts, no atomics
+}
+
+// counters[slot] = sum of n per-block counts (one block, fixed order)
+// block-wide integer sum (1-D or 2-D blocks of up to 1024 threads, multiple of 64)
+__device__ __forceinline__ int block_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  __shared__ int ws[16];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if ((tid & 63) == 0) ws[tid >> 6] = v;
+  __syncthreads();
+  int s = 0;
+  const int nw = int(blockDim.x * blockDim.y) >> 6;
+  for (int w = 0; w < nw; ++w) s += ws[w];
+  return s;
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, int n, const int* __restrict__ b, int nb,
+                                                     int32_t* __restrict__ counter_base, const int* __restrict__ frame,
+                                                     int max_frames, int slot_a, int slot_b, const int* __restrict__ extra,
+                                                     int slot_extra) {
+  int32_t* counters = counter_row(counter_base, frame, max_frames);
+  int sa = 0, sb = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sa += a[i];
+  if (b)
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) sb += b[i];
+  sa = block_sum_int(sa);
+  __syncthreads();
+  sb = block_sum_int(sb);
+  if (threadIdx.x == 0) {
+    counters[slot_a] = sa;
+    if (b) counters[slot_b] = sb;
+    if (extra) counters[slot_extra] = *extra;
+  }
 }
 
 // Per-brick summary for the raycast: bit 0 = some voxel observed (W > 0),
@@ -667,9 +765,23 @@ __global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T
   }
 }
 
+// end of tracking (a lost frame keeps its initial estimate), pose history,
+// and the reset of the brick list for fusion
+template <typename T, int D, int Q>
+__global__ void k_post_track(MPose<D, Q>* Pcur, const MPose<D, Q>* Pinit, KPose<T, D, Q>* Kcur, const int* lost,
+                             MPose<D, Q>* history, const int* frame, int max_frames, int* count) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (lost && *lost) {
+    *Pcur = *Pinit;
+    *Kcur = to_kpose<T, double>(*Pinit);
+  }
+  if (history) history[min(*frame, max_frames - 1)] = *Pcur;
+  *count = 0;
+}
+
 template <typename T>
-__global__ void k_fuse_prep(int* count, typename ZBits<T>::type* zmax) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) { *count = 0; *zmax = 0; }
+__global__ void k_frame_end(int* frame) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *frame += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -774,12 +886,14 @@ template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
                                                  const typename Vec2<T>::type* __restrict__ rec,
                                                  const T* __restrict__ Ftan, int64_t nvox, MapsOut<T, D, Q> out,
-                                                 int32_t* __restrict__ counters, const uint8_t* __restrict__ flags) {
+                                                 int* __restrict__ block_hits, int* __restrict__ block_samples,
+                                                 const uint8_t* __restrict__ flags) {
   using J = Jet<T, D, Q>;
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   const int W = kp.W, H = kp.H;
   const bool inside = x < W && y < H;
   bool ok = false;
+  int nsamp = 0;
   const J z = jzero<J>();
   V3<J> Vg = {z, z, z}, Ng = {z, z, z};
   T zhit = 0;
@@ -810,7 +924,7 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
     const T small = T(0.5) * s / nrm, big = T(0.8) * mu / nrm;
     bool prev_ok = false;
     T a_prev = 0, f_prev = 0;
-    for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it) {
+    for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it, ++nsamp) {
       const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
       T f;
       const bool okf = trilinear_re(kp, rec, flags, v, f);
@@ -859,8 +973,15 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
       alpha = alpha + step;
     }
   }
-  const unsigned long long bal = __ballot(ok);
-  if ((threadIdx.y * 16 + threadIdx.x) % 64 == 0 && bal) atomicAdd(counters + 2, int(__popcll(bal)));
+  {
+    const int nh = block_sum_int(ok ? 1 : 0);
+    __syncthreads();
+    const int ns = block_sum_int(nsamp);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+      block_hits[blockIdx.y * gridDim.x + blockIdx.x] = nh;
+      block_samples[blockIdx.y * gridDim.x + blockIdx.x] = ns;
+    }
+  }
   if (!inside) return;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
