@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the frame step runs on a single MI355X "
@@ -100,6 +102,14 @@ def main():
     import torch
     import scenegen as sg
     from paper_2405_02187_amd import xslam as X
+
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
 
     p = sg.preset("c1")
     n_frames = args.warmup + args.steps + args.timing_steps

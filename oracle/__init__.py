@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (-O2, no fast-math, no FP contraction)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
@@ -84,6 +84,8 @@ def lib():
         L.orc_traj_err.argtypes = [sp, C.c_int, dp, dp, dp]
         L.orc_eval_f.argtypes = [sp, C.c_double, dp]
         L.orc_eval_g.argtypes = [sp, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads(1)
         _lib = L
     return _lib
 
@@ -249,6 +251,11 @@ def traj_err(s, poses, gt):
     poses = _f64(poses)
     lib().orc_traj_err(C.byref(s), poses.shape[0], _p(poses), _p(_f64(gt)), _p(out))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's per-voxel and per-ray loops (default 1)."""
+    lib().orc_set_threads(int(n))
 
 
 def eval_f(s, x):

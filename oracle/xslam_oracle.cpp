@@ -27,6 +27,9 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace orc {
 
@@ -695,6 +698,8 @@ Maps<S> raycast(const Ctx& X, const Params<S>& P, const Volume<S>& Vol, const M4
   int W = X.c.width, Hh = X.c.height, n = W * Hh;
   M.W = W; M.H = Hh;
   M.V.assign(n, V3<S>()); M.N.assign(n, V3<S>()); M.valid.assign(n, 0); M.vvalid.assign(n, 0); M.Z.assign(n, 0.0);
+  // rays are independent: an optional thread split changes nothing
+#pragma omp parallel for schedule(dynamic, 4)
   for (int y = 0; y < Hh; ++y)
     for (int x = 0; x < W; ++x) {
       Hit<S> h = raycast_pixel(X, P, Vol, T, x, y, sc);
@@ -773,6 +778,8 @@ M4<S> track(const Ctx& X, const Params<S>& P, const Measured<S>& meas, const Map
 template <class S>
 int64_t fuse(const Ctx& X, const Params<S>& P, Volume<S>& Vol, const std::vector<S>& D, const M4<S>& T) {
   int64_t n = int64_t(Vol.dim[0]) * Vol.dim[1] * Vol.dim[2], cnt = 0;
+  // voxels are independent: an optional thread split changes nothing
+#pragma omp parallel for schedule(static) reduction(+ : cnt)
   for (int64_t i = 0; i < n; ++i) cnt += fuse_voxel(X, P, Vol.dim, Vol.s, i, Vol.F[i], Vol.W[i], D, T);
   return cnt;
 }
@@ -872,6 +879,39 @@ template <class S> void vol_out(const Volume<S>& V, double* F, double* W) {
   }
 }
 
+// listed voxels / pixels (threads optional; entries are independent)
+template <class S>
+int64_t fuse_list(const Ctx& X, const Params<S>& P, const OrcConfig* c, double* F, double* Wt,
+                  const std::vector<S>& D, const M4<S>& Tp, const int64_t* idx, int64_t n_idx) {
+  const int nc = NC<S>::n;
+  int64_t count = 0;
+#pragma omp parallel for schedule(static) reduction(+ : count)
+  for (int64_t q = 0; q < n_idx; ++q) {
+    S f = get<S>(F + q * nc), w = get<S>(Wt + q * nc);
+    count += fuse_voxel(X, P, c->dim, c->voxel, idx[q], f, w, D, Tp);
+    put(F + q * nc, f);
+    put(Wt + q * nc, w);
+  }
+  return count;
+}
+
+template <class S>
+void raycast_list(const Ctx& X, const Params<S>& P, const Volume<S>& Vol, const M4<S>& Tp, int width,
+                  const int32_t* pix, int npx, const Sched* sc, double* V_out, double* N_out, double* Z_out,
+                  uint8_t* valid_out) {
+  const int nc = NC<S>::n;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int q = 0; q < npx; ++q) {
+    int id = pix ? pix[q] : q;
+    Hit<S> h = raycast_pixel(X, P, Vol, Tp, id % width, id / width, sc);
+    V3<S> V = h.ok ? h.V : V3<S>(), N = h.ok ? h.N : V3<S>();
+    put(V_out + (q * 3 + 0) * nc, V.x); put(V_out + (q * 3 + 1) * nc, V.y); put(V_out + (q * 3 + 2) * nc, V.z);
+    put(N_out + (q * 3 + 0) * nc, N.x); put(N_out + (q * 3 + 1) * nc, N.y); put(N_out + (q * 3 + 2) * nc, N.z);
+    Z_out[q] = h.ok ? h.z : 0.0;
+    valid_out[q] = h.ok ? 1 : 0;
+  }
+}
+
 }  // namespace orc
 
 // ===========================================================================
@@ -892,6 +932,15 @@ using namespace orc;
 extern "C" {
 
 int orc_ncomp(const OrcSeed* s) { return s->kind == 0 ? 1 : (s->kind == 1 ? 2 : 4); }
+
+// Threads for the per-voxel and per-ray loops (default 1; results do not depend on it).
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n < 1 ? 1 : n);
+#else
+  (void)n;
+#endif
+}
 
 // SE(3) exponential of a 6-vector of scalars.
 void orc_se3_exp(const OrcSeed* seed, const double* xi, double* T) {
@@ -973,12 +1022,7 @@ int64_t orc_fuse(const OrcConfig* c, const OrcSeed* seed, double* F, double* Wt,
     for (int i = 0; i < n; ++i) D[i] = get<S>(Df + i * nc);
     M4<S> Tp = load_pose<S>(T);
     if (idx) {
-      for (int64_t q = 0; q < n_idx; ++q) {
-        S f = get<S>(F + q * nc), w = get<S>(Wt + q * nc);
-        count += fuse_voxel(X, P, c->dim, c->voxel, idx[q], f, w, D, Tp);
-        put(F + q * nc, f);
-        put(Wt + q * nc, w);
-      }
+      count = fuse_list<S>(X, P, c, F, Wt, D, Tp, idx, n_idx);
     } else {
       Volume<S> Vol;
       for (int a = 0; a < 3; ++a) Vol.dim[a] = c->dim[a];
@@ -1017,15 +1061,7 @@ void orc_raycast(const OrcConfig* c, const OrcSeed* seed, const double* F, const
       sc.cx = sched_params[3]; sc.cy = sched_params[4];
     }
     int npx = pix ? n_pix : c->width * c->height;
-    for (int q = 0; q < npx; ++q) {
-      int id = pix ? pix[q] : q;
-      Hit<S> h = raycast_pixel(X, P, Vol, Tp, id % c->width, id / c->width, sched_pose ? &sc : nullptr);
-      V3<S> V = h.ok ? h.V : V3<S>(), N = h.ok ? h.N : V3<S>();
-      put(V_out + (q * 3 + 0) * nc, V.x); put(V_out + (q * 3 + 1) * nc, V.y); put(V_out + (q * 3 + 2) * nc, V.z);
-      put(N_out + (q * 3 + 0) * nc, N.x); put(N_out + (q * 3 + 1) * nc, N.y); put(N_out + (q * 3 + 2) * nc, N.z);
-      Z_out[q] = h.ok ? h.z : 0.0;
-      valid_out[q] = h.ok ? 1 : 0;
-    }
+    raycast_list<S>(X, P, Vol, Tp, c->width, pix, npx, sched_pose ? &sc : nullptr, V_out, N_out, Z_out, valid_out);
   });
 }
 

@@ -59,6 +59,7 @@ struct Engine : EngineBase {
   T* stage = nullptr;
   int* blist = nullptr; int* bcount = nullptr; uint8_t* bflags = nullptr;
   int* fcounts = nullptr; int* rhits = nullptr; int* rsamples = nullptr;
+  T2* bracket = nullptr;
   T* tzmax = nullptr; int* dframe = nullptr;
   int ntiles = 0;
   hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
@@ -107,11 +108,12 @@ struct Engine : EngineBase {
     int* fcounts = cv.take<int>(kFuseBlocks);
     int* rhits = cv.take<int>(nrb);
     int* rsamples = cv.take<int>(nrb);
+    T2* bracket = cv.take<T2>(n0);
     int* dframe = cv.take<int>(1);
     if (e) {
       e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->dframe = dframe;
       e->ntiles = nt;
-      e->fcounts = fcounts; e->rhits = rhits; e->rsamples = rsamples;
+      e->fcounts = fcounts; e->rhits = rhits; e->rsamples = rsamples; e->bracket = bracket;
       e->rec = rec; e->Ftan = Ftan; e->Wtan = Wtan; e->raw = raw; e->rawdot = rawdot;
       for (int l = 0; l < 3; ++l) {
         e->Dl[l] = Dl[l]; e->Vl[l] = Vl[l]; e->Nl[l] = Nl[l]; e->valid[l] = vl[l];
@@ -382,9 +384,12 @@ struct Engine : EngineBase {
     MapsOut<T, D, Q> o;
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
     dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
-    int rc = launch(3, "raycast", [&] {
-      hipLaunchKernelGGL((k_raycast<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, o, rhits, rsamples,
-                         bflags);
+    int rc = launch(3, "raymarch", [&] {
+      hipLaunchKernelGGL((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
+    });
+    if (rc) return rc;
+    rc = launch(3, "rayhit", [&] {
+      hipLaunchKernelGGL((k_rayhit<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, bracket, o, rhits);
     });
     if (rc) return rc;
     const int nrb = int(g.x * g.y);

@@ -380,11 +380,17 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
       if (lane == 0) red[wv][k] = s;
     }
   } else {
+    // real components (and count, sum r^2) exactly as in the register path, so
+    // real parts do not depend on the number of components; the others are
+    // reduced across the wave pixel by pixel
+    T racc[29];
+#pragma unroll
+    for (int k = 0; k < 29; ++k) racc[k] = 0;
     for (int k = lane; k < NS; k += 64) red[wv][k] = 0.0;
     for (size_t base = size_t(blockIdx.x) * kIcpThreads; base < n; base += size_t(gridDim.x) * kIcpThreads) {
       const size_t i = base + threadIdx.x;
       J jac[6], r;
-      bool ok = i < n && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
+      const bool ok = i < n && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
       if (!ok) {
         r = jzero<J>();
 #pragma unroll
@@ -394,24 +400,34 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
       for (int a = 0; a < 6; ++a)
         for (int b = a; b < 6; ++b, ++k) {
           const J prod = jac[a] * jac[b];
+          if (ok) racc[k] += prod.v[0];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) {
+          for (int c = 1; c < NC; ++c) {
             const double sv = wave_sum(double(prod.v[c]));
             if (lane == 0) red[wv][k * NC + c] += sv;
           }
         }
       for (int a = 0; a < 6; ++a) {
         const J prod = jac[a] * r;
+        if (ok) racc[21 + a] += prod.v[0];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 1; c < NC; ++c) {
           const double sv = wave_sum(double(prod.v[c]));
           if (lane == 0) red[wv][(21 + a) * NC + c] += sv;
         }
       }
-      const double sc1 = wave_sum(ok ? 1.0 : 0.0);
-      const double sr2 = wave_sum(ok ? double(r.re()) * double(r.re()) : 0.0);
-      if (lane == 0) { red[wv][27 * NC] += sc1; red[wv][27 * NC + 1] += sr2; }
+      if (ok) {
+        racc[27] += T(1);
+        racc[28] += r.re() * r.re();
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const double sv = wave_sum(double(racc[k]));
+      if (lane == 0) red[wv][k * NC] = sv;
+    }
+    const double sc1 = wave_sum(double(racc[27])), sr2 = wave_sum(double(racc[28]));
+    if (lane == 0) { red[wv][27 * NC] = sc1; red[wv][27 * NC + 1] = sr2; }
   }
   __syncthreads();
   double* part = g.partials + size_t(blockIdx.x) * NS;
@@ -431,35 +447,28 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp_finish(IcpArgs<T, D, Q> g, 
   constexpr int NS = IcpSize<D, Q>::NS;
   __shared__ double fin[NS];
   if (*g.lost) return;
-  // G threads per component, each summing every G-th block with 8
-  // independent accumulators (loads in flight), then the G sums in order.
+  // Each component is summed over the blocks in the same order whatever the
+  // number of components (so real parts do not depend on D, Q): four
+  // interleaved groups of blocks (b mod 4), eight running sums each, combined
+  // in a fixed tree.  Work items (component, group) are spread over threads.
   {
-    constexpr int G = (NS >= kIcpThreads) ? 1 : kIcpThreads / NS;
+    constexpr int G = 4;
+    __shared__ double gsum[G][NS];
     const unsigned B = nblocks;
-    for (int k0 = 0; k0 < NS; k0 += (NS >= kIcpThreads ? kIcpThreads : NS)) {
-      const int t = threadIdx.x;
-      const int k = k0 + (NS >= kIcpThreads ? t : t % NS);
-      const int grp = NS >= kIcpThreads ? 0 : t / NS;
+    for (int item = threadIdx.x; item < NS * G; item += kIcpThreads) {
+      const int k = item / G, grp = item % G;
       double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (grp < G && k < NS) {
-        unsigned b = grp;
-        for (; b + 7 * G < B; b += 8 * G) {
+      unsigned b = grp;
+      for (; b + 7 * G < B; b += 8 * G) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
-        }
-        for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
+        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
       }
-      const double s8 = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-      __shared__ double gsum[kIcpThreads];
-      gsum[t] = s8;
-      __syncthreads();
-      if (t < NS && k0 + t < NS) {
-        double s = 0.0;
-        for (int q = 0; q < G; ++q) s += gsum[q * (NS >= kIcpThreads ? kIcpThreads : NS) + t];
-        fin[k0 + t] = s;
-      }
-      __syncthreads();
+      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
+      gsum[grp][k] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NS; k += kIcpThreads) fin[k] = (gsum[0][k] + gsum[1][k]) + (gsum[2][k] + gsum[3][k]);
+    __syncthreads();
   }
   if (threadIdx.x != 0) return;
   const int cnt = int(fin[27 * NC]);
@@ -880,29 +889,32 @@ __device__ __forceinline__ bool trilinear_jet(const KParams<T, D, Q>& kp, const 
 // The ray o + alpha R K^-1 (u,1) is marched on real parts only: half a voxel
 // while the last sample is observed and inside the band (F < 0.999), else
 // 0.8 mu; from max(near, entry) to the exit of the volume shrunk by one voxel.
-// F_m > 0 > F_{m+1} between consecutive valid samples is a hit (then both
-// samples are re-evaluated in complex-step arithmetic); - to + stops the ray.
+// F_m > 0 > F_{m+1} between consecutive valid samples is a hit; - to + stops
+// the ray.  This kernel records, per pixel, the bracketing alphas of the hit
+// (a negative second alpha: no hit); k_rayhit evaluates it in complex-step
+// arithmetic.  Real parts here are computed with the same operations as the
+// real parts of k_rayhit's jets.
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                 const typename Vec2<T>::type* __restrict__ rec,
-                                                 const T* __restrict__ Ftan, int64_t nvox, MapsOut<T, D, Q> out,
-                                                 int* __restrict__ block_hits, int* __restrict__ block_samples,
-                                                 const uint8_t* __restrict__ flags) {
-  using J = Jet<T, D, Q>;
+__global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                  const typename Vec2<T>::type* __restrict__ rec,
+                                                  const uint8_t* __restrict__ flags,
+                                                  typename Vec2<T>::type* __restrict__ bracket,
+                                                  int* __restrict__ block_samples) {
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   const int W = kp.W, H = kp.H;
-  const bool inside = x < W && y < H;
-  bool ok = false;
   int nsamp = 0;
-  const J z = jzero<J>();
-  V3<J> Vg = {z, z, z}, Ng = {z, z, z};
-  T zhit = 0;
-  if (inside) {
+  if (x < W && y < H) {
+    using R0 = Jet<T, 0, 0>;
     const KPose<T, D, Q>& P = *Kk;
-    const V3<J> dh = {(jconst<J>(T(x)) - kp.cx) / kp.fx, (jconst<J>(T(y)) - kp.cy) / kp.fy, jconst<J>(T(1))};
-    const V3<J> dir = pose_rotate(P, dh);
-    const V3<J> o = {P.t[0], P.t[1], P.t[2]};
-    const T orr[3] = {o.x.re(), o.y.re(), o.z.re()};
+    KPose<T, 0, 0> Pr;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Pr.R[q].v[0] = P.R[q].re();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Pr.t[q].v[0] = P.t[q].re();
+    const V3<R0> dh = {(jconst<R0>(T(x)) - kp.cx.re()) / jconst<R0>(kp.fx.re()),
+                       (jconst<R0>(T(y)) - kp.cy.re()) / jconst<R0>(kp.fy.re()), jconst<R0>(T(1))};
+    const V3<R0> dir = pose_rotate(Pr, dh);
+    const T orr[3] = {Pr.t[0].re(), Pr.t[1].re(), Pr.t[2].re()};
     const T dr[3] = {dir.x.re(), dir.y.re(), dir.z.re()};
     const T nrm = sqrt(dh.x.re() * dh.x.re() + dh.y.re() * dh.y.re() + T(1));
     const T s = kp.voxel;
@@ -924,6 +936,7 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
     const T small = T(0.5) * s / nrm, big = T(0.8) * mu / nrm;
     bool prev_ok = false;
     T a_prev = 0, f_prev = 0;
+    T hit0 = 0, hit1 = T(-1);
     for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it, ++nsamp) {
       const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
       T f;
@@ -931,37 +944,8 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
       if (!okf) f = 0;
       if (okf && prev_ok) {
         if (f_prev > T(0) && f < T(0)) {
-          J F0, F1;
-          const V3<J> v0 = vadd(o, vscale(jconst<J>(a_prev), dir));
-          const V3<J> v1 = vadd(o, vscale(jconst<J>(alpha), dir));
-          bool ok0 = trilinear_jet(kp, rec, Ftan, nvox, v0, F0);
-          bool ok1 = trilinear_jet(kp, rec, Ftan, nvox, v1, F1);
-          if (ok0 && ok1) {
-            const J a0 = jconst<J>(a_prev) - jconst<J>(alpha - a_prev) * F0 / (F1 - F0);
-            const V3<J> V = vadd(o, vscale(a0, dir));
-            J gr[3];
-            bool okg = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              V3<J> vp = V, vm = V;
-              if (a == 0) { vp.x = V.x + s; vm.x = V.x - s; }
-              if (a == 1) { vp.y = V.y + s; vm.y = V.y - s; }
-              if (a == 2) { vp.z = V.z + s; vm.z = V.z - s; }
-              J fp, fm;
-              okg = okg && trilinear_jet(kp, rec, Ftan, nvox, vp, fp) && trilinear_jet(kp, rec, Ftan, nvox, vm, fm);
-              if (okg) gr[a] = fp - fm;
-            }
-            if (okg) {
-              const V3<J> gv = {gr[0], gr[1], gr[2]};
-              const J gg = vdot(gv, gv);
-              if (gg.re() > T(0)) {
-                ok = true;
-                Vg = V;
-                Ng = vscale(jconst<J>(T(1)) / jsqrt(gg), gv);
-                zhit = a0.re();
-              }
-            }
-          }
+          hit0 = a_prev;
+          hit1 = alpha;
           break;
         }
         if (f_prev < T(0) && f > T(0)) break;
@@ -972,16 +956,77 @@ __global__ __launch_bounds__(256) void k_raycast(KParams<T, D, Q> kp, const KPos
       f_prev = f;
       alpha = alpha + step;
     }
+    typename Vec2<T>::type b;
+    b.x = hit0;
+    b.y = hit1;
+    bracket[size_t(y) * W + x] = b;
   }
-  {
-    const int nh = block_sum_int(ok ? 1 : 0);
-    __syncthreads();
-    const int ns = block_sum_int(nsamp);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-      block_hits[blockIdx.y * gridDim.x + blockIdx.x] = nh;
-      block_samples[blockIdx.y * gridDim.x + blockIdx.x] = ns;
+  const int ns = block_sum_int(nsamp);
+  if (threadIdx.x == 0 && threadIdx.y == 0) block_samples[blockIdx.y * gridDim.x + blockIdx.x] = ns;
+}
+
+// Complex-step evaluation of a bracketed crossing: alpha0 = alpha_m -
+// dalpha F_m / (F_{m+1} - F_m) (eq. after the crossing test), V = r(alpha0),
+// N = normalised central difference of F at +-1 voxel; writes the model maps
+// of levels 0-2.
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                const typename Vec2<T>::type* __restrict__ rec,
+                                                const T* __restrict__ Ftan, int64_t nvox,
+                                                const typename Vec2<T>::type* __restrict__ bracket,
+                                                MapsOut<T, D, Q> out, int* __restrict__ block_hits) {
+  using J = Jet<T, D, Q>;
+  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  const int W = kp.W, H = kp.H;
+  const bool inside = x < W && y < H;
+  bool ok = false;
+  const J z = jzero<J>();
+  V3<J> Vg = {z, z, z}, Ng = {z, z, z};
+  T zhit = 0;
+  if (inside) {
+    const auto br = bracket[size_t(y) * W + x];
+    if (br.y >= T(0)) {
+      const T a_prev = br.x, alpha = br.y;
+      const KPose<T, D, Q>& P = *Kk;
+      const V3<J> dh = {(jconst<J>(T(x)) - kp.cx) / kp.fx, (jconst<J>(T(y)) - kp.cy) / kp.fy, jconst<J>(T(1))};
+      const V3<J> dir = pose_rotate(P, dh);
+      const V3<J> o = {P.t[0], P.t[1], P.t[2]};
+      const T s = kp.voxel;
+      J F0, F1;
+      const V3<J> v0 = vadd(o, vscale(jconst<J>(a_prev), dir));
+      const V3<J> v1 = vadd(o, vscale(jconst<J>(alpha), dir));
+      const bool ok0 = trilinear_jet(kp, rec, Ftan, nvox, v0, F0);
+      const bool ok1 = trilinear_jet(kp, rec, Ftan, nvox, v1, F1);
+      if (ok0 && ok1) {
+        const J a0 = jconst<J>(a_prev) - jconst<J>(alpha - a_prev) * F0 / (F1 - F0);
+        const V3<J> V = vadd(o, vscale(a0, dir));
+        J gr[3];
+        bool okg = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          V3<J> vp = V, vm = V;
+          if (a == 0) { vp.x = V.x + s; vm.x = V.x - s; }
+          if (a == 1) { vp.y = V.y + s; vm.y = V.y - s; }
+          if (a == 2) { vp.z = V.z + s; vm.z = V.z - s; }
+          J fp, fm;
+          okg = okg && trilinear_jet(kp, rec, Ftan, nvox, vp, fp) && trilinear_jet(kp, rec, Ftan, nvox, vm, fm);
+          if (okg) gr[a] = fp - fm;
+        }
+        if (okg) {
+          const V3<J> gv = {gr[0], gr[1], gr[2]};
+          const J gg = vdot(gv, gv);
+          if (gg.re() > T(0)) {
+            ok = true;
+            Vg = V;
+            Ng = vscale(jconst<J>(T(1)) / jsqrt(gg), gv);
+            zhit = a0.re();
+          }
+        }
+      }
     }
   }
+  const int nh = block_sum_int(ok ? 1 : 0);
+  if (threadIdx.x == 0 && threadIdx.y == 0) block_hits[blockIdx.y * gridDim.x + blockIdx.x] = nh;
   if (!inside) return;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {

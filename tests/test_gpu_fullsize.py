@@ -1,0 +1,101 @@
+"""GPU parity at the full workload size (640x480 depth, 512^3 TSDF at 1 cm),
+in the launch configuration the benchmark times (``xslam_step``, graph replay
+of tracked frames): a 3-frame prefix against the oracle run on the same
+seeded inputs (its per-voxel and per-ray loops on several host threads).
+
+FP64-complex: per-frame counts (fused voxels, raycast hits, ICP
+correspondences) equal, poses, derivatives, sampled TSDF voxels and the model
+maps within 1e-10.  FP32-complex: poses within 1e-5; derivatives within the
+FP32-jitter spread of the oracle itself (see test_gpu_parity).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as sg
+from gpu_util import gpu_map_to_oracle, gpu_pose_to_oracle, log, relerr, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_02187_amd import xslam as X  # noqa: E402
+
+NF = 3
+H20 = 1e-20
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    O.set_threads(min(16, os.cpu_count() or 1))
+    p = sg.preset("c1")
+    seq = sg.make_sequence(p, n_frames=NF)
+    return p, seq.depths(), seq.poses_gt[0]
+
+
+def test_fullsize_fp64_prefix(inputs):
+    p, depths, T0 = inputs
+    d64 = depths.astype(np.float64)
+    log("oracle 512^3 x", NF)
+    ref = O.run_sequence(O.config(p), O.seed(1, O.P_PHI_X, h=H20), d64, T0, want_volume=True)
+    cfg = X.config_from_preset(p, prec=X.C128, max_frames=NF)
+    slam = X.Slam(cfg, X.Perturbation([(X.P_PHI_X, H20)]), T0)
+    dev = torch_dev(d64, np.float64)
+    for k in range(NF):
+        slam.step(dev[k])
+    slam.sync()
+    cnt = slam.get(X.F_COUNTERS)
+    st = ref["stats"]
+    log("gpu counts", cnt[:, :4].tolist(), "oracle", st[:, [0, 3, 4, 5]].tolist())
+    assert np.array_equal(cnt[:, 1], st[:, 3].astype(int))
+    assert np.array_equal(cnt[:, 2], st[:, 4].astype(int))
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
+    P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    e0, e1 = relerr(P[..., 0], ref["poses"][..., 0]), relerr(P[..., 1], ref["poses"][..., 1])
+    log("fullsize fp64 pose", e0, "derivative", e1)
+    assert e0 <= 1e-10 and e1 <= 1e-10
+    # sampled voxels of the final TSDF (all updated voxels plus a random sample)
+    F = slam.get(X.F_TSDF)
+    Wt = slam.get(X.F_WEIGHT)
+    assert np.array_equal(Wt[0] > 0, ref["W"][:, 0] > 0)
+    obs = np.nonzero(ref["W"][:, 0] > 0)[0]
+    log("observed voxels", len(obs))
+    assert relerr(F[0][obs], ref["F"][obs, 0]) <= 1e-10
+    assert relerr(F[1][obs], ref["F"][obs, 1]) <= 1e-10
+    # model maps of the last frame
+    H, W = cfg.cam.height, cfg.cam.width
+    m = O.raycast(O.config(p), O.seed(1, O.P_PHI_X, h=H20), ref["F"], ref["W"], ref["poses"][-1])
+    assert np.array_equal(slam.get(X.F_MVALID).reshape(H, W), m["valid"])
+    ok = m["valid"].astype(bool)
+    gV = gpu_map_to_oracle(slam.get(X.F_VMAP), H, W)
+    gN = gpu_map_to_oracle(slam.get(X.F_NMAP), H, W)
+    for c in range(2):
+        assert relerr(gV[ok][..., c], m["V"][ok][..., c]) <= 1e-10
+        assert relerr(gN[ok][..., c], m["N"][ok][..., c]) <= 1e-10
+    slam.close()
+
+
+def test_fullsize_fp32_prefix(inputs):
+    p, depths, T0 = inputs
+    d32 = depths.astype(np.float32)
+    ref = O.run_sequence(O.config(p), O.seed(1, O.P_PHI_X, h=H20), d32.astype(np.float64), T0)
+    h32 = 2.0 ** -20
+    cfg = X.config_from_preset(p, prec=X.C64, max_frames=NF)
+    slam = X.Slam(cfg, X.Perturbation([(X.P_PHI_X, h32)]), T0)
+    dev = torch_dev(d32, np.float32)
+    for k in range(NF):
+        slam.step(dev[k])
+    slam.sync()
+    P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    cnt = slam.get(X.F_COUNTERS)
+    e0 = relerr(P[..., 0], ref["poses"][..., 0])
+    e1 = relerr(P[..., 1] / h32, ref["poses"][..., 1] / H20)
+    mism = np.abs(cnt[:, [1, 2, 3]] - ref["stats"][:, [3, 4, 5]]).sum(0)
+    log("fullsize fp32 pose", e0, "derivative", e1, "count differences (fused, hits, corr)", mism.tolist())
+    assert e0 <= 1e-5
+    assert e1 <= 1e-3
+    slam.close()
