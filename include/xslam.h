@@ -95,7 +95,10 @@ typedef struct {
   double agate_deg;      /* degrees                                              */
   double level_w[3];     /* step relaxation per level (1 = plain Gauss-Newton)   */
   double disc_delta;     /* depth discontinuity threshold of bilinear lookups (m)*/
-  int32_t init;          /* 0: previous pose, 1: constant velocity               */
+  int32_t init;          /* 0: previous pose, 1: constant velocity, 2: network
+                            candidate judged against constant velocity by one
+                            level-2 association pass (640 x 480 only; without an
+                            attached network it behaves as 1)                  */
 } xslam_icp;
 typedef struct {
   int32_t prec;          /* enum xslam_prec                                       */
@@ -190,6 +193,47 @@ int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
  * kernel classes 0 measure, 1 icp, 2 fuse, 3 raycast, 4 other. */
 int xslam_set_timing(xslam_ctx ctx, int32_t on);
 int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]);
+
+/* ---- learned ICP initialiser (a systems form beyond the paper) -------------
+ * A CNN proposes the ICP initial pose increment from coarse maps: input
+ * 5 x 60 x 80 FP32 (current depth at pyramid level 3; raycast depth and raycast
+ * normal (x, y, z) of the previous frame in its camera frame; invalid pixels
+ * 0), four 3x3 stride-2 convolutions with ReLU (5->16->32->64->128), global
+ * average pool, 128->64 (ReLU)->6 = (phi, rho), the right increment of the
+ * previous camera pose.  bf16 MFMA convolutions with FP32 accumulation; FP32
+ * master weights and Adam (beta 0.9, 0.999, eps 1e-8).  Loss: mean over the
+ * batch of |100 (xi_hat - xi)|^2.  Parameters are one FP32 vector in the order
+ * conv0 W (Co,Ci,3,3), b, conv1 W, b, conv2 W, b, conv3 W, b, fc1 W (64,128),
+ * b, fc2 W (6,64), b.  The caller owns the workspace; calls are asynchronous
+ * on the given stream except get/set and train_step with loss_out. */
+typedef struct xslam_cnn_s* xslam_cnn;
+int32_t xslam_cnn_param_count(void);
+size_t xslam_cnn_workspace_bytes(int32_t max_batch);
+int xslam_cnn_create(void* dev_workspace, size_t bytes, void* stream, int32_t max_batch, xslam_cnn* out);
+int xslam_cnn_set_weights(xslam_cnn cnn, const float* host, size_t n);   /* also resets Adam */
+int xslam_cnn_get_weights(xslam_cnn cnn, float* host, size_t n);
+int xslam_cnn_get_grads(xslam_cnn cnn, float* host, size_t n);           /* of the last train step */
+/* x_dev: n x 5 x 60 x 80 FP32 device; xi_dev: n x 6 FP32 device */
+int xslam_cnn_forward(xslam_cnn cnn, const float* x_dev, int32_t n, float* xi_dev);
+/* one Adam step on a batch; label_dev n x 6 FP32 device; loss_out host or NULL */
+int xslam_cnn_train_step(xslam_cnn cnn, const float* x_dev, const float* label_dev, int32_t n, float lr,
+                         float* loss_out);
+const char* xslam_cnn_last_error(xslam_cnn cnn);
+int xslam_cnn_destroy(xslam_cnn cnn);
+
+/* Attach a network to a context (created on the same stream) for icp.init 2;
+ * NULL detaches.  Each tracked frame then builds the input from its measured
+ * depth and the previous model maps, proposes T_{k-1} exp(xi), and keeps the
+ * candidate (network or constant velocity) with the lower mean squared
+ * point-to-plane residual of one level-2 association pass; the network's only
+ * with at least 100 correspondences.  The network output is real: it carries
+ * no derivative. */
+int xslam_ctx_set_cnn(xslam_ctx ctx, xslam_cnn cnn);
+/* Network input parts of the current state (training data): depth_dev
+ * 60 x 80 FP32 (the last measured frame at level 3), model_dev 4 x 60 x 80
+ * FP32 (the last raycast: hit depth and normal in the camera frame of the
+ * current pose).  Device pointers; synchronises. */
+int xslam_cnn_parts(xslam_ctx ctx, float* depth_dev, float* model_dev);
 
 int xslam_sync(xslam_ctx ctx);
 const char* xslam_last_error(xslam_ctx ctx);

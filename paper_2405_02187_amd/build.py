@@ -39,7 +39,8 @@ def _run(cmd):
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
-    units = [(os.path.join(CSRC, "api.cpp"), os.path.join(BUILD, "api.o"), ["-x", "hip"])]
+    units = [(os.path.join(CSRC, "api.cpp"), os.path.join(BUILD, "api.o"), ["-x", "hip"]),
+             (os.path.join(CSRC, "cnn.hip"), os.path.join(BUILD, "cnn.o"), [])]
     for T, D, Q, name in combos():
         units.append((os.path.join(CSRC, "inst.hip"), os.path.join(BUILD, f"inst_{name}.o"),
                       [f"-DXS_T={T}", f"-DXS_D={D}", f"-DXS_Q={Q}", f"-DXS_NAME={name}"]))

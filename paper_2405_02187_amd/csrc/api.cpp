@@ -52,7 +52,9 @@ static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, 
     if (c->icp.iters[l] < 0 || c->icp.iters[l] > 64) return bad("icp iterations");
   if (c->icp.iters[0] + c->icp.iters[1] + c->icp.iters[2] > 25) return bad("icp iterations: at most 25 passes");
   if (!(c->icp.dgate > 0)) return bad("dgate");
-  if (c->icp.init != 0 && c->icp.init != 1) return bad("icp.init must be 0 or 1");
+  if (c->icp.init < 0 || c->icp.init > 2) return bad("icp.init must be 0, 1 or 2");
+  if (c->icp.init == 2 && (c->cam.width % 64 || c->cam.height % 32 || c->cam.width / 8 != 80 || c->cam.height / 8 != 60))
+    return bad("icp.init 2 (network) needs 640 x 480 depth (a 80 x 60 level-3 input)");
   if (c->bilateral_radius < 0 || c->bilateral_radius > 4) return bad("bilateral radius must be 0..4");
   if (c->bilateral_radius > 0 && !(c->bilateral_sigma_px > 0 && c->bilateral_sigma_m > 0)) return bad("bilateral sigmas");
   if (!(c->bilateral_sigma_m > 0)) return bad("bilateral_sigma_m gates the pyramid and must be > 0");
@@ -247,6 +249,17 @@ int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5])
     if (launches_out) launches_out[i] = t.launches[i];
   }
   return XSLAM_OK;
+}
+
+int xslam_ctx_set_cnn(xslam_ctx ctx, xslam_cnn cnn) {
+  XS_CTX_CHECK(ctx);
+  return ctx->eng->set_cnn(cnn);
+}
+
+int xslam_cnn_parts(xslam_ctx ctx, float* depth_dev, float* model_dev) {
+  XS_CTX_CHECK(ctx);
+  if (!depth_dev || !model_dev) return XSLAM_ERR_ARG;
+  return ctx->eng->cnn_parts(depth_dev, model_dev);
 }
 
 int xslam_sync(xslam_ctx ctx) {

@@ -11,7 +11,7 @@ constexpr int kBrick = 8;                 // TSDF bricks of 8^3 voxels, 512 cont
 constexpr int kBrickVox = kBrick * kBrick * kBrick;
 constexpr int kIcpThreads = 256;
 constexpr int kMaxIcpBlocks = 512;
-constexpr int kCounters = 32;
+constexpr int kCounters = 40;
 constexpr double kTapBias = 1e-3;         // ICP tap choice floor(u + 1e-3), see k_icp
 
 // Parameters of one context in kernel precision T (jets where perturbable).

@@ -21,6 +21,8 @@ struct EngineBase {
   virtual int set(int field, const void* src, size_t bytes) = 0;
   virtual int current_pose(double* out) = 0;
   virtual int frame_lost(int* lost) = 0;
+  virtual int set_cnn(xslam_cnn cnn) = 0;
+  virtual int cnn_parts(float* depth, float* model) = 0;
 };
 
 struct Timer {

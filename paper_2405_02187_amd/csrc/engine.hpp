@@ -60,6 +60,9 @@ struct Engine : EngineBase {
   int* blist = nullptr; int* bcount = nullptr; uint8_t* bflags = nullptr;
   int* fcounts = nullptr; int* rhits = nullptr; int* rsamples = nullptr;
   T2* bracket = nullptr;
+  float* cnn_in = nullptr; float* cnn_xi = nullptr; MPose<D, Q>* Pcand = nullptr;
+  double* sums_net = nullptr; double* sums_cv = nullptr;
+  xslam_cnn cnn = nullptr;
   T* tzmax = nullptr; int* dframe = nullptr;
   int ntiles = 0;
   hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
@@ -109,11 +112,17 @@ struct Engine : EngineBase {
     int* rhits = cv.take<int>(nrb);
     int* rsamples = cv.take<int>(nrb);
     T2* bracket = cv.take<T2>(n0);
+    float* cnn_in = cv.take<float>(5 * (c.cam.width >> 3) * (c.cam.height >> 3));
+    float* cnn_xi = cv.take<float>(8);
+    MPose<D, Q>* Pcand = cv.take<MPose<D, Q>>(1);
+    double* sums_net = cv.take<double>(NS);
+    double* sums_cv = cv.take<double>(NS);
     int* dframe = cv.take<int>(1);
     if (e) {
       e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->dframe = dframe;
       e->ntiles = nt;
       e->fcounts = fcounts; e->rhits = rhits; e->rsamples = rsamples; e->bracket = bracket;
+      e->cnn_in = cnn_in; e->cnn_xi = cnn_xi; e->Pcand = Pcand; e->sums_net = sums_net; e->sums_cv = sums_cv;
       e->rec = rec; e->Ftan = Ftan; e->Wtan = Wtan; e->raw = raw; e->rawdot = rawdot;
       for (int l = 0; l < 3; ++l) {
         e->Dl[l] = Dl[l]; e->Vl[l] = Vl[l]; e->Nl[l] = Nl[l]; e->valid[l] = vl[l];
@@ -298,13 +307,13 @@ struct Engine : EngineBase {
 
   int32_t* host_counter_row() { return counters + size_t(kCounters) * std::min(frame, C->cfg.max_frames - 1); }
 
-  int run_icp_level(int l, int iter_slot, int do_solve) {
+  int run_icp_level(int l, int iter_slot, int do_solve, double* sums_out = nullptr) {
     IcpArgs<T, D, Q> a;
     a.V = Vl[l]; a.N = Nl[l]; a.valid = valid[l];
     a.Vm = Vm[l]; a.Nm = Nm[l]; a.Zm = Zm[l]; a.validm = mvalid[l];
     a.W = W[l]; a.H = H[l]; a.level = l; a.iter_slot = iter_slot; a.do_solve = do_solve;
     a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l];
-    a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums;
+    a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums_out ? sums_out : sums;
     a.frame = dframe; a.max_frames = C->cfg.max_frames;
     int blocks = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
     int rc = launch(1, "icp", [&] {
@@ -326,11 +335,59 @@ struct Engine : EngineBase {
                               C->cfg.icp.init == 1 ? 1 : 0);
          })))
       return rc;
+    if (C->cfg.icp.init == 2 && cnn && (rc = learned_init())) return rc;
     int slot = 0;
     for (int l = 2; l >= 0; --l)
       for (int it = 0; it < C->cfg.icp.iters[l]; ++it, ++slot)
         if ((rc = run_icp_level(l, slot, 1))) return rc;
     return XSLAM_OK;
+  }
+
+  // network input of the current measured frame and the model maps at pose K
+  int enqueue_cnn_parts(const KPose<T, D, Q>* K, float* out_depth, float* out_model) {
+    dim3 b(16, 16), g(((W[0] >> 3) + 15) / 16, ((H[0] >> 3) + 15) / 16);
+    return launch(4, "cnn_parts", [&] {
+      hipLaunchKernelGGL((k_cnn_parts<T, D, Q>), g, b, 0, C->stream, kp, Dl[2], Nm[0], Zm[0], mvalid[0], K,
+                         out_depth, out_model);
+    });
+  }
+
+  // learned initial pose: network candidate vs previous / constant velocity,
+  // judged by the mean squared residual of one level-2 association pass
+  int learned_init() {
+    int rc;
+    const int n3 = (W[0] >> 3) * (H[0] >> 3);
+    if ((rc = enqueue_cnn_parts(Kprev, cnn_in, cnn_in + n3))) return rc;
+    if ((rc = xslam_cnn_forward(cnn, cnn_in, 1, cnn_xi))) return fail(rc, "learned init: network forward");
+    if ((rc = launch(4, "init_candidates", [&] {
+           hipLaunchKernelGGL((k_init_candidates<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pprev, Pinit, cnn_xi,
+                              Pcand, Pcur, Kcur);
+         })))
+      return rc;
+    if ((rc = run_icp_level(2, 0, 0, sums_net))) return rc;
+    if ((rc = launch(4, "set_current", [&] {
+           hipLaunchKernelGGL((k_set_current<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pinit, Pcur, Kcur);
+         })))
+      return rc;
+    if ((rc = run_icp_level(2, 0, 0, sums_cv))) return rc;
+    return launch(4, "choose_init", [&] {
+      hipLaunchKernelGGL((k_choose_init<T, D, Q>), dim3(1), dim3(64), 0, C->stream, sums_net, sums_cv, NS, Pcand,
+                         Pinit, Pcur, Kcur, counters, dframe, C->cfg.max_frames);
+    });
+  }
+
+  int set_cnn(xslam_cnn c) override {
+    cnn = c;
+    if (gexec) { hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { hipGraphDestroy(graph); graph = nullptr; }
+    use_graph = true;
+    return XSLAM_OK;
+  }
+
+  int cnn_parts(float* depth, float* model) override {
+    if (!measured || !have_model) return fail(XSLAM_ERR_STATE, "cnn_parts: needs a measured frame and model maps");
+    int rc = enqueue_cnn_parts(Kcur, depth, model);
+    return rc ? rc : sync();
   }
 
   // lost fallback + pose history (tracked frames), reset of the brick list

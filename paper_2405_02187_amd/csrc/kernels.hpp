@@ -186,7 +186,9 @@ template <int D, int Q> struct IcpSize {
 
 // per-frame counter row: 0 lost, 1 fused voxels, 2 raycast hits, 3 sum of ICP
 // correspondences, 4 last-pass correspondences, 5..29 per-pass correspondences,
-// 30 active bricks, 31 raycast samples
+// 30 active bricks, 31 raycast samples, 32 first pass (1-based) whose update
+// norm fell below 1e-6 (0: never), 33 initialiser used (0 previous / constant
+// velocity, 1 network)
 constexpr int kMaxPasses = 25;
 __device__ __forceinline__ int32_t* counter_row(int32_t* base, const int* frame, int max_frames) {
   return base + kCounters * min(*frame, max_frames - 1);
@@ -488,6 +490,11 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp_finish(IcpArgs<T, D, Q> g, 
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a) dx[a] = g.omega * dx[a];
+  {
+    double nn = 0.0;
+    for (int a = 0; a < 6; ++a) nn += dx[a].re() * dx[a].re();
+    if (crow[32] == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
+  }
   MPose<D, Q> E = se3_exp<D, Q>(dx);
   MPose<D, Q> Pn = pose_mul(E, *g.Pcur);
   *g.Pcur = Pn;
@@ -1038,6 +1045,103 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
     out.Z[l][il] = zhit;
     out.valid[l][il] = ok ? 1 : 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// learned initialiser plumbing
+// ---------------------------------------------------------------------------
+// Network input parts at pyramid level 3 (80 x 60 for 640 x 480): the depth
+// channel is the level-2 filtered depth reduced once more with the pyramid's
+// gated binomial (real parts); the model channels are the level-0 model maps
+// sampled at (8x, 8y): hit depth and the normal rotated into the camera frame
+// of pose Km.  Invalid pixels are 0.
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_cnn_parts(KParams<T, D, Q> kp, const T* __restrict__ D2,
+                                                   const T* __restrict__ Nm0, const T* __restrict__ Zm0,
+                                                   const uint8_t* __restrict__ mvalid0,
+                                                   const KPose<T, D, Q>* __restrict__ Km, float* __restrict__ out_depth,
+                                                   float* __restrict__ out_model) {
+  constexpr int NC = Jet<T, D, Q>::N;
+  const int W3 = kp.W >> 3, H3 = kp.H >> 3, W2 = kp.W >> 2, H2 = kp.H >> 2;
+  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  if (x >= W3 || y >= H3) return;
+  const int o = y * W3 + x;
+  // depth, level 3
+  float dv = 0.f;
+  const T c = D2[size_t(2 * y) * W2 + 2 * x];
+  if (c > T(0)) {
+    const int g[5] = {1, 4, 6, 4, 1};
+    T num = 0, den = 0;
+    for (int j = -2; j <= 2; ++j)
+      for (int i = -2; i <= 2; ++i) {
+        const int xx = 2 * x + i, yy = 2 * y + j;
+        if (xx < 0 || yy < 0 || xx >= W2 || yy >= H2) continue;
+        const T d = D2[size_t(yy) * W2 + xx];
+        if (!(d > T(0)) || fabs(d - c) > kp.pyr_gate) continue;
+        const T w = T(g[i + 2] * g[j + 2]);
+        num += w * d;
+        den += w;
+      }
+    dv = float(num / den);
+  }
+  out_depth[o] = dv;
+  // model, level 0 at (8x, 8y)
+  const size_t n0 = size_t(kp.W) * kp.H, s0 = size_t(8 * y) * kp.W + 8 * x;
+  float z = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
+  if (mvalid0[s0]) {
+    const T wx = Nm0[0 * NC * n0 + s0], wy = Nm0[1 * NC * n0 + s0], wz = Nm0[2 * NC * n0 + s0];
+    const KPose<T, D, Q>& P = *Km;
+    z = float(Zm0[s0]);
+    nx = float(P.R[0].re() * wx + P.R[3].re() * wy + P.R[6].re() * wz);
+    ny = float(P.R[1].re() * wx + P.R[4].re() * wy + P.R[7].re() * wz);
+    nz = float(P.R[2].re() * wx + P.R[5].re() * wy + P.R[8].re() * wz);
+  }
+  const int n3 = W3 * H3;
+  out_model[o] = z;
+  out_model[n3 + o] = nx;
+  out_model[2 * n3 + o] = ny;
+  out_model[3 * n3 + o] = nz;
+}
+
+// the two initial-pose candidates: network T_{k-1} exp(xi) (real increment,
+// the tangents come from T_{k-1}) and the previous / constant-velocity pose
+// already in Pinit; the network candidate becomes the current estimate
+template <typename T, int D, int Q>
+__global__ void k_init_candidates(const MPose<D, Q>* Pprev, const MPose<D, Q>* Pinit, const float* xi,
+                                  MPose<D, Q>* Pcand, MPose<D, Q>* Pcur, KPose<T, D, Q>* Kcur) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  using JD = Jet<double, D, Q>;
+  JD d[6];
+  for (int a = 0; a < 6; ++a) d[a] = jconst<JD>(double(xi[a]));
+  const MPose<D, Q> Tn = pose_mul(*Pprev, se3_exp<D, Q>(d));
+  *Pcand = Tn;
+  *Pcur = Tn;
+  *Kcur = to_kpose<T, double>(Tn);
+  (void)Pinit;
+}
+
+template <typename T, int D, int Q>
+__global__ void k_set_current(const MPose<D, Q>* P, MPose<D, Q>* Pcur, KPose<T, D, Q>* Kcur) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *Pcur = *P;
+  *Kcur = to_kpose<T, double>(*P);
+}
+
+// keep the candidate with the lower mean squared residual of one level-2 pass
+// (the network's only with at least 100 correspondences)
+template <typename T, int D, int Q>
+__global__ void k_choose_init(const double* sums_net, const double* sums_cv, int ns, const MPose<D, Q>* Pnet,
+                              MPose<D, Q>* Pinit, MPose<D, Q>* Pcur, KPose<T, D, Q>* Kcur, int32_t* counter_base,
+                              const int* frame, int max_frames) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t* crow = counter_row(counter_base, frame, max_frames);
+  const double cn = sums_net[ns - 2], cc = sums_cv[ns - 2];
+  const double en = cn > 0 ? sums_net[ns - 1] / cn : 1e300, ec = cc > 0 ? sums_cv[ns - 1] / cc : 1e300;
+  const bool use_net = cn >= 100.0 && en < ec;
+  if (use_net) *Pinit = *Pnet;
+  *Pcur = *Pinit;
+  *Kcur = to_kpose<T, double>(*Pinit);
+  crow[33] = use_net ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ C64, C128 = 0, 1
  P_ICPW0, P_ICPW1, P_ICPW2, P_FX, P_FY, P_CX, P_CY, P_DEPTH) = range(18)
 (F_POSE, F_POSES, F_TSDF, F_WEIGHT, F_VMAP, F_NMAP, F_ZMAP, F_MVALID, F_MEAS_DEPTH, F_MEAS_V,
  F_MEAS_N, F_MEAS_VALID, F_COUNTERS, F_PREV_POSE, F_FRAME) = range(15)
-N_COUNTERS = 32
+N_COUNTERS = 40
 
 
 class xslam_dir(C.Structure):
@@ -88,6 +88,8 @@ def lib():
             "xslam_sync": (C.c_int, [vp]),
             "xslam_last_error": (C.c_char_p, [vp]),
             "xslam_destroy": (C.c_int, [vp]),
+            "xslam_ctx_set_cnn": (C.c_int, [vp, vp]),
+            "xslam_cnn_parts": (C.c_int, [vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -96,10 +98,10 @@ def lib():
     return _lib
 
 
-EXPORTS = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
+EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
            "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
-           "xslam_destroy"]
+           "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts"]
 
 
 class XslamError(RuntimeError):
@@ -247,6 +249,18 @@ class Slam:
     def sync(self):
         return self._check(lib().xslam_sync(self.h))
 
+    def set_cnn(self, cnn):
+        self._cnn = cnn
+        return self._check(lib().xslam_ctx_set_cnn(self.h, None if cnn is None else cnn.h))
+
+    def cnn_parts(self):
+        """-> torch (1,60,80) depth channel and (4,60,80) model channels (device)."""
+        W3, H3 = self.cfg.cam.width >> 3, self.cfg.cam.height >> 3
+        d = self.torch.empty((1, H3, W3), dtype=self.torch.float32, device=self.ws.device)
+        m = self.torch.empty((4, H3, W3), dtype=self.torch.float32, device=self.ws.device)
+        self._check(lib().xslam_cnn_parts(self.h, C.c_void_p(d.data_ptr()), C.c_void_p(m.data_ptr())))
+        return d, m
+
     def set_timing(self, on=True):
         return self._check(lib().xslam_set_timing(self.h, 1 if on else 0))
 
@@ -321,3 +335,100 @@ class Slam:
             o1 += n
             o3 += 3 * n
         return out
+
+
+# --------------------------------------------------------------------------
+# learned ICP initialiser
+# --------------------------------------------------------------------------
+CNN_EXPORTS = ["xslam_cnn_param_count", "xslam_cnn_workspace_bytes", "xslam_cnn_create", "xslam_cnn_set_weights",
+               "xslam_cnn_get_weights", "xslam_cnn_get_grads", "xslam_cnn_forward", "xslam_cnn_train_step",
+               "xslam_cnn_last_error", "xslam_cnn_destroy"]
+
+
+def _cnn_lib():
+    L = lib()
+    if not getattr(L, "_cnn_sig", False):
+        vp, fp = C.c_void_p, C.POINTER(C.c_float)
+        sig = {
+            "xslam_cnn_param_count": (C.c_int32, []),
+            "xslam_cnn_workspace_bytes": (C.c_size_t, [C.c_int32]),
+            "xslam_cnn_create": (C.c_int, [vp, C.c_size_t, vp, C.c_int32, C.POINTER(vp)]),
+            "xslam_cnn_set_weights": (C.c_int, [vp, fp, C.c_size_t]),
+            "xslam_cnn_get_weights": (C.c_int, [vp, fp, C.c_size_t]),
+            "xslam_cnn_get_grads": (C.c_int, [vp, fp, C.c_size_t]),
+            "xslam_cnn_forward": (C.c_int, [vp, vp, C.c_int32, vp]),
+            "xslam_cnn_train_step": (C.c_int, [vp, vp, vp, C.c_int32, C.c_float, fp]),
+            "xslam_cnn_last_error": (C.c_char_p, [vp]),
+            "xslam_cnn_destroy": (C.c_int, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        L._cnn_sig = True
+    return L
+
+
+class Cnn:
+    """The initialiser network on one device (workspace from torch)."""
+
+    def __init__(self, max_batch=256, device="cuda:0"):
+        import torch
+        self.torch = torch
+        L = _cnn_lib()
+        self.n_params = L.xslam_cnn_param_count()
+        nbytes = L.xslam_cnn_workspace_bytes(max_batch)
+        if nbytes == 0:
+            raise XslamError("invalid batch size")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = L.xslam_cnn_create(C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                max_batch, C.byref(h))
+        if rc != 0:
+            raise XslamError(f"xslam_cnn_create: {rc}")
+        self.h = h
+        self.max_batch = max_batch
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise XslamError(f"cnn error {rc}: {_cnn_lib().xslam_cnn_last_error(self.h)}")
+
+    def set_weights(self, flat):
+        w = np.ascontiguousarray(flat, dtype=np.float32)
+        self._chk(_cnn_lib().xslam_cnn_set_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get_weights(self):
+        w = np.zeros(self.n_params, np.float32)
+        self._chk(_cnn_lib().xslam_cnn_get_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+        return w
+
+    def get_grads(self):
+        w = np.zeros(self.n_params, np.float32)
+        self._chk(_cnn_lib().xslam_cnn_get_grads(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+        return w
+
+    def forward(self, x):
+        """x: torch float32 (n,5,60,80) on the device -> torch (n,6)."""
+        out = self.torch.empty((x.shape[0], 6), dtype=self.torch.float32, device=x.device)
+        self._chk(_cnn_lib().xslam_cnn_forward(self.h, C.c_void_p(x.data_ptr()), x.shape[0], C.c_void_p(out.data_ptr())))
+        return out
+
+    def train_step(self, x, label, lr=1e-3, want_loss=True):
+        loss = C.c_float(0)
+        self._chk(_cnn_lib().xslam_cnn_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(label.data_ptr()),
+                                                  x.shape[0], lr, C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "h", None):
+            _cnn_lib().xslam_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+EXPORTS = EXPORTS_CORE + CNN_EXPORTS

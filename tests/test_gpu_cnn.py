@@ -1,0 +1,93 @@
+"""GPU: the learned ICP initialiser's bf16 MFMA forward/backward and Adam
+against the FP64 CNN oracle (bf16 weights and activations with FP32
+accumulation: per-tensor agreement within a few percent), and training that
+lowers the loss."""
+import numpy as np
+import pytest
+
+from oracle import cnn as OC
+from gpu_util import log, relerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_02187_amd import xslam as X  # noqa: E402
+
+
+def flat(params):
+    return np.concatenate([p.reshape(-1) for p in params])
+
+
+def unflat(v):
+    out, o = [], 0
+    for s in OC.shapes():
+        n = int(np.prod(s))
+        out.append(v[o:o + n].reshape(s))
+        o += n
+    return out
+
+
+def batch(n, seed=0):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 5, 60, 80))
+    x[:, 0:2] = 1.0 + rng.random((n, 2, 60, 80))           # depths
+    nrm = rng.standard_normal((n, 3, 60, 80))
+    x[:, 2:] = nrm / np.linalg.norm(nrm, axis=1, keepdims=True)
+    x[:, :, :5, :7] = 0.0                                  # an invalid corner
+    return x
+
+
+def test_param_count_matches_oracle():
+    assert X.Cnn(max_batch=4).n_params == OC.n_params()
+
+
+def test_forward_and_gradients_match_oracle():
+    N = 16
+    net = X.Cnn(max_batch=N)
+    p = OC.init_params(0)
+    p = [q + (0.01 if q.ndim == 1 else 0.0) for q in p]
+    net.set_weights(flat(p))
+    x = batch(N)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    xi = net.forward(xt).cpu().numpy()
+    ref, cache = OC.forward(p, x)
+    e = relerr(xi, ref)
+    log("cnn forward rel err", e)
+    assert e <= 3e-2
+    label = ref + 0.01 * np.random.default_rng(1).standard_normal(ref.shape)
+    lt = torch.from_numpy(label.astype(np.float32)).cuda()
+    loss = net.train_step(xt, lt, lr=1e-3)
+    g = unflat(net.get_grads())
+    rg = OC.backward(p, cache, ref, label)
+    assert abs(loss - OC.loss(ref, label)) <= 0.1 * OC.loss(ref, label)
+    for k in range(12):
+        ek = relerr(g[k], rg[k])
+        log("grad", k, OC.shapes()[k], "rel err", ek)
+        assert ek <= 8e-2, k
+    # the Adam step on the GPU's own gradients
+    newp = unflat(net.get_weights())
+    zeros = [np.zeros_like(q) for q in p]
+    exp_p, _, _ = OC.adam_step(p, g, zeros, zeros, t=1, lr=1e-3)
+    for k in range(12):
+        assert np.allclose(newp[k], exp_p[k], rtol=1e-5, atol=1e-6), k
+    net.close()
+
+
+def test_training_reduces_loss():
+    N = 64
+    net = X.Cnn(max_batch=N)
+    net.set_weights(flat(OC.init_params(3)))
+    rng = np.random.default_rng(5)
+    x = batch(N, seed=2)
+    # a learnable target: means of the input channels mixed linearly
+    A = 0.01 * rng.standard_normal((6, 5))
+    label = x.mean(axis=(2, 3)) @ A.T
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    lt = torch.from_numpy(label.astype(np.float32)).cuda()
+    losses = [net.train_step(xt, lt, lr=1e-3) for _ in range(150)]
+    log("cnn training loss", losses[0], losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    net.close()

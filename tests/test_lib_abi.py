@@ -39,7 +39,7 @@ def test_workspace_sizes():
 
 @pytest.mark.parametrize("bad", [
     dict(width=642), dict(dim=(500, 512, 512)), dict(voxel=0.0), dict(iters=(20, 10, 0)),
-    dict(bilateral_radius=9), dict(init=2),
+    dict(bilateral_radius=9), dict(init=3), dict(init=2, width=320, height=240),
 ])
 def test_invalid_configs_size_to_zero(bad):
     p1 = sg.preset("c1")
