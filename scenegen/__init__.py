@@ -319,9 +319,23 @@ class Sequence:
             self._cache[key] = (d.astype(self.depth_dtype), tan.astype(self.depth_dtype))
         return self._cache[key]
 
-    def depths(self, n: int | None = None, noise: bool = True) -> np.ndarray:
+    def depths(self, n: int | None = None, noise: bool = True, workers: int = 1) -> np.ndarray:
+        """Depth frames 0..n-1 (``workers`` > 1 renders them in a process pool)."""
         n = len(self) if n is None else n
+        if workers > 1 and n > 1:
+            from concurrent.futures import ProcessPoolExecutor
+            args = [(self.scene, self.poses_gt[k], self.camera, self.seed, k, noise, self.sigma2,
+                     self.depth_dtype) for k in range(n)]
+            with ProcessPoolExecutor(workers) as ex:
+                return np.stack(list(ex.map(_render_one, args, chunksize=4)))
         return np.stack([self.frame(k, noise)[0] for k in range(n)])
+
+
+def _render_one(a):
+    scene, pose, c, seed, k, noise, sigma2, dt = a
+    z = render_depth(scene, pose, c["width"], c["height"], c["fx"], c["fy"], c["cx"], c["cy"])
+    d = add_noise(z, seed, k, sigma2)[0] if noise else z
+    return d.astype(dt)
 
 
 PRESETS = {
