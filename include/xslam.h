@@ -125,10 +125,13 @@ enum xslam_field {
   XSLAM_F_MEAS_V = 9,    /* measured vertex maps (camera), levels 0,1,2: [3][NC][n_l] each   */
   XSLAM_F_MEAS_N = 10,   /* measured normal maps (camera), levels 0,1,2                      */
   XSLAM_F_MEAS_VALID = 11,/* measured validity, uint8, levels 0,1,2                          */
-  XSLAM_F_COUNTERS = 12, /* per frame int32[32]: 0 lost, 1 fused voxels, 2 raycast hits,
+  XSLAM_F_COUNTERS = 12, /* per frame int32[40]: 0 lost, 1 fused voxels, 2 raycast hits,
                             3 sum of ICP correspondences, 4 last-pass correspondences,
                             5..29 correspondences of every ICP pass, 30 bricks visited by
-                            fusion, 31 raycast samples                                      */
+                            fusion, 31 raycast samples, 32 first ICP pass (1-based) whose
+                            update norm |xi| fell below 1e-6 (0: none),
+                            33 initialiser used (1 network, 0 constant velocity),
+                            34..39 reserved (0)                                             */
   XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
   XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
 };

@@ -51,10 +51,14 @@ inline Bicomplex operator*(const Bicomplex& x, const Bicomplex& y) {
   return {x.a * y.a - x.b * y.b, x.a * y.b + x.b * y.a};  // i2^2 = -1, exact product
 }
 inline Bicomplex operator/(const Bicomplex& x, const Bicomplex& y) {
-  // 1/(c + d i2) = (c - d i2)/(c^2 + d^2), c^2 + d^2 in C(i1)
-  cd den = y.a * y.a + y.b * y.b;
-  Bicomplex inv(y.a / den, -y.b / den);
-  return x * inv;
+  // The exact quotient q = x / y of q y = x:
+  //   q.b = (x.b y.a - x.a y.b) / (y.a^2 + y.b^2),   q.a = (x.a + q.b y.b) / y.a.
+  // Written this way (not as x times 1/y) the real part of q is the real
+  // quotient re(x)/re(y) of a real run, so that every decision taken on real
+  // parts is the real run's.
+  const cd qb = (x.b * y.a - x.a * y.b) / (y.a * y.a + y.b * y.b);
+  const cd qa = (x.a + qb * y.b) / y.a;
+  return {qa, qb};
 }
 inline Bicomplex& operator+=(Bicomplex& x, const Bicomplex& y) { x = x + y; return x; }
 inline Bicomplex& operator-=(Bicomplex& x, const Bicomplex& y) { x = x - y; return x; }

@@ -907,7 +907,7 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
                                                   const uint8_t* __restrict__ flags,
                                                   typename Vec2<T>::type* __restrict__ bracket,
                                                   int* __restrict__ block_samples) {
-  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   int nsamp = 0;
   if (x < W && y < H) {
@@ -983,7 +983,7 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
                                                 const typename Vec2<T>::type* __restrict__ bracket,
                                                 MapsOut<T, D, Q> out, int* __restrict__ block_hits) {
   using J = Jet<T, D, Q>;
-  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   const bool inside = x < W && y < H;
   bool ok = false;

@@ -57,16 +57,18 @@ def test_forward_and_gradients_match_oracle():
     e = relerr(xi, ref)
     log("cnn forward rel err", e)
     assert e <= 3e-2
-    label = ref + 0.01 * np.random.default_rng(1).standard_normal(ref.shape)
+    # labels far from the output, so that the loss gradient is set by the label
+    # and not by the bf16 rounding of the forward pass (which the oracle lacks)
+    label = ref + 0.5 * np.random.default_rng(1).standard_normal(ref.shape)
     lt = torch.from_numpy(label.astype(np.float32)).cuda()
     loss = net.train_step(xt, lt, lr=1e-3)
     g = unflat(net.get_grads())
     rg = OC.backward(p, cache, ref, label)
     assert abs(loss - OC.loss(ref, label)) <= 0.1 * OC.loss(ref, label)
+    errs = [relerr(g[k], rg[k]) for k in range(12)]
     for k in range(12):
-        ek = relerr(g[k], rg[k])
-        log("grad", k, OC.shapes()[k], "rel err", ek)
-        assert ek <= 8e-2, k
+        log("grad", k, OC.shapes()[k], "rel err", errs[k])
+    assert max(errs) <= 8e-2, errs
     # the Adam step on the GPU's own gradients
     newp = unflat(net.get_weights())
     zeros = [np.zeros_like(q) for q in p]

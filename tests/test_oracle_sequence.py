@@ -144,3 +144,21 @@ def test_trajectory_error_closed_form():
     ref = np.sqrt(np.mean(np.sum(off ** 2, -1)))
     assert E[0] == pytest.approx(ref, rel=1e-14)
     assert E[1] / h == pytest.approx(ref, rel=1e-13)   # E is 1-homogeneous in the offsets
+
+
+@pytest.mark.parametrize("pair", [(O.P_TRUNC, O.P_TRUNC), (O.P_TRUNC, O.P_FX), (O.P_RHO_X, O.P_CY)])
+def test_bicomplex_and_complex_runs_share_the_real_run(pair):
+    """Sec. 3: the real part of a complex-step evaluation is f(x) up to O(h^2),
+    i.e. exactly f(x) in FP64 at h = 1e-20.  Every decision (validity, taps,
+    gates, update masks) is taken on real parts, so complex and bicomplex runs
+    must reproduce the real run bit for bit: poses, TSDF, weights and counts."""
+    depths, T0, _ = small_seq()
+    c = small_cfg()
+    r0 = O.run_sequence(c, O.seed(0), depths, T0, want_volume=True)
+    rc = O.run_sequence(c, O.seed(1, pair[0], h=1e-20), depths, T0, want_volume=True)
+    rb = O.run_sequence(c, O.seed(2, pair[0], pair[1], 1e-20), depths, T0, want_volume=True)
+    for r in (rc, rb):
+        assert np.array_equal(r["poses"][..., 0], r0["poses"][..., 0])
+        assert np.array_equal(r["F"][:, 0], r0["F"][:, 0])
+        assert np.array_equal(r["W"][:, 0], r0["W"][:, 0])
+        assert np.array_equal(r["stats"][:, [0, 1, 3, 4, 5]], r0["stats"][:, [0, 1, 3, 4, 5]])
