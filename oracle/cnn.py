@@ -9,6 +9,14 @@ batch is the mean over samples of |diag(1/0.01) (xi_hat - xi)|^2.  Training
 uses Adam.  This file writes those definitions out with plain numpy loops over
 kernel offsets; backward passes are derived by hand.  Only tests and the
 benchmark's CPU baseline use it.
+
+``quant=bf16_round`` (forward and backward) rounds to bfloat16 at the points
+where a bf16 implementation stores values: the network input, the
+convolution weights and biases, every post-ReLU activation, and the gradient
+with respect to every convolution output.  Arithmetic stays FP64.  The ReLU
+masks are decisions taken by floating point, so a bf16 implementation is
+compared with this mode (both take the masks from bf16-stored values); with
+``quant=None`` everything is FP64.
 """
 from __future__ import annotations
 
@@ -51,6 +59,20 @@ def init_params(seed: int = 0):
     return out
 
 
+def bf16_round(a):
+    """Round to the nearest bfloat16 (the upper 16 bits of an IEEE binary32,
+    ties to even), returned as float64.  The value is first rounded to
+    binary32."""
+    a32 = np.ascontiguousarray(a, dtype=np.float32)
+    bits = a32.view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(a):
+    return a
+
+
 def conv_s2(x, w, b):
     """x (N,Ci,H,W), w (Co,Ci,3,3), stride 2, zero padding 1 -> (N,Co,Ho,Wo)."""
     N, Ci, H, W = x.shape
@@ -82,21 +104,23 @@ def conv_s2_backward(x, w, dy):
     return dxp[:, :, 1:H + 1, 1:W + 1], dw, db
 
 
-def forward(params, x):
+def forward(params, x, quant=None):
     """-> (xi (N,6), cache)."""
-    acts = [x]
+    q = quant or _ident
+    h = q(x)
+    acts = [h]
     pre = []
-    h = x
+    convw = [(q(params[2 * i]), q(params[2 * i + 1])) for i in range(4)]
     for i in range(4):
-        z = conv_s2(h, params[2 * i], params[2 * i + 1])
+        z = conv_s2(h, *convw[i])
         pre.append(z)
-        h = np.maximum(z, 0.0)
+        h = q(np.maximum(z, 0.0))
         acts.append(h)
     g = h.mean(axis=(2, 3))                                                  # (N,128)
     z5 = g @ params[8].T + params[9]
     h5 = np.maximum(z5, 0.0)
     xi = h5 @ params[10].T + params[11]
-    return xi, dict(acts=acts, pre=pre, g=g, z5=z5, h5=h5)
+    return xi, dict(acts=acts, pre=pre, g=g, z5=z5, h5=h5, convw=convw, quant=q)
 
 
 def loss(xi, label):
@@ -117,10 +141,11 @@ def backward(params, cache, xi, label):
     grads[9] = dz5.sum(0)
     dg = dz5 @ params[8]
     h4 = cache["acts"][4]
+    q = cache["quant"]
     dh = np.broadcast_to(dg[:, :, None, None] / (h4.shape[2] * h4.shape[3]), h4.shape).copy()
     for i in range(3, -1, -1):
-        dz = dh * (cache["pre"][i] > 0)
-        dx, dw, db = conv_s2_backward(cache["acts"][i], params[2 * i], dz)
+        dz = q(dh * (cache["pre"][i] > 0))
+        dx, dw, db = conv_s2_backward(cache["acts"][i], cache["convw"][i][0], dz)
         grads[2 * i], grads[2 * i + 1] = dw, db
         dh = dx
     return grads

@@ -45,6 +45,12 @@ def test_param_count_matches_oracle():
 
 
 def test_forward_and_gradients_match_oracle():
+    """Against the oracle in bf16-storage mode (weights, activations and
+    activation gradients rounded to bf16 where the kernels store them, so the
+    ReLU masks are decided on the same values): what is left is FP32 versus
+    FP64 accumulation and the rare bf16 rounding it tips over, 1e-2 at most.
+    The all-FP64 network is the reference for the quantisation error itself
+    (3e-2 on the output)."""
     N = 16
     net = X.Cnn(max_batch=N)
     p = OC.init_params(0)
@@ -53,28 +59,30 @@ def test_forward_and_gradients_match_oracle():
     x = batch(N)
     xt = torch.from_numpy(x.astype(np.float32)).cuda()
     xi = net.forward(xt).cpu().numpy()
-    ref, cache = OC.forward(p, x)
-    e = relerr(xi, ref)
-    log("cnn forward rel err", e)
-    assert e <= 3e-2
-    # labels far from the output, so that the loss gradient is set by the label
-    # and not by the bf16 rounding of the forward pass (which the oracle lacks)
+    ref64, _ = OC.forward(p, x)
+    ref, cache = OC.forward(p, x, quant=OC.bf16_round)
+    e64, e = relerr(xi, ref64), relerr(xi, ref)
+    log("cnn forward rel err vs FP64", e64, "vs bf16-storage oracle", e)
+    assert e64 <= 3e-2 and e <= 2e-3
+    # labels far from the output: the loss gradient is set by the label
     label = ref + 0.5 * np.random.default_rng(1).standard_normal(ref.shape)
     lt = torch.from_numpy(label.astype(np.float32)).cuda()
     loss = net.train_step(xt, lt, lr=1e-3)
     g = unflat(net.get_grads())
     rg = OC.backward(p, cache, ref, label)
-    assert abs(loss - OC.loss(ref, label)) <= 0.1 * OC.loss(ref, label)
+    assert abs(loss - OC.loss(ref, label)) <= 1e-3 * OC.loss(ref, label)
     errs = [relerr(g[k], rg[k]) for k in range(12)]
     for k in range(12):
         log("grad", k, OC.shapes()[k], "rel err", errs[k])
-    assert max(errs) <= 8e-2, errs
-    # the Adam step on the GPU's own gradients
+    assert max(errs) <= 1e-2, errs
+    # one Adam step (t = 1) from the oracle's gradients: p - lr g/(|g| + eps),
+    # compared where the gradient is not near zero (its sign decides there)
     newp = unflat(net.get_weights())
     zeros = [np.zeros_like(q) for q in p]
-    exp_p, _, _ = OC.adam_step(p, g, zeros, zeros, t=1, lr=1e-3)
+    exp_p, _, _ = OC.adam_step(p, rg, zeros, zeros, t=1, lr=1e-3)
     for k in range(12):
-        assert np.allclose(newp[k], exp_p[k], rtol=1e-5, atol=1e-6), k
+        sel = np.abs(rg[k]) > 1e-2 * np.abs(rg[k]).max()
+        assert np.allclose(newp[k][sel], exp_p[k][sel], rtol=1e-5, atol=1e-6), k
     net.close()
 
 

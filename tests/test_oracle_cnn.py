@@ -80,3 +80,26 @@ def test_adam_first_step_is_sign_step():
     g = [np.array([0.5, -4.0, 1e-3])]
     P, M, V = cnn.adam_step(p, g, [np.zeros(3)], [np.zeros(3)], t=1, lr=0.1)
     assert np.allclose(P[0], p[0] - 0.1 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
+
+
+def test_bf16_round_ties_to_even_and_matches_torch():
+    one = 1.0
+    u = 2.0 ** -7                       # bf16 spacing at 1
+    vals = np.array([one, one + u / 2, one + 3 * u / 2, one + u / 2 + 2.0 ** -20, -2.5 - u / 4, 3.0e-5, 1e30])
+    r = cnn.bf16_round(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == one + 2 * u and r[3] == one + u
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    a = np.concatenate([vals, rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000)])
+    tb = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(cnn.bf16_round(a), tb)
+
+
+def test_bf16_storage_mode_stays_close_to_fp64():
+    p = cnn.init_params(0)
+    rng = np.random.default_rng(0)
+    x = 1.0 + rng.random((2, 5, 60, 80))
+    a, _ = cnn.forward(p, x)
+    b, cache = cnn.forward(p, x, quant=cnn.bf16_round)
+    assert np.abs(a - b).max() <= 3e-2 * np.abs(a).max()
+    assert all(np.array_equal(cnn.bf16_round(h), h) for h in cache["acts"])
