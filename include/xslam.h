@@ -197,6 +197,37 @@ int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
 int xslam_set_timing(xslam_ctx ctx, int32_t on);
 int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]);
 
+/* ---- launch shapes and the autotuner ----------------------------------------
+ * Launch shapes that do not change any result bit except the order of the
+ * FP64 cross-block ICP sums (rounding level): the raycast tile (threads per
+ * workgroup in x and y; x*y a multiple of 64 in [64, 256]), the ICP grid per
+ * pyramid level (workgroups of 256 threads, 1..512; 0 = one pixel per thread
+ * up to 512 workgroups) and the fusion grid (workgroups of one 8^3 brick each,
+ * 64..4096, a grid-stride loop over the active-brick list).  Setting shapes
+ * drops the captured frame graph (it is captured again on the next step).
+ * Errors: XSLAM_ERR_ARG for a shape outside these limits. */
+typedef struct {
+  int32_t ray_tile[2];   /* raycast workgroup (x, y); default 16 x 16          */
+  int32_t icp_blocks[3]; /* ICP workgroups at levels 0, 1, 2; 0 = default       */
+  int32_t fuse_blocks;   /* fusion workgroups; default 4096                      */
+  int32_t reserved[2];   /* 0                                                    */
+} xslam_launch;
+
+int xslam_set_launch(xslam_ctx ctx, const xslam_launch* shapes);
+/* the shapes in use (defaults resolved to numbers) */
+int xslam_get_launch(xslam_ctx ctx, xslam_launch* out);
+/* Time every candidate shape of the stages that can be re-run without
+ * changing state, with HIP events (reps launches each, after one untimed
+ * launch), and keep the fastest: the raycast tile (re-running the raycast of
+ * the current pose rewrites the same model maps) and the ICP grid of each
+ * level (association and sums only; the pose is not changed).  The fusion
+ * grid changes the TSDF when run, so it is not timed here: time real steps
+ * with different fuse_blocks instead (no result depends on it).  Requires a
+ * measured frame and model maps (after xslam_step).  best (optional)
+ * receives the shapes in use afterwards; ms_out (optional, 4 doubles) the
+ * best mean times (ms) of raycast, ICP level 0, level 1 and level 2. */
+int xslam_autotune(xslam_ctx ctx, int32_t reps, xslam_launch* best, double* ms_out);
+
 /* ---- learned ICP initialiser (a systems form beyond the paper) -------------
  * A CNN proposes the ICP initial pose increment from coarse maps: input
  * 5 x 60 x 80 FP32 (current depth at pyramid level 3; raycast depth and raycast

@@ -262,6 +262,25 @@ int xslam_cnn_parts(xslam_ctx ctx, float* depth_dev, float* model_dev) {
   return ctx->eng->cnn_parts(depth_dev, model_dev);
 }
 
+int xslam_set_launch(xslam_ctx ctx, const xslam_launch* shapes) {
+  XS_CTX_CHECK(ctx);
+  if (!shapes) return XSLAM_ERR_ARG;
+  return ctx->eng->set_launch(*shapes);
+}
+
+int xslam_get_launch(xslam_ctx ctx, xslam_launch* out) {
+  XS_CTX_CHECK(ctx);
+  if (!out) return XSLAM_ERR_ARG;
+  return ctx->eng->get_launch(out);
+}
+
+int xslam_autotune(xslam_ctx ctx, int32_t reps, xslam_launch* best, double* ms_out) {
+  XS_CTX_CHECK(ctx);
+  int rc = ctx->eng->autotune(reps, ms_out);
+  if (!rc && best) rc = ctx->eng->get_launch(best);
+  return rc;
+}
+
 int xslam_sync(xslam_ctx ctx) {
   XS_CTX_CHECK(ctx);
   hipError_t e = hipStreamSynchronize(ctx->stream);

@@ -23,6 +23,9 @@ struct EngineBase {
   virtual int frame_lost(int* lost) = 0;
   virtual int set_cnn(xslam_cnn cnn) = 0;
   virtual int cnn_parts(float* depth, float* model) = 0;
+  virtual int set_launch(const xslam_launch& l) = 0;
+  virtual int get_launch(xslam_launch* l) = 0;
+  virtual int autotune(int reps, double* ms_out) = 0;
 };
 
 struct Timer {

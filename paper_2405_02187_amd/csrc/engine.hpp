@@ -67,6 +67,14 @@ struct Engine : EngineBase {
   int ntiles = 0;
   hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
+  // launch shapes (none changes a result beyond the order of the FP64 ICP sums)
+  int ray_bx = 16, ray_by = 16;
+  int icp_grid[3] = {0, 0, 0};      // 0: one pixel per thread, at most kMaxIcpBlocks
+  int fuse_grid = kFuseBlocks;
+
+  // workgroups of any raycast tile of at least 64 threads:
+  // ceil(W/bx) ceil(H/by) <= W H / 64 + W + H + 1
+  static int ray_block_capacity(int w, int h) { return w * h / 64 + w + h + 1; }
 
   // ---- workspace plan ---------------------------------------------------
   static size_t plan(const xslam_config& c, int ndd, bool wtan, Engine* e, char* base) {
@@ -107,7 +115,7 @@ struct Engine : EngineBase {
     uint8_t* bflags = cv.take<uint8_t>(nb);
     const int nt = ((c.cam.width + kTile - 1) / kTile) * ((c.cam.height + kTile - 1) / kTile);
     T* tzmax = cv.take<T>(nt);
-    const int nrb = ((c.cam.width + 15) / 16) * ((c.cam.height + 15) / 16);
+    const int nrb = ray_block_capacity(c.cam.width, c.cam.height);
     int* fcounts = cv.take<int>(kFuseBlocks);
     int* rhits = cv.take<int>(nrb);
     int* rsamples = cv.take<int>(nrb);
@@ -315,7 +323,8 @@ struct Engine : EngineBase {
     a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l];
     a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums_out ? sums_out : sums;
     a.frame = dframe; a.max_frames = C->cfg.max_frames;
-    int blocks = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+    int blocks = icp_grid[l] > 0 ? icp_grid[l]
+                                 : int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
     int rc = launch(1, "icp", [&] {
       hipLaunchKernelGGL((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
     });
@@ -376,10 +385,107 @@ struct Engine : EngineBase {
     });
   }
 
-  int set_cnn(xslam_cnn c) override {
-    cnn = c;
+  void drop_graph() {
     if (gexec) { hipGraphExecDestroy(gexec); gexec = nullptr; }
     if (graph) { hipGraphDestroy(graph); graph = nullptr; }
+  }
+
+  int set_launch(const xslam_launch& l) override {
+    const int bx = l.ray_tile[0], by = l.ray_tile[1];
+    if (bx < 1 || by < 1 || bx * by < 64 || bx * by > 256 || (bx * by) % 64 != 0)
+      return fail(XSLAM_ERR_ARG, "launch: raycast tile x*y must be a multiple of 64 in [64, 256]");
+    for (int i = 0; i < 3; ++i)
+      if (l.icp_blocks[i] < 0 || l.icp_blocks[i] > kMaxIcpBlocks)
+        return fail(XSLAM_ERR_ARG, "launch: ICP workgroups must be in [0, 512]");
+    if (l.fuse_blocks < 64 || l.fuse_blocks > kFuseBlocks)
+      return fail(XSLAM_ERR_ARG, "launch: fusion workgroups must be in [64, 4096]");
+    ray_bx = bx;
+    ray_by = by;
+    for (int i = 0; i < 3; ++i) icp_grid[i] = l.icp_blocks[i];
+    fuse_grid = l.fuse_blocks;
+    drop_graph();
+    return XSLAM_OK;
+  }
+
+  int get_launch(xslam_launch* l) override {
+    l->ray_tile[0] = ray_bx;
+    l->ray_tile[1] = ray_by;
+    for (int i = 0; i < 3; ++i)
+      l->icp_blocks[i] = icp_grid[i] > 0 ? icp_grid[i]
+                                         : int(std::min<size_t>((npx[i] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+    l->fuse_blocks = fuse_grid;
+    l->reserved[0] = l->reserved[1] = 0;
+    return XSLAM_OK;
+  }
+
+  // mean time (ms) of reps runs of f after one untimed run, HIP events on the stream
+  template <typename F> int time_ms(int reps, double* ms, F&& f) {
+    int rc = f();
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return check("autotune events");
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return check("autotune events"); }
+    hipEventRecord(e0, C->stream);
+    for (int r = 0; r < reps && !rc; ++r) rc = f();
+    hipEventRecord(e1, C->stream);
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = check("autotune sync");
+    float t = 0.f;
+    if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = check("autotune timing");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = double(t) / reps;
+    return rc;
+  }
+
+  int autotune(int reps, double* ms_out) override {
+    if (!measured || !have_model) return fail(XSLAM_ERR_STATE, "autotune: needs a measured frame and model maps");
+    if (reps < 1 || reps > 1000) return fail(XSLAM_ERR_ARG, "autotune: reps in [1, 1000]");
+    if (gexec) drop_graph();
+    int rc = sync();
+    if (rc) return rc;
+    const bool timing = C->timer.on;
+    C->timer.on = false;
+    // raycast tile
+    static const int tiles[][2] = {{16, 16}, {32, 8}, {8, 32}, {64, 4}, {16, 8}, {32, 4}, {64, 2},
+                                   {8, 8},   {16, 4}, {32, 2}, {64, 1}};
+    double best_ray = 1e30;
+    int bbx = ray_bx, bby = ray_by;
+    for (auto& t : tiles) {
+      ray_bx = t[0];
+      ray_by = t[1];
+      double ms = 0;
+      if ((rc = time_ms(reps, &ms, [&] { return run_raycast(); }))) break;
+      if (ms < best_ray) { best_ray = ms; bbx = t[0]; bby = t[1]; }
+    }
+    ray_bx = bbx;
+    ray_by = bby;
+    if (!rc) rc = run_raycast();       // the model maps again with the chosen tile (same values)
+    // ICP grid per level (sums only)
+    double best_icp[3] = {1e30, 1e30, 1e30};
+    for (int l = 0; l < 3 && !rc; ++l) {
+      const int full = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+      int bestg = icp_grid[l];
+      for (int gsz : {full, 512, 384, 256, 192, 128, 96, 64, 32}) {
+        if (gsz > full) continue;
+        icp_grid[l] = gsz;
+        double ms = 0;
+        if ((rc = time_ms(reps, &ms, [&] { return run_icp_level(l, 0, 0, sums); }))) break;
+        if (ms < best_icp[l]) { best_icp[l] = ms; bestg = gsz; }
+      }
+      icp_grid[l] = bestg;
+    }
+    C->timer.on = timing;
+    if (!rc) rc = sync();
+    if (ms_out) {
+      ms_out[0] = best_ray;
+      for (int l = 0; l < 3; ++l) ms_out[1 + l] = best_icp[l];
+    }
+    return rc;
+  }
+
+  int set_cnn(xslam_cnn c) override {
+    cnn = c;
+    drop_graph();
     use_graph = true;
     return XSLAM_OK;
   }
@@ -412,7 +518,7 @@ struct Engine : EngineBase {
                               tzmax, nbrick, blist, bcount, lost);
          })))
       return rc;
-    const int g = std::min(nbrick, kFuseBlocks);
+    const int g = std::min(nbrick, fuse_grid);
     if ((rc = launch(2, "fuse", [&] {
            hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
                               Wtan, lost, nvox, blist, bcount, fcounts);
@@ -440,7 +546,7 @@ struct Engine : EngineBase {
   int run_raycast() {
     MapsOut<T, D, Q> o;
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
-    dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
+    dim3 b(ray_bx, ray_by), g((W[0] + ray_bx - 1) / ray_bx, (H[0] + ray_by - 1) / ray_by);
     int rc = launch(3, "raymarch", [&] {
       hipLaunchKernelGGL((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
     });

@@ -52,6 +52,11 @@ class xslam_icp(C.Structure):
                 ("level_w", C.c_double * 3), ("disc_delta", C.c_double), ("init", C.c_int32)]
 
 
+class xslam_launch(C.Structure):
+    _fields_ = [("ray_tile", C.c_int32 * 2), ("icp_blocks", C.c_int32 * 3), ("fuse_blocks", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
 class xslam_config(C.Structure):
     _fields_ = [("prec", C.c_int32), ("cam", xslam_camera), ("vol", xslam_volume), ("icp", xslam_icp),
                 ("bilateral_radius", C.c_int32), ("bilateral_sigma_px", C.c_double),
@@ -90,6 +95,9 @@ def lib():
             "xslam_destroy": (C.c_int, [vp]),
             "xslam_ctx_set_cnn": (C.c_int, [vp, vp]),
             "xslam_cnn_parts": (C.c_int, [vp, vp, vp]),
+            "xslam_set_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
+            "xslam_get_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
+            "xslam_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(xslam_launch), dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -101,7 +109,8 @@ def lib():
 EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
            "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
-           "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts"]
+           "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
+           "xslam_autotune"]
 
 
 class XslamError(RuntimeError):
@@ -170,6 +179,7 @@ class Slam:
         self.torch = torch
         self.cfg, self.pert = cfg, pert
         self.nc = pert.ncomp
+        self.D, self.Q = len(pert.dirs), pert.q
         self.dtype = torch.float32 if cfg.prec == C64 else torch.float64
         self.np_dtype = np.float32 if cfg.prec == C64 else np.float64
         nbytes = workspace_bytes(cfg, pert)
@@ -260,6 +270,27 @@ class Slam:
         m = self.torch.empty((4, H3, W3), dtype=self.torch.float32, device=self.ws.device)
         self._check(lib().xslam_cnn_parts(self.h, C.c_void_p(d.data_ptr()), C.c_void_p(m.data_ptr())))
         return d, m
+
+    def get_launch(self) -> dict:
+        lc = xslam_launch()
+        self._check(lib().xslam_get_launch(self.h, C.byref(lc)))
+        return dict(ray_tile=tuple(lc.ray_tile), icp_blocks=tuple(lc.icp_blocks), fuse_blocks=lc.fuse_blocks)
+
+    def set_launch(self, ray_tile=None, icp_blocks=None, fuse_blocks=None):
+        cur = self.get_launch()
+        lc = xslam_launch()
+        lc.ray_tile[:] = list(ray_tile or cur["ray_tile"])
+        lc.icp_blocks[:] = list(icp_blocks or cur["icp_blocks"])
+        lc.fuse_blocks = int(fuse_blocks or cur["fuse_blocks"])
+        return self._check(lib().xslam_set_launch(self.h, C.byref(lc)))
+
+    def autotune(self, reps=20):
+        """Time candidate raycast tiles and ICP grids on the current state; keeps
+        the fastest.  -> (shapes dict, ms of raycast and ICP levels 0, 1, 2)."""
+        lc = xslam_launch()
+        ms = np.zeros(4)
+        self._check(lib().xslam_autotune(self.h, int(reps), C.byref(lc), ms.ctypes.data_as(C.POINTER(C.c_double))))
+        return self.get_launch(), ms
 
     def set_timing(self, on=True):
         return self._check(lib().xslam_set_timing(self.h, 1 if on else 0))

@@ -44,17 +44,24 @@ def test_param_count_matches_oracle():
     assert X.Cnn(max_batch=4).n_params == OC.n_params()
 
 
-def test_forward_and_gradients_match_oracle():
+@pytest.mark.parametrize("fc1_shift,conv_tol", [(5.0, 5e-3), (0.0, 5e-2)])
+def test_forward_and_gradients_match_oracle(fc1_shift, conv_tol):
     """Against the oracle in bf16-storage mode (weights, activations and
     activation gradients rounded to bf16 where the kernels store them, so the
-    ReLU masks are decided on the same values): what is left is FP32 versus
-    FP64 accumulation and the rare bf16 rounding it tips over, 1e-2 at most.
-    The all-FP64 network is the reference for the quantisation error itself
-    (3e-2 on the output)."""
+    convolution ReLU masks are decided on the same stored values): what is
+    left is FP32 versus FP64 accumulation and the rare bf16 rounding it tips
+    over (forward 2e-3, head gradients 5e-3).  The hidden fully connected
+    layer decides its ReLU on FP32 (kernel) versus FP64 (oracle) values that
+    differ by ~1e-3; a unit within that margin of zero flips the gradient of
+    its whole sample.  With its bias shifted by +5 every unit is active and
+    the convolution gradients agree within 5e-3; with the plain init a few
+    flips move them by up to a few percent (5e-2).  The all-FP64 network is
+    the reference for the quantisation error itself (3e-2 on the output)."""
     N = 16
     net = X.Cnn(max_batch=N)
     p = OC.init_params(0)
     p = [q + (0.01 if q.ndim == 1 else 0.0) for q in p]
+    p[9] = p[9] + fc1_shift
     net.set_weights(flat(p))
     x = batch(N)
     xt = torch.from_numpy(x.astype(np.float32)).cuda()
@@ -74,7 +81,8 @@ def test_forward_and_gradients_match_oracle():
     errs = [relerr(g[k], rg[k]) for k in range(12)]
     for k in range(12):
         log("grad", k, OC.shapes()[k], "rel err", errs[k])
-    assert max(errs) <= 1e-2, errs
+    assert max(errs[8:]) <= 5e-3, errs
+    assert max(errs[:8]) <= conv_tol, errs
     # one Adam step (t = 1) from the oracle's gradients: p - lr g/(|g| + eps),
     # compared where the gradient is not near zero (its sign decides there)
     newp = unflat(net.get_weights())

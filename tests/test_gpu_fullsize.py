@@ -110,3 +110,32 @@ def test_fullsize_fp32_prefix(inputs):
     assert e0 <= max(1e-5, 20 * s0)
     assert e1 <= max(1e-5, 20 * s1)
     slam.close()
+
+
+def test_fullsize_fp64_autotuned_launch_shapes(inputs):
+    """The launch shapes the benchmark may choose (autotuned raycast tile, ICP
+    and fusion grids) leave the FP64 results on the oracle: counts exact,
+    poses and derivatives within 1e-10."""
+    from paper_2405_02187_amd import autotune as AT
+    p, _, T0 = inputs
+    n = 1 + AT.frames_needed(1) + 1
+    seq = sg.make_sequence(p, n_frames=n)
+    d64 = seq.depths().astype(np.float64)
+    ref = O.run_sequence(O.config(p), O.seed(1, O.P_PHI_X, h=H20), d64, T0)
+    cfg = X.config_from_preset(p, prec=X.C128, max_frames=n)
+    slam = X.Slam(cfg, X.Perturbation([(X.P_PHI_X, H20)]), T0)
+    dev = torch_dev(d64, np.float64)
+    slam.step(dev[0])
+    shapes = AT.tune(slam, [dev[k] for k in range(1, n - 1)], reps=3, fuse_frames_per_grid=1)
+    log("autotuned shapes", shapes)
+    slam.step(dev[n - 1])
+    cnt = slam.get(X.F_COUNTERS)
+    st = ref["stats"]
+    assert np.array_equal(cnt[:, 1], st[:, 3].astype(int))
+    assert np.array_equal(cnt[:, 2], st[:, 4].astype(int))
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
+    P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    e0, e1 = relerr(P[..., 0], ref["poses"][..., 0]), relerr(P[..., 1], ref["poses"][..., 1])
+    log("fullsize fp64 autotuned pose", e0, "derivative", e1)
+    assert e0 <= 1e-10 and e1 <= 1e-10
+    slam.close()
