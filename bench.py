@@ -7,8 +7,12 @@ trajectory at 30 Hz (inputs resident in HBM before timing).  A step is one
 whole frame step: measurement, tracking, fusion and raycast.
 
 Prints one JSON line: frames*directions/s, per-kernel timing from HIP events
-on the library's stream, the roofline of the dominant kernel, and the CPU
-oracle timed on a bounded sample of the same workload.
+on the library's stream, the roofline of the dominant kernel, the CPU oracle
+timed on a bounded sample of the same workload, and the other forms of the
+frame step on the same GPU (FP64-complex single direction, six batched
+directions, 16 directions with a fused 4x4 Hessian at 256^3, 24 uneven
+independent sequences together), each with its derivative error against the
+FP64-complex run where one applies.
 """
 from __future__ import annotations
 
@@ -83,6 +87,94 @@ def cpu_baseline(p, seq, n_ray_stride=32):
                         f"({t['raycast_sample']:.2f}s, scaled x{n_ray_stride}); estimated {total:.1f}s per frame"))
 
 
+def _timed_run(X, torch, cfg, pert, T0, dev, n_warm, n_timed, tan=None, shapes=None):
+    """Steps frames 0..n_warm+n_timed-1; times the last n_timed.  -> (slam, seconds)."""
+    slam = X.Slam(cfg, pert, T0)
+    if shapes:
+        slam.set_launch(**shapes)
+    for k in range(n_warm):
+        slam.step(dev[k], None if tan is None else tan[k])
+    slam.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_warm, n_warm + n_timed):
+        slam.step(dev[k], None if tan is None else tan[k])
+    slam.sync()
+    torch.cuda.synchronize()
+    return slam, time.perf_counter() - t0
+
+
+def _rel(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def forms(X, torch, sg, p1, dev1, T0, poses32, n_warm=5, n_timed=30, multi_cap=None, shapes=None):
+    """The other forms of the frame step on this GPU."""
+    out = {}
+    nf = n_warm + n_timed
+    h32 = 2.0 ** -20
+    # FP64-complex, one direction, on the same frames; the FP32 run's error against it
+    cfg = X.config_from_preset(p1, prec=X.C128, max_frames=nf)
+    dev64 = dev1[:nf].to(torch.float64)
+    slam, dt = _timed_run(X, torch, cfg, X.Perturbation([(X.P_PHI_X, 1e-20)]), T0, dev64, n_warm, n_timed,
+                          shapes=shapes)
+    P64 = slam.get(X.F_POSES)
+    slam.close()
+    e_pose = _rel(poses32[:nf, 0], P64[:, 0])
+    e_grad = _rel(poses32[:nf, 1] / h32, P64[:, 1] / 1e-20)
+    out["fp64_1dir"] = dict(value=n_timed / dt, unit="frames·directions/s", frames=n_timed,
+                            workload="seq640x480_tsdf512_1cm_fp64complex_1dir")
+    out["fp32_vs_fp64_over_first_frames"] = dict(frames=nf, pose_rel_err=e_pose, grad_rel_err=e_grad)
+    del dev64
+    # six initial-pose directions in one launch vs one at a time
+    cfg = X.config_from_preset(p1, prec=X.C64, max_frames=nf)
+    slam, dt = _timed_run(X, torch, cfg, X.Perturbation([(q, h32) for q in range(6)]), T0, dev1, n_warm, n_timed,
+                          shapes=shapes)
+    P6 = slam.get(X.F_POSES)
+    slam.close()
+    out["fp32_6dir_batched"] = dict(value=6 * n_timed / dt, unit="frames·directions/s", frames=n_timed,
+                                    workload="seq640x480_tsdf512_1cm_fp32complex_6dir",
+                                    grad_phi_x_rel_err_vs_1dir=_rel(P6[:, 1], poses32[:nf, 1]))
+    # 16 directions + 4x4 Hessian (10 pairs) in one launch per stage, 256^3 at 2 cm
+    p2 = sg.preset("c2")
+    seq2 = sg.make_sequence(p2, n_frames=nf)
+    d2, t2 = seq2.depths_and_tangents(nf, workers=16)
+    dev2 = torch.from_numpy(d2.astype(np.float32)).to("cuda:0")
+    tan2 = torch.from_numpy(t2.astype(np.float32)).to("cuda:0")
+    hess = [X.P_TRUNC, X.P_WCAP, X.P_FX, X.P_DGATE]
+    order = hess + [q for q in sg.PARAMS16 if q not in hess]
+    cfg = X.config_from_preset(p2, prec=X.C64, max_frames=nf)
+    slam, dt = _timed_run(X, torch, cfg, X.Perturbation([(q, 2.0 ** -16) for q in order], 4), seq2.poses_gt[0],
+                          dev2, n_warm, n_timed, tan=tan2)
+    slam.close()
+    out["fp32_16dir_10pair"] = dict(value=(16 + 10) * n_timed / dt, unit="frames·directions/s", frames=n_timed,
+                                    directions=16, hessian_pairs=10,
+                                    workload="seq640x480_tsdf256_2cm_fp32complex_16dir_4x4hessian")
+    cfg = X.config_from_preset(p2, prec=X.C64, max_frames=nf)
+    slam, dt1 = _timed_run(X, torch, cfg, X.Perturbation([(X.P_TRUNC, 2.0 ** -16)]), seq2.poses_gt[0],
+                           dev2, n_warm, n_timed)
+    slam.close()
+    out["fp32_16dir_10pair"]["same_workload_1dir_value"] = n_timed / dt1
+    del dev2, tan2
+    # 24 uneven independent sequences together
+    from paper_2405_02187_amd import multi as M
+    t0 = time.perf_counter()
+    insts = M.make_instances(sg.instance_presets(24), frame_cap=multi_cap)
+    log(f"multi-instance inputs in {time.perf_counter() - t0:.1f}s")
+    res = M.run_batch(insts, n_streams=8)
+    lost = int(sum(s.get(X.F_COUNTERS)[:, 0].sum() for s in res["slams"]))
+    for s_ in res["slams"]:
+        s_.close()
+    out["multi_instance_24"] = dict(value=res["value"], unit="frames·directions/s", frames=res["frames"],
+                                    frames_x_directions=res["frames_x_dirs"], wall_s=res["wall_s"],
+                                    streams=res["streams"], latency_ms=res["latency_ms"], lost_frames=lost,
+                                    workload="24 sequences: 128^3-384^3 TSDF at 1-2 cm, 320x240 or 640x480, "
+                                             "60-400 frames, 1-6 directions each, FP32-complex")
+    del insts
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +183,9 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--no-forms", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shapes")
+    ap.add_argument("--multi-cap", type=int, default=None, help="cap frames per multi-instance sequence")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -116,7 +211,7 @@ def main():
     assert n_frames <= p["n_frames"], "the sequence has 500 frames"
     t0 = time.perf_counter()
     seq = sg.make_sequence(p, n_frames=n_frames)
-    depths = seq.depths()
+    depths = seq.depths(workers=16)
     log(f"generated {n_frames} frames in {time.perf_counter() - t0:.1f}s")
     prec = X.C64 if args.prec == "c64" else X.C128
     tdtype = torch.float32 if prec == X.C64 else torch.float64
@@ -126,7 +221,18 @@ def main():
     pert = X.Perturbation([(X.P_PHI_X, h)])
     slam = X.Slam(cfg, pert, seq.poses_gt[0])
 
-    for k in range(args.warmup):
+    from paper_2405_02187_amd import autotune as AT
+    shapes = None
+    if not args.no_autotune and args.warmup >= 2 + AT.frames_needed(2):
+        slam.step(dev[0])
+        t0 = time.perf_counter()
+        tuned = AT.tune(slam, [dev[k] for k in range(1, 1 + AT.frames_needed(2))], reps=20)
+        shapes = {k: tuned[k] for k in ("ray_tile", "icp_blocks", "fuse_blocks")}
+        log(f"autotuned in {time.perf_counter() - t0:.1f}s: {tuned}")
+        k_start = 1 + AT.frames_needed(2)
+    else:
+        k_start = 0
+    for k in range(k_start, args.warmup):
         slam.step(dev[k])
     slam.sync()
     torch.cuda.synchronize()
@@ -194,8 +300,13 @@ def main():
         "roofline": roofline,
         "kernels": per, "kernel_rooflines": kern, "per_frame": extra,
         "lost_frames": int(cnt[:, 0].sum()),
+        "launch_shapes": slam.get_launch(),
     }
+    poses32 = slam.get(X.F_POSES)
     slam.close()
+    if not args.no_forms and prec == X.C64:
+        out["forms"] = forms(X, torch, sg, p, dev, seq.poses_gt[0], poses32, multi_cap=args.multi_cap,
+                             shapes=shapes)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, seq)

@@ -36,7 +36,15 @@ def _run(cmd):
     return r
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(obj: str, deps: list) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every unit (incremental=True: only units older than a source)."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     units = [(os.path.join(CSRC, "api.cpp"), os.path.join(BUILD, "api.o"), ["-x", "hip"]),
@@ -44,7 +52,13 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for T, D, Q, name in combos():
         units.append((os.path.join(CSRC, "inst.hip"), os.path.join(BUILD, f"inst_{name}.o"),
                       [f"-DXS_T={T}", f"-DXS_D={D}", f"-DXS_Q={Q}", f"-DXS_NAME={name}"]))
-    cmds = [["hipcc", *FLAGS, *extra, "-c", src, "-o", obj] for src, obj, extra in units]
+    hdr = os.path.join(HERE, "..", "include", "xslam.h")
+    eng = [os.path.join(CSRC, f) for f in ("jet.hpp", "common.hpp", "kernels.hpp", "engine.hpp", "ctx.hpp",
+                                           "inst.hip")] + [hdr]
+    deps = {"api.cpp": eng + [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "combos.hpp")],
+            "inst.hip": eng, "cnn.hip": [os.path.join(CSRC, "cnn.hip"), hdr]}
+    cmds = [["hipcc", *FLAGS, *extra, "-c", src, "-o", obj] for src, obj, extra in units
+            if not incremental or _stale(obj, deps[os.path.basename(src)])]
     with ThreadPoolExecutor(jobs) as ex:
         for r in ex.map(_run, cmds):
             if verbose and (r.stdout or r.stderr):
@@ -56,4 +70,4 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

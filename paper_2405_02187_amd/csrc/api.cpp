@@ -291,6 +291,83 @@ int xslam_sync(xslam_ctx ctx) {
   return XSLAM_OK;
 }
 
+struct xslam_batch_s {
+  std::vector<xslam_ctx> ctx;
+  std::vector<hipEvent_t> e0, e1;
+  std::vector<char> ran;
+  int32_t last_index = -1;
+};
+
+int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out) {
+  if (!ctxs || n < 1 || !out) return XSLAM_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !ctxs[i]->eng) return XSLAM_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return XSLAM_ERR_ARG;
+  }
+  auto* b = new xslam_batch_s;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->e0.assign(n, nullptr);
+  b->e1.assign(n, nullptr);
+  b->ran.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (hipSetDevice(ctxs[i]->device) != hipSuccess || hipEventCreate(&b->e0[i]) != hipSuccess ||
+        hipEventCreate(&b->e1[i]) != hipSuccess) {
+      for (auto e : b->e0) if (e) hipEventDestroy(e);
+      for (auto e : b->e1) if (e) hipEventDestroy(e);
+      delete b;
+      return XSLAM_ERR_HIP;
+    }
+  }
+  *out = b;
+  return XSLAM_OK;
+}
+
+int xslam_batch_step(xslam_batch b, const void* const* depths, const void* const* depth_dots,
+                     const int32_t* active) {
+  if (!b || !depths) return XSLAM_ERR_ARG;
+  b->last_index = -1;
+  const int n = int(b->ctx.size());
+  for (int i = 0; i < n; ++i) {
+    b->ran[i] = 0;
+    if (active && !active[i]) continue;
+    xslam_ctx c = b->ctx[i];
+    hipEventRecord(b->e0[i], c->stream);
+    int rc = c->eng->step(depths[i], depth_dots ? depth_dots[i] : nullptr);
+    hipEventRecord(b->e1[i], c->stream);
+    if (rc) {
+      b->last_index = i;
+      return rc;
+    }
+    b->ran[i] = 1;
+  }
+  return XSLAM_OK;
+}
+
+int xslam_batch_latency(xslam_batch b, float* ms_out) {
+  if (!b || !ms_out) return XSLAM_ERR_ARG;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    ms_out[i] = -1.f;
+    if (!b->ran[i]) continue;
+    if (hipEventSynchronize(b->e1[i]) != hipSuccess) return XSLAM_ERR_HIP;
+    if (hipEventElapsedTime(&ms_out[i], b->e0[i], b->e1[i]) != hipSuccess) return XSLAM_ERR_HIP;
+  }
+  return XSLAM_OK;
+}
+
+int32_t xslam_batch_last_index(xslam_batch b) { return b ? b->last_index : -1; }
+
+int xslam_batch_destroy(xslam_batch b) {
+  if (!b) return XSLAM_ERR_ARG;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    if (b->ran[i]) hipEventSynchronize(b->e1[i]);
+    hipEventDestroy(b->e0[i]);
+    hipEventDestroy(b->e1[i]);
+  }
+  delete b;
+  return XSLAM_OK;
+}
+
 const char* xslam_last_error(xslam_ctx ctx) {
   if (!ctx) return "null context";
   return ctx->err.c_str();

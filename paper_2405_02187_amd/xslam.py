@@ -98,6 +98,11 @@ def lib():
             "xslam_set_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
             "xslam_get_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
             "xslam_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(xslam_launch), dp]),
+            "xslam_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, C.POINTER(vp)]),
+            "xslam_batch_step": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int32)]),
+            "xslam_batch_latency": (C.c_int, [vp, C.POINTER(C.c_float)]),
+            "xslam_batch_last_index": (C.c_int32, [vp]),
+            "xslam_batch_destroy": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -110,7 +115,8 @@ EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xs
            "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
            "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
-           "xslam_autotune"]
+           "xslam_autotune", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
+           "xslam_batch_last_index", "xslam_batch_destroy"]
 
 
 class XslamError(RuntimeError):
@@ -397,6 +403,55 @@ def _cnn_lib():
             f.restype, f.argtypes = res, args
         L._cnn_sig = True
     return L
+
+
+class Batch:
+    """Independent contexts advanced together, one frame each per step (each on
+    the stream it was created with)."""
+
+    def __init__(self, slams):
+        self.slams = list(slams)
+        n = len(self.slams)
+        arr = (C.c_void_p * n)(*[s.h for s in self.slams])
+        h = C.c_void_p()
+        rc = lib().xslam_batch_create(arr, n, C.byref(h))
+        if rc != 0:
+            raise XslamError(f"xslam_batch_create: error {rc}")
+        self.h = h
+        self.n = n
+
+    def step(self, depths, depth_dots=None, active=None):
+        """depths / depth_dots: per context a device tensor or None."""
+        n = self.n
+        d = (C.c_void_p * n)(*[None if x is None else x.data_ptr() for x in depths])
+        dd = None
+        if depth_dots is not None:
+            dd = (C.c_void_p * n)(*[None if x is None else x.data_ptr() for x in depth_dots])
+        act = None if active is None else (C.c_int32 * n)(*[1 if a else 0 for a in active])
+        rc = lib().xslam_batch_step(self.h, d, dd, act)
+        if rc < 0:
+            i = lib().xslam_batch_last_index(self.h)
+            msg = lib().xslam_last_error(self.slams[i].h) if i >= 0 else b""
+            raise XslamError(f"batch step: context {i}: error {rc}: {msg.decode() if msg else ''}")
+        return rc
+
+    def latency(self):
+        ms = np.zeros(self.n, dtype=np.float32)
+        rc = lib().xslam_batch_latency(self.h, ms.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != 0:
+            raise XslamError(f"batch latency: error {rc}")
+        return ms
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().xslam_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Cnn:

@@ -330,12 +330,29 @@ class Sequence:
                 return np.stack(list(ex.map(_render_one, args, chunksize=4)))
         return np.stack([self.frame(k, noise)[0] for k in range(n)])
 
+    def depths_and_tangents(self, n: int | None = None, workers: int = 1):
+        """Noisy depth frames 0..n-1 and their noise-scale tangents."""
+        n = len(self) if n is None else n
+        if workers > 1 and n > 1:
+            from concurrent.futures import ProcessPoolExecutor
+            args = [(self.scene, self.poses_gt[k], self.camera, self.seed, k, True, self.sigma2,
+                     self.depth_dtype, True) for k in range(n)]
+            with ProcessPoolExecutor(workers) as ex:
+                out = list(ex.map(_render_one, args, chunksize=4))
+        else:
+            out = [self.frame(k) for k in range(n)]
+        return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
+
 
 def _render_one(a):
-    scene, pose, c, seed, k, noise, sigma2, dt = a
+    scene, pose, c, seed, k, noise, sigma2, dt = a[:8]
+    with_tangent = len(a) > 8 and a[8]
     z = render_depth(scene, pose, c["width"], c["height"], c["fx"], c["fy"], c["cx"], c["cy"])
-    d = add_noise(z, seed, k, sigma2)[0] if noise else z
-    return d.astype(dt)
+    if noise:
+        d, tan = add_noise(z, seed, k, sigma2)
+    else:
+        d, tan = z, np.zeros_like(z)
+    return (d.astype(dt), tan.astype(dt)) if with_tangent else d.astype(dt)
 
 
 PRESETS = {
@@ -355,6 +372,44 @@ PRESETS = {
                n_frames=300, traj="spline", prec="c64",
                icp=dict(iters=(10, 5, 4), dgate=0.1, agate_deg=20.0), h=2.0 ** -20),
 }
+
+
+# The 16 parameters of the batched-direction workload: initial pose (6),
+# truncation, weight cap, ICP distance and angle gates, the three per-level ICP
+# step weights, the depth-noise scale, fx, fy (library parameter ids).
+PARAMS16 = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 17, 13, 14)
+
+
+def instance_presets(n: int = 24, seed0: int = 100) -> list:
+    """Uneven independent sequences: TSDF of 128^3..384^3 voxels at 1 or 2 cm
+    (cubes below 2.56 m are redrawn: the scene generator places its objects in
+    the central 70% of a cube of at least that size), 320x240 (fx=fy=262.5) or
+    640x480 (fx=fy=525) depth, 60..400 frames, 1..6 complex directions drawn
+    from PARAMS16.  Instance i uses scene seed seed0 + i; the draws come from
+    PCG64 stream SeedSequence(seed0 + i, spawn_key=(3,)).  Cubes of at least
+    3.84 m use the spline trajectory, smaller ones the 1.5 m circle."""
+    out = []
+    for i in range(n):
+        seed = seed0 + i
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(3,))))
+        while True:
+            dim = int(rng.choice([128, 192, 256, 320, 384]))
+            voxel = float(rng.choice([0.01, 0.02]))
+            if dim * voxel >= 2.56 - 1e-9:
+                break
+        if rng.random() < 0.5:
+            cam = dict(width=320, height=240, fx=262.5, fy=262.5, cx=159.5, cy=119.5)
+        else:
+            cam = dict(width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5)
+        frames = int(rng.integers(60, 401))
+        nd = int(rng.integers(1, 7))
+        dirs = [int(x) for x in rng.choice(PARAMS16, size=nd, replace=False)]
+        L = dim * voxel
+        out.append(dict(seed=seed, L=L, dim=dim, voxel=voxel, trunc=0.06, wcap=64.0, camera=cam,
+                        n_frames=frames, traj="spline" if L >= 3.84 - 1e-9 else "circle", radius=1.5,
+                        prec="c64", icp=dict(iters=(10, 5, 4), dgate=0.1, agate_deg=20.0), h=2.0 ** -20,
+                        dirs=dirs))
+    return out
 
 
 def preset(name: str, **overrides) -> dict:
