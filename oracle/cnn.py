@@ -12,8 +12,9 @@ benchmark's CPU baseline use it.
 
 ``quant=bf16_round`` (forward and backward) rounds to bfloat16 at the points
 where a bf16 implementation stores values: the network input, the
-convolution weights and biases, every post-ReLU activation, and the gradient
-with respect to every convolution output.  Arithmetic stays FP64.  The ReLU
+convolution weights, every post-ReLU activation, and the gradient with
+respect to every convolution output (biases and the fully connected layers
+stay in full precision).  Arithmetic stays FP64.  The ReLU
 masks are decisions taken by floating point, so a bf16 implementation is
 compared with this mode (both take the masks from bf16-stored values); with
 ``quant=None`` everything is FP64.
@@ -110,7 +111,7 @@ def forward(params, x, quant=None):
     h = q(x)
     acts = [h]
     pre = []
-    convw = [(q(params[2 * i]), q(params[2 * i + 1])) for i in range(4)]
+    convw = [(q(params[2 * i]), params[2 * i + 1]) for i in range(4)]
     for i in range(4):
         z = conv_s2(h, *convw[i])
         pre.append(z)

@@ -44,19 +44,20 @@ def test_param_count_matches_oracle():
     assert X.Cnn(max_batch=4).n_params == OC.n_params()
 
 
-@pytest.mark.parametrize("fc1_shift,conv_tol", [(5.0, 5e-3), (0.0, 5e-2)])
+@pytest.mark.parametrize("fc1_shift,conv_tol", [(5.0, 2e-2), (0.0, 5e-2)])
 def test_forward_and_gradients_match_oracle(fc1_shift, conv_tol):
-    """Against the oracle in bf16-storage mode (weights, activations and
-    activation gradients rounded to bf16 where the kernels store them, so the
-    convolution ReLU masks are decided on the same stored values): what is
-    left is FP32 versus FP64 accumulation and the rare bf16 rounding it tips
-    over (forward 2e-3, head gradients 5e-3).  The hidden fully connected
-    layer decides its ReLU on FP32 (kernel) versus FP64 (oracle) values that
-    differ by ~1e-3; a unit within that margin of zero flips the gradient of
-    its whole sample.  With its bias shifted by +5 every unit is active and
-    the convolution gradients agree within 5e-3; with the plain init a few
-    flips move them by up to a few percent (5e-2).  The all-FP64 network is
-    the reference for the quantisation error itself (3e-2 on the output)."""
+    """Against the oracle in bf16-storage mode (input, weights, activations
+    and activation gradients rounded to bf16 where the kernels store them, so
+    the convolution ReLU masks are decided on the same stored values): what
+    is left is FP32 versus FP64 accumulation and the bf16 roundings it tips
+    over.  Those are amplified in the convolution gradients: in the oracle
+    itself, pre-activations jittered by 1e-6 relative move them by up to
+    1.2%, so they are held to 2e-2 (forward 2e-3, head gradients 5e-3).  The
+    hidden fully connected layer decides its ReLU on values that differ by
+    ~1e-3; with its bias shifted by +5 every unit is active, with the plain
+    init a few units flip and move the convolution gradients by up to a few
+    percent (5e-2).  The all-FP64 network is the reference for the
+    quantisation error itself (3e-2 on the output)."""
     N = 16
     net = X.Cnn(max_batch=N)
     p = OC.init_params(0)
