@@ -191,11 +191,16 @@ int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out
 int xslam_get(xslam_ctx ctx, int32_t field, void* dst, size_t bytes);
 int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
 
-/* Per-kernel timing with HIP events on the context stream (0 off, 1 on);
- * xslam_kernel_times writes accumulated milliseconds and launch counts for
- * kernel classes 0 measure, 1 icp, 2 fuse, 3 raycast, 4 other. */
+/* Per-kernel timing with HIP events on the context stream (0 off, 1 on;
+ * while on, tracked frames launch eagerly instead of through the graph);
+ * xslam_kernel_times waits for the stream and writes accumulated
+ * milliseconds and launch counts for 8 kernel classes: 0 measurement
+ * (bilateral, pyramid, vertex/normal maps), 1 k_icp (association and
+ * per-workgroup sums), 2 k_fuse, 3 k_raymarch, 4 other small kernels, 5
+ * k_icp_finish (cross-workgroup sum, solve, pose update), 6 k_rayhit, 7
+ * k_brick_cull. */
 int xslam_set_timing(xslam_ctx ctx, int32_t on);
-int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]);
+int xslam_kernel_times(xslam_ctx ctx, double ms_out[8], int64_t launches_out[8]);
 
 /* ---- launch shapes and the autotuner ----------------------------------------
  * Launch shapes that do not change any result bit except the order of the
@@ -227,6 +232,30 @@ int xslam_get_launch(xslam_ctx ctx, xslam_launch* out);
  * receives the shapes in use afterwards; ms_out (optional, 4 doubles) the
  * best mean times (ms) of raycast, ICP level 0, level 1 and level 2. */
 int xslam_autotune(xslam_ctx ctx, int32_t reps, xslam_launch* best, double* ms_out);
+
+/* ---- several independent sequences (multi-instance) -----------------------
+ * A batch advances independent contexts (each its own sequence, volume,
+ * image size and perturbation) by one frame each per call.  Every context's
+ * frame step is enqueued on the stream it was created with; contexts created
+ * on distinct streams run concurrently on the device, so small volumes and
+ * the latency-bound ICP passes of one sequence overlap with the work of the
+ * others.  Per context, HIP events around its frame give the frame's latency
+ * on the device under that load.  The batch does not own the contexts: they
+ * must outlive it.  Errors: XSLAM_ERR_ARG (NULL, n < 1, a context twice);
+ * xslam_batch_step returns the first failing context's code, and its index
+ * is in xslam_batch_last_index. */
+typedef struct xslam_batch_s* xslam_batch;
+int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out);
+/* depths[i] / depth_dots[i]: the frame of context i (device pointers, layout
+ * as in xslam_step; depth_dots may be NULL); active (optional, n flags):
+ * contexts with 0 are skipped (finished sequences). */
+int xslam_batch_step(xslam_batch b, const void* const* depths, const void* const* depth_dots,
+                     const int32_t* active);
+/* waits for the last step of every context; ms_out[i] = device time from
+ * the start to the end of context i's last frame step (-1 if it was skipped) */
+int xslam_batch_latency(xslam_batch b, float* ms_out);
+int32_t xslam_batch_last_index(xslam_batch b);
+int xslam_batch_destroy(xslam_batch b);
 
 /* ---- learned ICP initialiser (a systems form beyond the paper) -------------
  * A CNN proposes the ICP initial pose increment from coarse maps: input

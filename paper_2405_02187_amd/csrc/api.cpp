@@ -232,7 +232,7 @@ int xslam_set_timing(xslam_ctx ctx, int32_t on) {
   return XSLAM_OK;
 }
 
-int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5]) {
+int xslam_kernel_times(xslam_ctx ctx, double ms_out[8], int64_t launches_out[8]) {
   XS_CTX_CHECK(ctx);
   Timer& t = ctx->timer;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return XSLAM_ERR_HIP;
@@ -244,7 +244,7 @@ int xslam_kernel_times(xslam_ctx ctx, double ms_out[5], int64_t launches_out[5])
   }
   t.pending.clear();
   t.next = 0;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < Timer::kClasses; ++i) {
     if (ms_out) ms_out[i] = t.ms[i];
     if (launches_out) launches_out[i] = t.launches[i];
   }

@@ -33,8 +33,9 @@ struct Timer {
   std::vector<hipEvent_t> pool;
   size_t next = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  double ms[5] = {0, 0, 0, 0, 0};
-  int64_t launches[5] = {0, 0, 0, 0, 0};
+  static constexpr int kClasses = 8;
+  double ms[kClasses] = {};
+  int64_t launches[kClasses] = {};
 };
 
 }  // namespace xs

@@ -160,7 +160,8 @@ struct Engine : EngineBase {
     return XSLAM_OK;
   }
 
-  // kernel launch with optional event timing; cls: 0 measure 1 icp 2 fuse 3 raycast 4 other
+  // kernel launch with optional event timing; cls: 0 measurement, 1 k_icp, 2 k_fuse, 3 k_raymarch,
+  // 4 other, 5 k_icp_finish, 6 k_rayhit, 7 k_brick_cull
   template <typename F> int launch(int cls, const char* what, F&& f) {
     Timer& tm = C->timer;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -329,7 +330,7 @@ struct Engine : EngineBase {
       hipLaunchKernelGGL((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
     });
     if (rc) return rc;
-    return launch(1, "icp_finish", [&] {
+    return launch(5, "icp_finish", [&] {
       hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kIcpThreads), 0, C->stream, a, blocks);
     });
   }
@@ -513,7 +514,7 @@ struct Engine : EngineBase {
            hipLaunchKernelGGL(k_tile_zmax<T>, dim3(ntx, nty), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax);
          })))
       return rc;
-    if ((rc = launch(4, "brick_cull", [&] {
+    if ((rc = launch(7, "brick_cull", [&] {
            hipLaunchKernelGGL((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
                               tzmax, nbrick, blist, bcount, lost);
          })))
@@ -551,7 +552,7 @@ struct Engine : EngineBase {
       hipLaunchKernelGGL((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
     });
     if (rc) return rc;
-    rc = launch(3, "rayhit", [&] {
+    rc = launch(6, "rayhit", [&] {
       hipLaunchKernelGGL((k_rayhit<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, bracket, o, rhits);
     });
     if (rc) return rc;

@@ -14,6 +14,17 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { typedef float2 type; };
 template <> struct Vec2<double> { typedef double2 type; };
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
+// by linear workgroup id.  xcd_remap turns the physical id into a logical one
+// such that every XCD receives a contiguous range of logical ids, so that
+// neighbouring pixels (and the map rows or voxels they share) meet in the same
+// L2.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int id, int n) {
+  const int x = id % kXcds, k = id / kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // A1. depth promotion (eq. "csfd_depth") and bilateral filter
 // ---------------------------------------------------------------------------
@@ -331,6 +342,65 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
 // Few components: per-thread sums over a few pixels, then an FP64 block tree.
 // Many components: every pixel's terms are reduced across the wave at once
 // (FP64) into per-wave LDS accumulators, so no thread holds 27 NC sums.
+// One workgroup: fixed-order FP64 sum of the per-workgroup partials, then
+// (unless only the sums are wanted) the FP64 solve, relaxation and SE(3)
+// update.  gsum: [4][NS] and fin: [NS] in LDS.
+template <typename T, int D, int Q>
+__device__ void icp_finish_block(const IcpArgs<T, D, Q>& g, int nblocks, double (*gsum)[IcpSize<D, Q>::NS],
+                                 double* fin) {
+  constexpr int NC = Jet<T, D, Q>::N;
+  constexpr int NS = IcpSize<D, Q>::NS;
+  // Each component is summed over the blocks in the same order whatever the
+  // number of components (so real parts do not depend on D, Q): four
+  // interleaved groups of blocks (b mod 4), eight running sums each, combined
+  // in a fixed tree.  Work items (component, group) are spread over threads.
+  {
+    constexpr int G = 4;
+    const unsigned B = nblocks;
+    for (int item = threadIdx.x; item < NS * G; item += kIcpThreads) {
+      const int k = item / G, grp = item % G;
+      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      unsigned b = grp;
+      for (; b + 7 * G < B; b += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
+      }
+      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
+      gsum[grp][k] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NS; k += kIcpThreads) fin[k] = (gsum[0][k] + gsum[1][k]) + (gsum[2][k] + gsum[3][k]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const int cnt = int(fin[27 * NC]);
+  int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
+  if (!g.do_solve) {
+    for (int k = 0; k < NS; ++k) g.sums_out[k] = fin[k];
+    return;
+  }
+  crow[3] += cnt;
+  crow[4] = cnt;
+  if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
+  Jet<double, D, Q> dx[6];
+  if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
+    *g.lost = 1;
+    crow[0] = 1;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) dx[a] = g.omega * dx[a];
+  {
+    double nn = 0.0;
+    for (int a = 0; a < 6; ++a) nn += dx[a].re() * dx[a].re();
+    if (crow[32] == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
+  }
+  MPose<D, Q> E = se3_exp<D, Q>(dx);
+  MPose<D, Q> Pn = pose_mul(E, *g.Pcur);
+  *g.Pcur = Pn;
+  *g.Kcur = to_kpose<T, double>(Pn);
+}
+
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
   using J = Jet<T, D, Q>;
@@ -346,12 +416,17 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   const J fx = kp.fx * sc, fy = kp.fy * sc, cx = kp.cx * sc, cy = kp.cy * sc;
   const size_t n = size_t(g.W) * g.H;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // each logical workgroup takes a contiguous run of pixels (a multiple of the
+  // workgroup size); with the XCD remap every L2 sees one band of the image
+  const size_t chunk = (n + size_t(gridDim.x) * kIcpThreads - 1) / (size_t(gridDim.x) * kIcpThreads) * kIcpThreads;
+  const size_t p0 = size_t(xcd_remap(blockIdx.x, gridDim.x)) * chunk;
+  const size_t p1 = p0 + chunk < n ? p0 + chunk : n;
 
   if constexpr (kRegAcc) {
     T acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0;
-    for (size_t i = size_t(blockIdx.x) * kIcpThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kIcpThreads) {
+    for (size_t i = p0 + threadIdx.x; i < p1; i += kIcpThreads) {
       J jac[6], r;
       if (!icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r)) continue;
       int k = 0;
@@ -389,10 +464,10 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 #pragma unroll
     for (int k = 0; k < 29; ++k) racc[k] = 0;
     for (int k = lane; k < NS; k += 64) red[wv][k] = 0.0;
-    for (size_t base = size_t(blockIdx.x) * kIcpThreads; base < n; base += size_t(gridDim.x) * kIcpThreads) {
+    for (size_t base = p0; base < p1; base += kIcpThreads) {
       const size_t i = base + threadIdx.x;
       J jac[6], r;
-      const bool ok = i < n && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
+      const bool ok = i < p1 && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
       if (!ok) {
         r = jzero<J>();
 #pragma unroll
@@ -441,65 +516,18 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   }
 }
 
-// One block: fixed-order FP64 sum of the per-block partials, then (unless
-// only the sums are wanted) the FP64 solve, relaxation, SE(3) update.
+// One workgroup after k_icp (a kernel boundary makes every partial visible to
+// it without device-wide fences in k_icp, whose cross-XCD L2 write-back cost
+// more than the launch it would save).
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(kIcpThreads) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
-  constexpr int NC = Jet<T, D, Q>::N;
   constexpr int NS = IcpSize<D, Q>::NS;
+  __shared__ double gsum[4][NS];
   __shared__ double fin[NS];
   if (*g.lost) return;
-  // Each component is summed over the blocks in the same order whatever the
-  // number of components (so real parts do not depend on D, Q): four
-  // interleaved groups of blocks (b mod 4), eight running sums each, combined
-  // in a fixed tree.  Work items (component, group) are spread over threads.
-  {
-    constexpr int G = 4;
-    __shared__ double gsum[G][NS];
-    const unsigned B = nblocks;
-    for (int item = threadIdx.x; item < NS * G; item += kIcpThreads) {
-      const int k = item / G, grp = item % G;
-      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      unsigned b = grp;
-      for (; b + 7 * G < B; b += 8 * G) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
-      }
-      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
-      gsum[grp][k] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < NS; k += kIcpThreads) fin[k] = (gsum[0][k] + gsum[1][k]) + (gsum[2][k] + gsum[3][k]);
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const int cnt = int(fin[27 * NC]);
-  int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
-  if (!g.do_solve) {
-    for (int k = 0; k < NS; ++k) g.sums_out[k] = fin[k];
-    return;
-  }
-  crow[3] += cnt;
-  crow[4] = cnt;
-  if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
-  Jet<double, D, Q> dx[6];
-  if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
-    *g.lost = 1;
-    crow[0] = 1;
-    return;
-  }
-#pragma unroll
-  for (int a = 0; a < 6; ++a) dx[a] = g.omega * dx[a];
-  {
-    double nn = 0.0;
-    for (int a = 0; a < 6; ++a) nn += dx[a].re() * dx[a].re();
-    if (crow[32] == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
-  }
-  MPose<D, Q> E = se3_exp<D, Q>(dx);
-  MPose<D, Q> Pn = pose_mul(E, *g.Pcur);
-  *g.Pcur = Pn;
-  *g.Kcur = to_kpose<T, double>(Pn);
+  icp_finish_block<T, D, Q>(g, nblocks, gsum, fin);
 }
+
 
 // start of tracking for frame k >= 1: shift the pose history and set the
 // initial estimate (previous pose, or constant velocity T1 T2^-1 T1)
@@ -907,7 +935,8 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
                                                   const uint8_t* __restrict__ flags,
                                                   typename Vec2<T>::type* __restrict__ bracket,
                                                   int* __restrict__ block_samples) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int tile = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int x = (tile % gridDim.x) * blockDim.x + threadIdx.x, y = (tile / gridDim.x) * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   int nsamp = 0;
   if (x < W && y < H) {
@@ -983,7 +1012,8 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
                                                 const typename Vec2<T>::type* __restrict__ bracket,
                                                 MapsOut<T, D, Q> out, int* __restrict__ block_hits) {
   using J = Jet<T, D, Q>;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int tile = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int x = (tile % gridDim.x) * blockDim.x + threadIdx.x, y = (tile / gridDim.x) * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   const bool inside = x < W && y < H;
   bool ok = false;

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libxslam.so")
 OK, WARN_TRACK_LOST = 0, 1
 ERR_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 C64, C128 = 0, 1
+# kernel classes of Slam.kernel_times()
+TIMER_CLASSES = ("measure", "k_icp", "k_fuse", "k_raymarch", "other", "k_icp_finish", "k_rayhit", "k_brick_cull")
+N_TIMER_CLASSES = len(TIMER_CLASSES)
 (P_PHI_X, P_PHI_Y, P_PHI_Z, P_RHO_X, P_RHO_Y, P_RHO_Z, P_TRUNC, P_WCAP, P_DGATE, P_AGATE,
  P_ICPW0, P_ICPW1, P_ICPW2, P_FX, P_FY, P_CX, P_CY, P_DEPTH) = range(18)
 (F_POSE, F_POSES, F_TSDF, F_WEIGHT, F_VMAP, F_NMAP, F_ZMAP, F_MVALID, F_MEAS_DEPTH, F_MEAS_V,
@@ -302,8 +305,8 @@ class Slam:
         return self._check(lib().xslam_set_timing(self.h, 1 if on else 0))
 
     def kernel_times(self):
-        ms = np.zeros(5)
-        n = np.zeros(5, dtype=np.int64)
+        ms = np.zeros(N_TIMER_CLASSES)
+        n = np.zeros(N_TIMER_CLASSES, dtype=np.int64)
         self._check(lib().xslam_kernel_times(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
                                              n.ctypes.data_as(C.POINTER(C.c_int64))))
         return ms, n
