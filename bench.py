@@ -87,6 +87,22 @@ def cpu_baseline(p, seq, n_ray_stride=32):
                         f"({t['raycast_sample']:.2f}s, scaled x{n_ray_stride}); estimated {total:.1f}s per frame"))
 
 
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when the
+    kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2405_02187_amd", "csrc", "kernels.hpp")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for f in glob.glob(os.path.join(ROOT, "profiles", "pmc_traffic_*.md")):
+        for m in re.finditer(r"traffic (\S+) bytes_per_launch=(\d+) kernels_sha256_16=([0-9a-f]+)", open(f).read()):
+            if m.group(1) == kernel and m.group(3) == h:
+                return float(m.group(2))
+    return None
+
+
 def _timed_run(X, torch, cfg, pert, T0, dev, n_warm, n_timed, tan=None, shapes=None):
     """Steps frames 0..n_warm+n_timed-1; times the last n_timed.  -> (slam, seconds)."""
     slam = X.Slam(cfg, pert, T0)
@@ -299,7 +315,7 @@ def main():
     cand = {k: v["frame_ms"] for k, v in kern.items() if v["bytes"] is not None}
     dom = max(cand, key=cand.get)
     roofline = {"bound": "hbm", "achieved": kern[dom]["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kern[dom]["frac"], "traffic": None, "kernel": dom,
+                "frac": kern[dom]["frac"], "traffic": pmc_traffic(dom), "kernel": dom,
                 "algorithmic_bytes_per_launch": kern[dom]["bytes"], "avg_launch_us": kern[dom]["us"]}
     extra = {"updated_voxels_per_fuse": fused, "bytes_per_updated_voxel": bpv,
              "fusion_bricks_visited": float(cnt[:, 30].mean()), "raycast_samples": float(cnt[:, 31].mean()),
