@@ -293,8 +293,10 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
                                           Jet<T, D, Q>& r) {
   using J = Jet<T, D, Q>;
   const int W = g.W, H = g.H;
-  if (!g.valid[i]) return false;
+  // the pixel's maps are loaded together with its flag (one memory round trip)
+  const uint8_t vi = g.valid[i];
   const V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+  if (!vi) return false;
   const V3<J> p = pose_apply(Tc, v);
   const V3<J> nr = pose_rotate(Tc, nv);
   const V3<J> xc = pose_apply_inv(Tp, p);
@@ -308,23 +310,34 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
   if (!(fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2))) return false;
   const int i0 = int(fx0), j0 = int(fy0);
   const size_t t0 = size_t(j0) * W + i0, t1 = t0 + 1, t2 = t0 + W, t3 = t2 + 1;
-  if (!(g.validm[t0] && g.validm[t1] && g.validm[t2] && g.validm[t3])) return false;
+  // everything the four taps hold, in flight at once; the nearest tap
+  // floor(u + 1/2) is one of them (u - floor(u + 1e-3) lies in [-1e-3, 1))
+  const uint8_t w0 = g.validm[t0], w1 = g.validm[t1], w2 = g.validm[t2], w3 = g.validm[t3];
+  const T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
+  const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+  const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+  const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+  const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+  if (!(w0 && w1 && w2 && w3)) return false;
   const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
+  const bool inside = (in == i0 || in == i0 + 1) && (jn == j0 || jn == j0 + 1);
+  const int sel = (jn - j0) * 2 + (in - i0);
   const size_t tn = size_t(jn) * W + in;
-  const T zn = g.Zm[tn];
-  const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
+  const T zn = inside ? (sel == 0 ? z0 : sel == 1 ? z1 : sel == 2 ? z2 : z3) : g.Zm[tn];
+  const T disc = fabs(z0 - zn) + fabs(z1 - zn) + fabs(z2 - zn) + fabs(z3 - zn);
   V3<J> q, m;
   if (disc >= kp.disc_delta) {
-    q = vload<J>(g.Vm, n, tn);
-    m = vload<J>(g.Nm, n, tn);
+    if (inside) {
+      q = sel == 0 ? q0 : sel == 1 ? q1 : sel == 2 ? q2 : q3;
+      m = sel == 0 ? m0 : sel == 1 ? m1 : sel == 2 ? m2 : m3;
+    } else {
+      q = vload<J>(g.Vm, n, tn);
+      m = vload<J>(g.Nm, n, tn);
+    }
   } else {
     const J a = ux - fx0, b = uy - fy0;
     const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
-    const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-    const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
     q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
-    const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-    const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
     V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
     m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
   }
@@ -844,7 +857,8 @@ struct MapsOut {
 // then evaluated without loading them, so every sample value is unchanged.
 template <typename T, int D, int Q>
 __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
-                                             const uint8_t* __restrict__ flags, const T v[3], T& out) {
+                                             const uint8_t* __restrict__ flags, const T v[3], T& out,
+                                             int64_t& cached_brick, uint8_t& cached_flag) {
   int i0[3];
   T f[3];
 #pragma unroll
@@ -855,23 +869,30 @@ __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const t
     i0[a] = int(fl);
     f[a] = ga - fl;
   }
-  const uint8_t bf = flags[(int64_t(i0[2] >> 3) * kp.nbr[1] + (i0[1] >> 3)) * kp.nbr[0] + (i0[0] >> 3)];
+  // the flag of the brick holding the lower corner, cached along the ray
+  const int64_t bi = (int64_t(i0[2] >> 3) * kp.nbr[1] + (i0[1] >> 3)) * kp.nbr[0] + (i0[0] >> 3);
+  if (bi != cached_brick) {
+    cached_brick = bi;
+    cached_flag = flags[bi];
+  }
+  const uint8_t bf = cached_flag;
   if (!(bf & 1)) return false;
   T c[8];
   if ((bf & 2) && (i0[0] & 7) != 7 && (i0[1] & 7) != 7 && (i0[2] & 7) != 7) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) c[q] = T(1);
   } else {
+    // all eight records in flight before any is inspected
+    typename Vec2<T>::type r[8];
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+    for (int q = 0; q < 8; ++q) r[q] = rec[vox_index(i0[0] + (q & 1), i0[1] + ((q >> 1) & 1), i0[2] + (q >> 2), kp.nbr)];
+    bool ok = true;
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const auto r = rec[vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr)];
-          if (!(r.y > T(0))) return false;
-          c[dz * 4 + dy * 2 + dx] = r.x;
-        }
+    for (int q = 0; q < 8; ++q) {
+      ok = ok & (r[q].y > T(0));
+      c[q] = r[q].x;
+    }
+    if (!ok) return false;
   }
   const T fx1 = T(1) - f[0], fy1 = T(1) - f[1], fz1 = T(1) - f[2];
   const T c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
@@ -898,20 +919,17 @@ __device__ __forceinline__ bool trilinear_jet(const KParams<T, D, Q>& kp, const 
     f[a] = ga - fl;
   }
   J c[8];
+  bool ok = true;
 #pragma unroll
-  for (int dz = 0; dz < 2; ++dz)
+  for (int k = 0; k < 8; ++k) {
+    const int64_t id = vox_index(i0[0] + (k & 1), i0[1] + ((k >> 1) & 1), i0[2] + (k >> 2), kp.nbr);
+    const auto r = rec[id];
+    ok = ok & (r.y > T(0));
+    c[k].v[0] = r.x;
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 2; ++dx) {
-        const int64_t id = vox_index(i0[0] + dx, i0[1] + dy, i0[2] + dz, kp.nbr);
-        const auto r = rec[id];
-        if (!(r.y > T(0))) return false;
-        J& cj = c[dz * 4 + dy * 2 + dx];
-        cj.v[0] = r.x;
-#pragma unroll
-        for (int q = 1; q < J::N; ++q) cj.v[q] = Ftan[size_t(q - 1) * nvox + id];
-      }
+    for (int q = 1; q < J::N; ++q) c[k].v[q] = Ftan[size_t(q - 1) * nvox + id];
+  }
+  if (!ok) return false;
   const J one = jconst<J>(T(1));
   const J fx1 = one - f[0], fy1 = one - f[1], fz1 = one - f[2];
   const J c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
@@ -973,10 +991,12 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
     bool prev_ok = false;
     T a_prev = 0, f_prev = 0;
     T hit0 = 0, hit1 = T(-1);
+    int64_t cbrick = -1;
+    uint8_t cflag = 0;
     for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it, ++nsamp) {
       const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
       T f;
-      const bool okf = trilinear_re(kp, rec, flags, v, f);
+      const bool okf = trilinear_re(kp, rec, flags, v, f, cbrick, cflag);
       if (!okf) f = 0;
       if (okf && prev_ok) {
         if (f_prev > T(0) && f < T(0)) {
