@@ -10,7 +10,7 @@ constexpr int kMaxDirs = 16;
 constexpr int kBrick = 8;                 // TSDF bricks of 8^3 voxels, 512 contiguous voxels each
 constexpr int kBrickVox = kBrick * kBrick * kBrick;
 constexpr int kIcpThreads = 256;
-constexpr int kMaxIcpBlocks = 512;
+constexpr int kMaxIcpBlocks = 1200;
 constexpr int kCounters = 40;
 constexpr double kTapBias = 1e-3;         // ICP tap choice floor(u + 1e-3), see k_icp
 

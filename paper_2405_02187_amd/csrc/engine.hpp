@@ -331,7 +331,7 @@ struct Engine : EngineBase {
     });
     if (rc) return rc;
     return launch(5, "icp_finish", [&] {
-      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kIcpThreads), 0, C->stream, a, blocks);
+      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kFinishThreads), 0, C->stream, a, blocks);
     });
   }
 
@@ -397,7 +397,7 @@ struct Engine : EngineBase {
       return fail(XSLAM_ERR_ARG, "launch: raycast tile x*y must be a multiple of 64 in [64, 256]");
     for (int i = 0; i < 3; ++i)
       if (l.icp_blocks[i] < 0 || l.icp_blocks[i] > kMaxIcpBlocks)
-        return fail(XSLAM_ERR_ARG, "launch: ICP workgroups must be in [0, 512]");
+        return fail(XSLAM_ERR_ARG, "launch: ICP workgroups must be in [0, 1200]");
     if (l.fuse_blocks < 64 || l.fuse_blocks > kFuseBlocks)
       return fail(XSLAM_ERR_ARG, "launch: fusion workgroups must be in [64, 4096]");
     ray_bx = bx;
@@ -466,7 +466,7 @@ struct Engine : EngineBase {
     for (int l = 0; l < 3 && !rc; ++l) {
       const int full = int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
       int bestg = icp_grid[l];
-      for (int gsz : {full, 512, 384, 256, 192, 128, 96, 64, 32}) {
+      for (int gsz : {full, 960, 768, 512, 384, 256, 192, 128, 96, 64, 32}) {
         if (gsz > full) continue;
         icp_grid[l] = gsz;
         double ms = 0;

@@ -212,6 +212,39 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// The wave sums of NS per-lane values, each bit for bit what wave_sum gives
+// (the same butterfly: at every step a lane adds its partner's value to its
+// own), but exchanging only the half of the values that is still needed: at
+// the step of lane bit o a lane keeps one half of its current range and sends
+// the other.  63 M double exchanges instead of 6 NS (M = ceil(NS / 64)); lane
+// l ends with the totals of values l M .. l M + M - 1 (zero past NS).
+template <int NS, typename A>
+__device__ __forceinline__ void wave_sum_transposed(const A (&acc)[NS], int lane, double (&out)[(NS + 63) / 64]) {
+  constexpr int M = (NS + 63) / 64, V = 64 * M;
+  double a[V / 2];
+  {
+    const bool up = (lane & 32) != 0;
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) {
+      const double lo = i < NS ? double(acc[i]) : 0.0;
+      const double hi = i + V / 2 < NS ? double(acc[i + V / 2]) : 0.0;
+      const double keep = up ? hi : lo, send = up ? lo : hi;
+      a[i] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+#pragma unroll
+  for (int o = 16, L = V / 2; o >= 1; o >>= 1, L >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < L / 2; ++i) {
+      const double keep = up ? a[i + L / 2] : a[i], send = up ? a[i] : a[i + L / 2];
+      a[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) out[j] = a[j];
+}
+
 // 6x6 symmetric solve with a real LDL^T factorisation of the real part and
 // first/second-order parts from A x = -b differentiated (no conjugation).
 template <int D, int Q>
@@ -355,37 +388,12 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
 // Few components: per-thread sums over a few pixels, then an FP64 block tree.
 // Many components: every pixel's terms are reduced across the wave at once
 // (FP64) into per-wave LDS accumulators, so no thread holds 27 NC sums.
-// One workgroup: fixed-order FP64 sum of the per-workgroup partials, then
-// (unless only the sums are wanted) the FP64 solve, relaxation and SE(3)
-// update.  gsum: [4][NS] and fin: [NS] in LDS.
+// The solve after the sums (one thread): FP64 solve, relaxation, SE(3)
+// update, counters; or only the sums when they are all that is wanted.
 template <typename T, int D, int Q>
-__device__ void icp_finish_block(const IcpArgs<T, D, Q>& g, int nblocks, double (*gsum)[IcpSize<D, Q>::NS],
-                                 double* fin) {
+__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin) {
   constexpr int NC = Jet<T, D, Q>::N;
   constexpr int NS = IcpSize<D, Q>::NS;
-  // Each component is summed over the blocks in the same order whatever the
-  // number of components (so real parts do not depend on D, Q): four
-  // interleaved groups of blocks (b mod 4), eight running sums each, combined
-  // in a fixed tree.  Work items (component, group) are spread over threads.
-  {
-    constexpr int G = 4;
-    const unsigned B = nblocks;
-    for (int item = threadIdx.x; item < NS * G; item += kIcpThreads) {
-      const int k = item / G, grp = item % G;
-      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      unsigned b = grp;
-      for (; b + 7 * G < B; b += 8 * G) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
-      }
-      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
-      gsum[grp][k] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < NS; k += kIcpThreads) fin[k] = (gsum[0][k] + gsum[1][k]) + (gsum[2][k] + gsum[3][k]);
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
   const int cnt = int(fin[27 * NC]);
   int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
   if (!g.do_solve) {
@@ -413,6 +421,7 @@ __device__ void icp_finish_block(const IcpArgs<T, D, Q>& g, int nblocks, double 
   *g.Pcur = Pn;
   *g.Kcur = to_kpose<T, double>(Pn);
 }
+
 
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
@@ -464,10 +473,13 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
     // order.  The tangent sums cancel strongly (the derivative of a converged
     // pose is a small difference of large per-pixel terms), so only the
     // per-thread sums over a few pixels stay in T.
+    {
+      constexpr int M = (NS + 63) / 64;
+      double tot[M];
+      wave_sum_transposed<NS>(acc, lane, tot);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      double s = wave_sum(double(acc[k]));
-      if (lane == 0) red[wv][k] = s;
+      for (int j = 0; j < M; ++j)
+        if (lane * M + j < NS) red[wv][lane * M + j] = tot[j];
     }
   } else {
     // real components (and count, sum r^2) exactly as in the register path, so
@@ -531,14 +543,44 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 
 // One workgroup after k_icp (a kernel boundary makes every partial visible to
 // it without device-wide fences in k_icp, whose cross-XCD L2 write-back cost
-// more than the launch it would save).
+// more than the launch it would save).  Each component is summed over the
+// workgroup partials in the same order whatever the number of components (so
+// real parts do not depend on D, Q): 16 interleaved groups of workgroups
+// (b mod 16), eight running sums each, combined in a fixed tree; components
+// are taken 64 at a time, one (component, group) per thread.
+constexpr int kFinishThreads = 1024;
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(kIcpThreads) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
+__global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
   constexpr int NS = IcpSize<D, Q>::NS;
-  __shared__ double gsum[4][NS];
+  constexpr int G = 16, KC = kFinishThreads / G;
+  __shared__ double gs[G][KC];
   __shared__ double fin[NS];
   if (*g.lost) return;
-  icp_finish_block<T, D, Q>(g, nblocks, gsum, fin);
+  const int grp = threadIdx.x / KC, kk = threadIdx.x % KC;
+  const unsigned B = nblocks;
+  for (int kc = 0; kc < NS; kc += KC) {
+    const int k = kc + kk;
+    double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (k < NS) {
+      unsigned b = grp;
+      for (; b + 7 * G < B; b += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
+      }
+      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
+    }
+    gs[grp][kk] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+    __syncthreads();
+    if (threadIdx.x < KC && kc + int(threadIdx.x) < NS) {
+      double s8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s8[u] = gs[2 * u][threadIdx.x] + gs[2 * u + 1][threadIdx.x];
+      fin[kc + threadIdx.x] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  icp_finish_solve<T, D, Q>(g, fin);
 }
 
 
@@ -624,11 +666,13 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
       const double nn = sqrt(n[q][0] * n[q][0] + n[q][1] * n[q][1] + n[q][2] * n[q][2]);
       keep = dn >= -r * nn;
     }
-    if (keep) {
-      const int ntx = (kp.W + kTile - 1) / kTile, nty = (kp.H + kTile - 1) / kTile;
-      int tx0 = 0, tx1 = ntx - 1, ty0 = 0, ty1 = nty - 1;
+    // a brick reaching to the camera plane (z0 <= 1 mm) has no bounded
+    // footprint: it is kept without the depth test (a conservative cull)
+    if (keep && x[2] - r > 1e-3) {
+      const int ntx = (kp.W + kTile - 1) / kTile;
+      int tx0, tx1, ty0, ty1;
       const double z0 = x[2] - r, z1 = x[2] + r;
-      if (z0 > 1e-3) {
+      {
         const double ul = cx + fx * fmin((x[0] - r) / z0, (x[0] - r) / z1), uh = cx + fx * fmax((x[0] + r) / z0, (x[0] + r) / z1);
         const double vl = cy + fy * fmin((x[1] - r) / z0, (x[1] - r) / z1), vh = cy + fy * fmax((x[1] + r) / z0, (x[1] + r) / z1);
         const int pxl = int(fmax(floor(ul) - 1.0, 0.0)), pxh = int(fmin(floor(uh) + 2.0, double(kp.W - 1)));
@@ -641,12 +685,22 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
       keep = zm > 0.0 && z0 <= zm + double(kp.mu.re()) * 1.01 + 1e-6;
     }
   }
+  // one list append per workgroup (ballots, then a prefix over the 4 waves)
   const unsigned long long bal = __ballot(keep);
-  int base = 0;
-  const int lane = threadIdx.x & 63;
-  if (lane == 0 && bal) base = atomicAdd(count, int(__popcll(bal)));
-  base = __shfl(base, 0, 64);
-  if (keep) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int wcount[4], wbase[4], bbase;
+  if (lane == 0) wcount[wv] = int(__popcll(bal));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      wbase[w] = tot;
+      tot += wcount[w];
+    }
+    bbase = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  if (keep) list[bbase + wbase[wv] + __popcll(bal & ((1ull << lane) - 1ull))] = b;
 }
 
 template <typename T, int D, int Q>
