@@ -63,7 +63,7 @@ struct Engine : EngineBase {
   float* cnn_in = nullptr; float* cnn_xi = nullptr; MPose<D, Q>* Pcand = nullptr;
   double* sums_net = nullptr; double* sums_cv = nullptr;
   xslam_cnn cnn = nullptr;
-  T* tzmax = nullptr; int* dframe = nullptr;
+  T* tzmax = nullptr; T* czmax = nullptr; int* dframe = nullptr;
   int ntiles = 0;
   hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
@@ -115,6 +115,9 @@ struct Engine : EngineBase {
     uint8_t* bflags = cv.take<uint8_t>(nb);
     const int nt = ((c.cam.width + kTile - 1) / kTile) * ((c.cam.height + kTile - 1) / kTile);
     T* tzmax = cv.take<T>(nt);
+    const int ncell = ((c.cam.width + kTile * kCell - 1) / (kTile * kCell)) *
+                      ((c.cam.height + kTile * kCell - 1) / (kTile * kCell));
+    T* czmax = cv.take<T>(ncell);
     const int nrb = ray_block_capacity(c.cam.width, c.cam.height);
     int* fcounts = cv.take<int>(kFuseBlocks);
     int* rhits = cv.take<int>(nrb);
@@ -127,7 +130,8 @@ struct Engine : EngineBase {
     double* sums_cv = cv.take<double>(NS);
     int* dframe = cv.take<int>(1);
     if (e) {
-      e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->dframe = dframe;
+      e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->czmax = czmax;
+      e->dframe = dframe;
       e->ntiles = nt;
       e->fcounts = fcounts; e->rhits = rhits; e->rsamples = rsamples; e->bracket = bracket;
       e->cnn_in = cnn_in; e->cnn_xi = cnn_xi; e->Pcand = Pcand; e->sums_net = sums_net; e->sums_cv = sums_cv;
@@ -510,13 +514,15 @@ struct Engine : EngineBase {
   int run_fuse() {
     int rc;
     const int ntx = (W[0] + kTile - 1) / kTile, nty = (H[0] + kTile - 1) / kTile;
+    const int ncx = (ntx + kCell - 1) / kCell, ncy = (nty + kCell - 1) / kCell;
     if ((rc = launch(4, "tile_zmax", [&] {
-           hipLaunchKernelGGL(k_tile_zmax<T>, dim3(ntx, nty), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax);
+           hipLaunchKernelGGL(k_tile_zmax<T>, dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax,
+                              czmax);
          })))
       return rc;
     if ((rc = launch(7, "brick_cull", [&] {
            hipLaunchKernelGGL((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
-                              tzmax, nbrick, blist, bcount, lost);
+                              tzmax, czmax, nbrick, blist, bcount, lost);
          })))
       return rc;
     const int g = std::min(nbrick, fuse_grid);

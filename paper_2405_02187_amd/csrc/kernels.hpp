@@ -618,22 +618,40 @@ __device__ __forceinline__ void voxel_centre(const KParams<T, D, Q>& kp, int i, 
 // Largest filtered depth per 16x16 tile of level 0 (bound of every L(x)
 // whose bilinear taps fall in that tile).
 constexpr int kTile = 16;
+// Largest filtered depth of every 16x16 tile of level 0 (tmax) and of every
+// 64x64 cell of 4x4 tiles (cmax): one workgroup per cell, 16 lanes per tile,
+// each lane one tile row.
+constexpr int kCell = 4;   // tiles per coarse cell and axis
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax) {
-  const int x = blockIdx.x * kTile + threadIdx.x % kTile, y = blockIdx.y * kTile + threadIdx.x / kTile;
+__global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax,
+                                                   T* __restrict__ cmax) {
+  const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
+  const int tile = threadIdx.x >> 4, row = threadIdx.x & 15;
+  const int tx = blockIdx.x * kCell + (tile & 3), ty = blockIdx.y * kCell + (tile >> 2);
   T m = 0;
-  if (x < W && y < H) {
-    const T d = D0[size_t(y) * W + x];
-    if (d > m) m = d;
+  const int y = ty * kTile + row;
+  if (tx < ntx && ty < nty && y < H) {
+    const T* src = D0 + size_t(y) * W;
+#pragma unroll
+    for (int i = 0; i < kTile; ++i) {
+      const int x = tx * kTile + i;
+      if (x < W) {
+        const T d = src[x];
+        m = d > m ? d : m;
+      }
+    }
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) { T v = __shfl_xor(m, o, 64); m = v > m ? v : m; }
+  for (int o = 8; o >= 1; o >>= 1) { const T v = __shfl_xor(m, o, 64); m = v > m ? v : m; }
+  if (row == 0 && tx < ntx && ty < nty) tmax[ty * ntx + tx] = m;
+#pragma unroll
+  for (int o = 32; o >= 16; o >>= 1) { const T v = __shfl_xor(m, o, 64); m = v > m ? v : m; }
   __shared__ T wm[4];
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    T a = wm[0] > wm[1] ? wm[0] : wm[1], b = wm[2] > wm[3] ? wm[2] : wm[3];
-    tmax[blockIdx.y * gridDim.x + blockIdx.x] = a > b ? a : b;
+    const T a = wm[0] > wm[1] ? wm[0] : wm[1], b = wm[2] > wm[3] ? wm[2] : wm[3];
+    cmax[blockIdx.y * gridDim.x + blockIdx.x] = a > b ? a : b;
   }
 }
 
@@ -643,7 +661,8 @@ __global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int
 // largest depth over the tiles its projection (plus one pixel) covers.
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                    const T* __restrict__ tmax, int nbrick, int* __restrict__ list,
+                                                    const T* __restrict__ tmax, const T* __restrict__ cmax,
+                                                    int nbrick, int* __restrict__ list,
                                                     int* __restrict__ count, const int* __restrict__ lost) {
   const int b = blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
@@ -680,8 +699,15 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
         tx0 = pxl / kTile; tx1 = pxh / kTile; ty0 = pyl / kTile; ty1 = pyh / kTile;
       }
       double zm = 0.0;
-      for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) zm = fmax(zm, double(tmax[ty * ntx + tx]));
+      if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= kCell * kCell) {
+        for (int ty = ty0; ty <= ty1; ++ty)
+          for (int tx = tx0; tx <= tx1; ++tx) zm = fmax(zm, double(tmax[ty * ntx + tx]));
+      } else {
+        // a large footprint: the 64x64 cells covering it (a bound at least as large)
+        const int ncx = (ntx + kCell - 1) / kCell;
+        for (int cy = ty0 / kCell; cy <= ty1 / kCell; ++cy)
+          for (int cx = tx0 / kCell; cx <= tx1 / kCell; ++cx) zm = fmax(zm, double(cmax[cy * ncx + cx]));
+      }
       keep = zm > 0.0 && z0 <= zm + double(kp.mu.re()) * 1.01 + 1e-6;
     }
   }
