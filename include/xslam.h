@@ -95,10 +95,11 @@ typedef struct {
   double agate_deg;      /* degrees                                              */
   double level_w[3];     /* step relaxation per level (1 = plain Gauss-Newton)   */
   double disc_delta;     /* depth discontinuity threshold of bilinear lookups (m)*/
-  int32_t init;          /* 0: previous pose, 1: constant velocity, 2: network
-                            candidate judged against constant velocity by one
-                            level-2 association pass (640 x 480 only; without an
-                            attached network it behaves as 1)                  */
+  int32_t init;          /* 0: previous pose, 1: constant velocity (the previous
+                            pose when either of the two previous frames was
+                            lost), 2: network candidate judged against constant
+                            velocity by one level-2 association pass (640 x 480
+                            only; without an attached network it behaves as 1) */
 } xslam_icp;
 typedef struct {
   int32_t prec;          /* enum xslam_prec                                       */
@@ -206,8 +207,8 @@ int xslam_kernel_times(xslam_ctx ctx, double ms_out[8], int64_t launches_out[8])
  * Launch shapes that do not change any result bit except the order of the
  * FP64 cross-block ICP sums (rounding level): the raycast tile (threads per
  * workgroup in x and y; x*y a multiple of 64 in [64, 256]), the ICP grid per
- * pyramid level (workgroups of 256 threads, 1..512; 0 = one pixel per thread
- * up to 512 workgroups) and the fusion grid (workgroups of one 8^3 brick each,
+ * pyramid level (workgroups of 256 threads, 1..1200; 0 = one pixel per thread
+ * up to 1200 workgroups) and the fusion grid (workgroups of one 8^3 brick each,
  * 64..4096, a grid-stride loop over the active-brick list).  Setting shapes
  * drops the captured frame graph (it is captured again on the next step).
  * Errors: XSLAM_ERR_ARG for a shape outside these limits. */

@@ -346,7 +346,7 @@ struct Engine : EngineBase {
     if ((rc = launch(4, "track_begin", [&] {
            hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pprev, Pprev2, Pinit,
                               Kcur, Kprev, lost, counters, dframe, C->cfg.max_frames,
-                              C->cfg.icp.init == 1 ? 1 : 0);
+                              C->cfg.icp.init >= 1 ? 1 : 0);
          })))
       return rc;
     if (C->cfg.icp.init == 2 && cnn && (rc = learned_init())) return rc;

@@ -585,7 +585,9 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
 
 
 // start of tracking for frame k >= 1: shift the pose history and set the
-// initial estimate (previous pose, or constant velocity T1 T2^-1 T1)
+// initial estimate: the previous pose, or constant velocity T1 T2^-1 T1 when
+// both previous frames were tracked (after a lost frame the velocity is
+// unknown, and extrapolating a guess would never re-acquire the camera)
 template <typename T, int D, int Q>
 __global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>* Pprev2, MPose<D, Q>* Pinit,
                               KPose<T, D, Q>* Kcur, KPose<T, D, Q>* Kprev, int* lost, int32_t* counter_base,
@@ -595,7 +597,30 @@ __global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>
   *Pprev2 = *Pprev;
   *Pprev = *Pcur;
   MPose<D, Q> init = *Pprev;
-  if (const_vel && *frame > 1) init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
+  const int k = *frame;
+  if (const_vel && k > 1 && k - 1 < max_frames) {
+    const bool tracked = counter_base[size_t(kCounters) * (k - 1)] == 0 && counter_base[size_t(kCounters) * (k - 2)] == 0;
+    if (tracked) {
+      init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
+      // R1 R2^T R1 triples the rotation's departure from orthonormality, and
+      // the next prediction starts from it: two Newton steps of the polar
+      // decomposition, R <- (3R - R R^T R)/2, keep it at rounding level
+      for (int it = 0; it < 2; ++it) {
+        using JD = Jet<double, D, Q>;
+        JD RtR[9], N[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            RtR[r * 3 + c] = init.m[0 * 3 + r] * init.m[0 * 3 + c] + init.m[1 * 3 + r] * init.m[1 * 3 + c] +
+                             init.m[2 * 3 + r] * init.m[2 * 3 + c];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            N[r * 3 + c] = 1.5 * init.m[r * 3 + c] -
+                           0.5 * (init.m[r * 3 + 0] * RtR[0 * 3 + c] + init.m[r * 3 + 1] * RtR[1 * 3 + c] +
+                                  init.m[r * 3 + 2] * RtR[2 * 3 + c]);
+        for (int q = 0; q < 9; ++q) init.m[q] = N[q];
+      }
+    }
+  }
   *Pinit = init;
   *Pcur = init;
   *Kcur = to_kpose<T, double>(init);

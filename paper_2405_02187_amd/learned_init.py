@@ -132,17 +132,20 @@ def train(net: "X.Cnn", data, Yd=None, steps: int = 1000, batch: int = 256, lr: 
     return losses
 
 
-def evaluate(cfg_base, depths_dev, T0, gt, frame_step: int, net=None):
-    """Track every frame_step-th frame with constant velocity (net None) or the
-    network initialiser; -> dict(mean first converged ICP pass per tracked
-    frame (passes + 1 when none converged), trajectory error, network use
-    rate, lost frames)."""
+def evaluate(cfg_base, depths_dev, T0, gt, frame_step, net=None):
+    """Track every frame_step-th frame (or the frames listed in frame_step)
+    with constant velocity (net None) or the network initialiser; -> dict(mean
+    first converged ICP pass per tracked frame (passes + 1 when none
+    converged), trajectory error, network use rate, lost frames)."""
     cfg = X.xslam_config.from_buffer_copy(cfg_base)
     cfg.icp.init = 2 if net is not None else 1
     slam = X.Slam(cfg, X.Perturbation([]), T0)
     if net is not None:
         slam.set_cnn(net)
-    idx = list(range(0, depths_dev.shape[0], frame_step))
+    if isinstance(frame_step, int):
+        idx = list(range(0, depths_dev.shape[0], frame_step))
+    else:
+        idx = [int(k) for k in frame_step]
     for k in idx:
         slam.step(depths_dev[k])
     cnt = slam.get(X.F_COUNTERS)[1:]
@@ -214,9 +217,15 @@ def main(argv=None):
     for j in range(a.test_seeds):
         p, s, d = _sequence(sg, torch, "c1", 2000 + j, a.frames)
         cfg = X.config_from_preset(p, prec=X.C64, max_frames=a.frames)
-        for fs in [int(x) for x in a.frame_steps.split(",")]:
-            cv = evaluate(cfg, d, s.poses_gt[0], s.poses_gt, fs, None)
-            nn = evaluate(cfg, d, s.poses_gt[0], s.poses_gt, fs, net)
+        # regular steps, and irregular ones (dropped frames: gaps of 1..6
+        # frames, seeded) where a constant velocity extrapolates the wrong gap
+        rng = np.random.default_rng(2000 + j)
+        irregular = np.cumsum(np.concatenate([[0], rng.integers(1, 7, size=a.frames)]))
+        irregular = irregular[irregular < a.frames]
+        for fs in [int(x) for x in a.frame_steps.split(",")] + ["irregular"]:
+            steps = irregular if fs == "irregular" else fs
+            cv = evaluate(cfg, d, s.poses_gt[0], s.poses_gt, steps, None)
+            nn = evaluate(cfg, d, s.poses_gt[0], s.poses_gt, steps, net)
             report["tests"].append(dict(seed=2000 + j, frame_step=fs, constant_velocity=cv, network=nn))
             print(f"test seed {2000 + j} step {fs}: cv {cv}  net {nn}", flush=True)
         del d

@@ -242,8 +242,10 @@ def spline_trajectory(seed: int, scene: Scene, n_frames: int, v_max: float = 0.5
     """Catmull-Rom position spline through ``n_ctrl`` points in the central 50% of
     the cube, 0.8-1.8 m above the floor and >= ``clearance`` from every surface,
     looking at a second spline through points near the object centroid; retimed
-    so speed <= v_max and angular rate <= w_max at ``fps``; ping-pongs along the
-    path if it is shorter than the requested number of frames."""
+    so speed <= v_max and angular rate <= w_max at ``fps`` with a smooth speed
+    profile (no jumps in velocity) that slows down towards the path's ends;
+    ping-pongs along the path if it is shorter than the requested number of
+    frames."""
     rng = np.random.Generator(np.random.PCG64(_children(seed)[1]))
     L = scene.L
     half = 0.25 * L
@@ -272,6 +274,19 @@ def spline_trajectory(seed: int, scene: Scene, n_frames: int, v_max: float = 0.5
     da = _rot_angle(Rs[:-1], Rs[1:])
     # seconds per segment at the limits (5% margin for the within-segment nonlinearity)
     cost = np.maximum(dl / (0.95 * v_max), da / np.deg2rad(0.95 * w_max_deg))
+    # a smooth speed profile: the running maximum over +-W samples, averaged
+    # over +-W samples, bounds every sample's own cost (so the limits still
+    # hold) and changes continuously; towards both ends of the path the speed
+    # ramps down to a tenth, so that the ping-pong turnaround is gentle
+    W = 400
+    pad = np.pad(cost, W, mode="edge")
+    win = np.lib.stride_tricks.sliding_window_view(pad, 2 * W + 1)
+    env = win.max(axis=1)
+    ker = np.ones(2 * W + 1) / (2 * W + 1)
+    cost = np.convolve(np.pad(env, W, mode="edge"), ker, mode="valid")
+    ramp = 3 * W
+    u = np.minimum(np.arange(len(cost)), np.arange(len(cost))[::-1]) / ramp
+    cost = cost / np.maximum(0.1, np.sin(0.5 * np.pi * np.minimum(u, 1.0)))
     tcum = np.concatenate([[0.0], np.cumsum(cost)])
     total = tcum[-1]
     period = 2.0 * total
