@@ -6,6 +6,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <utility>
 #include "common.hpp"
 
 namespace xs {
@@ -245,6 +246,83 @@ __device__ __forceinline__ void wave_sum_transposed(const A (&acc)[NS], int lane
   for (int j = 0; j < M; ++j) out[j] = a[j];
 }
 
+// Component C of the jet product x * y, by the same operations as the jet
+// operator (so the same bits): real part, first-order part, or the part of
+// the pair (a, b) of the first Q directions (row-major upper triangle).
+template <int Q>
+__host__ __device__ constexpr int pair_a(int p) {
+  int a = 0;
+  while (p >= Q - a) { p -= Q - a; ++a; }
+  return a;
+}
+template <int Q>
+__host__ __device__ constexpr int pair_b(int p) {
+  int a = 0;
+  while (p >= Q - a) { p -= Q - a; ++a; }
+  return a + p;
+}
+template <int C, typename T, int D, int Q>
+__device__ __forceinline__ T jet_prod_comp(const Jet<T, D, Q>& x, const Jet<T, D, Q>& y) {
+  if constexpr (C == 0) {
+    return x.v[0] * y.v[0];
+  } else if constexpr (C <= D) {
+    return tfma(x.v[0], y.v[C], x.v[C] * y.v[0]);
+  } else {
+    constexpr int a = pair_a<Q>(C - 1 - D), b = pair_b<Q>(C - 1 - D);
+    T s = tfma(x.v[0], y.v[C], x.v[C] * y.v[0]);
+    s = tfma(x.v[1 + a], y.v[1 + b], s);
+    return tfma(x.v[1 + b], y.v[1 + a], s);
+  }
+}
+// Flat index F over the 27 normal-equation products (21 J_a J_b with a <= b,
+// then 6 J_a r) and their non-real components 1..NC-1 (product-major).
+__host__ __device__ constexpr int jj_a(int k) {
+  int a = 0;
+  while (k >= 6 - a) { k -= 6 - a; ++a; }
+  return a;
+}
+__host__ __device__ constexpr int jj_b(int k) {
+  int a = 0;
+  while (k >= 6 - a) { k -= 6 - a; ++a; }
+  return a + k;
+}
+template <int F, typename T, int D, int Q>
+__device__ __forceinline__ double icp_flat_comp(const Jet<T, D, Q> (&jac)[6], const Jet<T, D, Q>& r) {
+  constexpr int NT = Jet<T, D, Q>::N - 1;
+  if constexpr (F >= 27 * NT) {
+    return 0.0;
+  } else {
+    constexpr int k = F / NT, c = 1 + F % NT;
+    if constexpr (k < 21)
+      return double(jet_prod_comp<c>(jac[jj_a(k)], jac[jj_b(k)]));
+    else
+      return double(jet_prod_comp<c>(jac[k - 21], r));
+  }
+}
+template <int F0, typename T, int D, int Q, int... J>
+__device__ __forceinline__ void icp_fill_chunk(const Jet<T, D, Q> (&jac)[6], const Jet<T, D, Q>& r,
+                                               double (&vals)[64], std::integer_sequence<int, J...>) {
+  ((vals[J] = icp_flat_comp<F0 + J>(jac, r)), ...);
+}
+// Wave sums of every non-real component of one pixel's 27 products, 64 at a
+// time with the half-exchanging butterfly (each sum bit for bit a wave_sum),
+// added into the wave's row of LDS sums.
+template <typename T, int D, int Q, int... CH>
+__device__ __forceinline__ void icp_tangent_sums(const Jet<T, D, Q> (&jac)[6], const Jet<T, D, Q>& r, int lane,
+                                                 double* red_row, std::integer_sequence<int, CH...>) {
+  constexpr int NC = Jet<T, D, Q>::N, NT = NC - 1;
+  auto one = [&](auto chi) {
+    constexpr int ch = decltype(chi)::value;
+    double vals[64];
+    icp_fill_chunk<ch * 64>(jac, r, vals, std::make_integer_sequence<int, 64>{});
+    double tot[1];
+    wave_sum_transposed<64>(vals, lane, tot);
+    const int f = ch * 64 + lane;
+    if (f < 27 * NT) red_row[(f / NT) * NC + 1 + f % NT] += tot[0];
+  };
+  (one(std::integral_constant<int, CH>{}), ...);
+}
+
 // 6x6 symmetric solve with a real LDL^T factorisation of the real part and
 // first/second-order parts from A x = -b differentiated (no conjugation).
 template <int D, int Q>
@@ -343,36 +421,59 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
   if (!(fx0 >= T(0) && fy0 >= T(0) && fx0 <= T(W - 2) && fy0 <= T(H - 2))) return false;
   const int i0 = int(fx0), j0 = int(fy0);
   const size_t t0 = size_t(j0) * W + i0, t1 = t0 + 1, t2 = t0 + W, t3 = t2 + 1;
-  // everything the four taps hold, in flight at once; the nearest tap
-  // floor(u + 1/2) is one of them (u - floor(u + 1e-3) lies in [-1e-3, 1))
-  const uint8_t w0 = g.validm[t0], w1 = g.validm[t1], w2 = g.validm[t2], w3 = g.validm[t3];
-  const T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
-  const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-  const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
-  const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-  const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
-  if (!(w0 && w1 && w2 && w3)) return false;
-  const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
-  const bool inside = (in == i0 || in == i0 + 1) && (jn == j0 || jn == j0 + 1);
-  const int sel = (jn - j0) * 2 + (in - i0);
-  const size_t tn = size_t(jn) * W + in;
-  const T zn = inside ? (sel == 0 ? z0 : sel == 1 ? z1 : sel == 2 ? z2 : z3) : g.Zm[tn];
-  const T disc = fabs(z0 - zn) + fabs(z1 - zn) + fabs(z2 - zn) + fabs(z3 - zn);
   V3<J> q, m;
-  if (disc >= kp.disc_delta) {
-    if (inside) {
-      q = sel == 0 ? q0 : sel == 1 ? q1 : sel == 2 ? q2 : q3;
-      m = sel == 0 ? m0 : sel == 1 ? m1 : sel == 2 ? m2 : m3;
+  if constexpr (J::N <= 8) {
+    // everything the four taps hold, in flight at once; the nearest tap
+    // floor(u + 1/2) is one of them (u - floor(u + 1e-3) lies in [-1e-3, 1))
+    const uint8_t w0 = g.validm[t0], w1 = g.validm[t1], w2 = g.validm[t2], w3 = g.validm[t3];
+    const T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
+    const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+    const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+    const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+    const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+    if (!(w0 && w1 && w2 && w3)) return false;
+    const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
+    const bool inside = (in == i0 || in == i0 + 1) && (jn == j0 || jn == j0 + 1);
+    const int sel = (jn - j0) * 2 + (in - i0);
+    const size_t tn = size_t(jn) * W + in;
+    const T zn = inside ? (sel == 0 ? z0 : sel == 1 ? z1 : sel == 2 ? z2 : z3) : g.Zm[tn];
+    const T disc = fabs(z0 - zn) + fabs(z1 - zn) + fabs(z2 - zn) + fabs(z3 - zn);
+    if (disc >= kp.disc_delta) {
+      if (inside) {
+        q = sel == 0 ? q0 : sel == 1 ? q1 : sel == 2 ? q2 : q3;
+        m = sel == 0 ? m0 : sel == 1 ? m1 : sel == 2 ? m2 : m3;
+      } else {
+        q = vload<J>(g.Vm, n, tn);
+        m = vload<J>(g.Nm, n, tn);
+      }
     } else {
-      q = vload<J>(g.Vm, n, tn);
-      m = vload<J>(g.Nm, n, tn);
+      const J a = ux - fx0, b = uy - fy0;
+      const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
+      q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
+      V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
+      m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
     }
   } else {
-    const J a = ux - fx0, b = uy - fy0;
-    const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
-    q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
-    V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
-    m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
+    // many components: the taps are loaded only as they are used (registers)
+    if (!(g.validm[t0] && g.validm[t1] && g.validm[t2] && g.validm[t3])) return false;
+    const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
+    const size_t tn = size_t(jn) * W + in;
+    const T zn = g.Zm[tn];
+    const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
+    if (disc >= kp.disc_delta) {
+      q = vload<J>(g.Vm, n, tn);
+      m = vload<J>(g.Nm, n, tn);
+    } else {
+      const J a = ux - fx0, b = uy - fy0;
+      const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
+      const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+      const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+      q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
+      const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+      const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+      V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
+      m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
+    }
   }
   const V3<J> d = vsub(p, q);
   if (!(vdot(d, d).re() <= kp.dgate2)) return false;
@@ -498,26 +599,17 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 #pragma unroll
         for (int a = 0; a < 6; ++a) jac[a] = jzero<J>();
       }
-      int k = 0;
-      for (int a = 0; a < 6; ++a)
-        for (int b = a; b < 6; ++b, ++k) {
-          const J prod = jac[a] * jac[b];
-          if (ok) racc[k] += prod.v[0];
+      if (ok) {
+        int k = 0;
 #pragma unroll
-          for (int c = 1; c < NC; ++c) {
-            const double sv = wave_sum(double(prod.v[c]));
-            if (lane == 0) red[wv][k * NC + c] += sv;
-          }
-        }
-      for (int a = 0; a < 6; ++a) {
-        const J prod = jac[a] * r;
-        if (ok) racc[21 + a] += prod.v[0];
+        for (int a = 0; a < 6; ++a)
 #pragma unroll
-        for (int c = 1; c < NC; ++c) {
-          const double sv = wave_sum(double(prod.v[c]));
-          if (lane == 0) red[wv][(21 + a) * NC + c] += sv;
-        }
+          for (int b = a; b < 6; ++b, ++k) racc[k] += jac[a].v[0] * jac[b].v[0];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) racc[21 + a] += jac[a].v[0] * r.v[0];
       }
+      constexpr int NCH = (27 * (NC - 1) + 63) / 64;
+      icp_tangent_sums<T, D, Q>(jac, r, lane, red[wv], std::make_integer_sequence<int, NCH>{});
       if (ok) {
         racc[27] += T(1);
         racc[28] += r.re() * r.re();
