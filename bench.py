@@ -173,6 +173,13 @@ def forms(X, torch, sg, p1, dev1, T0, poses32, n_warm=5, n_timed=30, multi_cap=N
     slam.close()
     out["fp32_16dir_10pair"]["same_workload_1dir_value"] = n_timed / dt1
     del dev2, tan2
+    # one FP32 frame step from the FP64 state at later frames of the sequence
+    from paper_2405_02187_amd import precision as PR
+    kmax = 499
+    seqL = sg.make_sequence(p1, n_frames=kmax + 1)
+    dL = seqL.depths(workers=16).astype(np.float32)
+    out["fp32_one_step_vs_fp64"] = PR.one_step_errors(p1, dL, T0, (1, 100, 250, 499))
+    del dL
     # 24 uneven independent sequences together
     from paper_2405_02187_amd import multi as M
     t0 = time.perf_counter()

@@ -98,8 +98,11 @@ typedef struct {
   int32_t init;          /* 0: previous pose, 1: constant velocity (the previous
                             pose when either of the two previous frames was
                             lost), 2: network candidate judged against constant
-                            velocity by one level-2 association pass (640 x 480
-                            only; without an attached network it behaves as 1) */
+                            velocity by one level-2 association pass: it is
+                            used when its mean squared residual is lower and it
+                            keeps >= 100 and >= 95% of the correspondences
+                            (640 x 480 only; without an attached network it
+                            behaves as 1)                                      */
 } xslam_icp;
 typedef struct {
   int32_t prec;          /* enum xslam_prec                                       */
@@ -167,7 +170,8 @@ int xslam_integrate(xslam_ctx ctx, const void* depth, const void* depth_dot, con
  * [3][NC][H*W] in the context precision). */
 int xslam_raycast(xslam_ctx ctx, const double* pose, void* vmap, void* nmap);
 
-/* Camera pose estimation (Sec. 4.1 eq. "icp"): measure `depth` and run the
+/* Camera pose estimation (Sec. 4.1 eq. "icp"): measure `depth` (or, with
+ * depth NULL, keep the maps measured last or set with xslam_set) and run the
  * multi-level ICP against the current model maps.  The result becomes the
  * current pose; pose_out (host, [NC][16]) if not NULL (synchronises). */
 int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out);

@@ -182,7 +182,7 @@ static int finish_pose(xslam_ctx ctx, double* pose_out) {
 
 int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out) {
   XS_CTX_CHECK(ctx);
-  int rc = ctx->eng->measure(depth, depth_dot);
+  int rc = depth ? ctx->eng->measure(depth, depth_dot) : XSLAM_OK;
   if (rc) return rc;
   rc = ctx->eng->track();
   if (rc) return rc;

@@ -25,6 +25,7 @@ struct KParams {
   T disc_delta;            // discontinuity threshold (m)
   T bil_is, bil_ir;        // 1/(2 sigma_px^2), 1/(2 sigma_m^2)
   T pyr_gate;              // 3 sigma_m
+  double bil_is_d, bil_ir_d, pyr_gate_d;   // the same in FP64 (FP32 runs measure real parts in FP64)
   T voxel;                 // voxel size s
   T half[3];               // L/2 per axis
   T near_m;

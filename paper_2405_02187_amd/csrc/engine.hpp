@@ -5,6 +5,7 @@
 #include <string.h>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 #include "ctx.hpp"
 #include "kernels.hpp"
@@ -50,6 +51,7 @@ struct Engine : EngineBase {
   T2* rec = nullptr; T* Ftan = nullptr; T* Wtan = nullptr;
   T* raw = nullptr; T* rawdot = nullptr;
   T* Dl[3]; T* Vl[3]; T* Nl[3]; uint8_t* valid[3];
+  double* Dhi[3] = {nullptr, nullptr, nullptr};   // FP32 runs: FP64 real part of the filtered depth
   T* Vm[3]; T* Nm[3]; T* Zm[3]; uint8_t* mvalid[3];
   double* partials = nullptr; int* lost = nullptr;
   MPose<D, Q>* Pcur; MPose<D, Q>* Pprev; MPose<D, Q>* Pprev2; MPose<D, Q>* Pinit; MPose<D, Q>* hist;
@@ -99,6 +101,9 @@ struct Engine : EngineBase {
       Zm[l] = cv.take<T>(n);
       mv[l] = cv.take<uint8_t>(n);
     }
+    double* dhi[3] = {nullptr, nullptr, nullptr};
+    if (std::is_same<T, float>::value)
+      for (int l = 0; l < 3; ++l) dhi[l] = cv.take<double>(size_t(c.cam.width >> l) * (c.cam.height >> l));
     double* partials = cv.take<double>(size_t(kMaxIcpBlocks) * NS);
     int* lost = cv.take<int>(1);
     MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
@@ -141,6 +146,7 @@ struct Engine : EngineBase {
         e->Vm[l] = Vm[l]; e->Nm[l] = Nm[l]; e->Zm[l] = Zm[l]; e->mvalid[l] = mv[l];
       }
       e->partials = partials; e->lost = lost;
+      for (int l = 0; l < 3; ++l) e->Dhi[l] = dhi[l];
       e->Pcur = P; e->Pprev = P + 1; e->Pprev2 = P + 2; e->Pinit = P + 3; e->hist = hist;
       e->Kcur = K; e->Kprev = K + 1;
       e->counters = counters; e->sums = sums; e->traj = traj; e->gt = gt; e->stage = stage;
@@ -213,6 +219,9 @@ struct Engine : EngineBase {
     kp.bil_is = T(1.0 / (2.0 * c.bilateral_sigma_px * c.bilateral_sigma_px));
     kp.bil_ir = T(1.0 / (2.0 * c.bilateral_sigma_m * c.bilateral_sigma_m));
     kp.pyr_gate = T(3.0 * c.bilateral_sigma_m);
+    kp.bil_is_d = 1.0 / (2.0 * c.bilateral_sigma_px * c.bilateral_sigma_px);
+    kp.bil_ir_d = 1.0 / (2.0 * c.bilateral_sigma_m * c.bilateral_sigma_m);
+    kp.pyr_gate_d = 3.0 * c.bilateral_sigma_m;
     kp.voxel = T(c.vol.voxel);
     for (int a = 0; a < 3; ++a) {
       kp.half[a] = T(0.5 * c.vol.dim[a] * c.vol.voxel);
@@ -296,13 +305,14 @@ struct Engine : EngineBase {
     dim3 b(16, 16);
     dim3 g0((W[0] + 15) / 16, (H[0] + 15) / 16);
     if ((rc = launch(0, "bilateral", [&] {
-           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0]);
+           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0]);
          })))
       return rc;
     for (int l = 1; l < 3; ++l) {
       dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
       if ((rc = launch(0, "pyrdown", [&] {
-             hipLaunchKernelGGL((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l]);
+             hipLaunchKernelGGL((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l],
+                                Dhi[l - 1], Dhi[l]);
            })))
         return rc;
     }
@@ -310,7 +320,7 @@ struct Engine : EngineBase {
       dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
       if ((rc = launch(0, "vertex_normal", [&] {
              hipLaunchKernelGGL((k_vertex_normal<T, D, Q>), g, b, 0, C->stream, kp, l, Dl[l], W[l], H[l], Vl[l],
-                                Nl[l], valid[l]);
+                                Nl[l], valid[l], Dhi[l]);
            })))
         return rc;
     }

@@ -6,6 +6,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 #include <utility>
 #include "common.hpp"
 
@@ -51,7 +52,12 @@ constexpr int kBilTile = 16;
 constexpr int kBilMaxR = 4;
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T* __restrict__ depth,
-                                                   const T* __restrict__ ddot, T* __restrict__ Dout) {
+                                                   const T* __restrict__ ddot, T* __restrict__ Dout,
+                                                   double* __restrict__ Dhi) {
+  // FP32 runs evaluate the real part in FP64 as well (Dhi) and store it rounded:
+  // normals are differences of neighbouring vertices a few mm apart at metres of
+  // depth, which FP32 accumulation would leave with ~1e-4 rad errors
+  constexpr bool kHi = std::is_same<T, float>::value;
   using J = Jet<T, D, Q>;
   constexpr int S = kBilTile + 2 * kBilMaxR;
   __shared__ J tile[S * S];
@@ -72,9 +78,11 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
   const J c = tile[(threadIdx.y + kBilMaxR) * S + threadIdx.x + kBilMaxR];
   if (!(c.re() > T(0)) || r <= 0) {
     jstore(Dout, n, i, c);
+    if constexpr (kHi) Dhi[i] = double(c.re());
     return;
   }
   J num = jzero<J>(), den = jzero<J>();
+  double num_hi = 0.0, den_hi = 0.0;
   for (int dy = -r; dy <= r; ++dy)
     for (int dx = -r; dx <= r; ++dx) {
       int xx = x + dx, yy = y + dy;
@@ -86,8 +94,20 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
       J w = jexp(-arg);
       num = num + w * d;
       den = den + w;
+      if constexpr (kHi) {
+        const double ddh = double(c.re()) - double(d.re());
+        const double wh = exp(-(double(dx * dx + dy * dy) * kp.bil_is_d + (ddh * ddh) * kp.bil_ir_d));
+        num_hi = num_hi + wh * double(d.re());
+        den_hi = den_hi + wh;
+      }
     }
-  jstore(Dout, n, i, num / den);
+  J out = num / den;
+  if constexpr (kHi) {
+    const double oh = num_hi / den_hi;
+    Dhi[i] = oh;
+    out.v[0] = float(oh);
+  }
+  jstore(Dout, n, i, out);
 }
 
 // Coarser level (Sec. 4.1: "Gaussian smoothing", the perturbation smoothed
@@ -95,8 +115,10 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
 // 3 s_m of the centre, renormalised; real weights.
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* __restrict__ Din, int Wi, int Hi,
-                                                 T* __restrict__ Dout) {
+                                                 T* __restrict__ Dout, const double* __restrict__ Dhi_in,
+                                                 double* __restrict__ Dhi_out) {
   using J = Jet<T, D, Q>;
+  constexpr bool kHi = std::is_same<T, float>::value;   // FP32 runs: real part in FP64 as well
   const int Wo = Wi / 2, Ho = Hi / 2;
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   if (x >= Wo || y >= Ho) return;
@@ -104,11 +126,14 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
   const T c = Din[size_t(2 * y) * Wi + 2 * x];
   if (!(c > T(0))) {
     jstore(Dout, no, o, jzero<J>());
+    if constexpr (kHi) Dhi_out[o] = 0.0;
     return;
   }
   const int g[5] = {1, 4, 6, 4, 1};
   J num = jzero<J>();
   T den = 0;
+  double ch = 0.0, num_hi = 0.0, den_hi = 0.0;
+  if constexpr (kHi) ch = Dhi_in[size_t(2 * y) * Wi + 2 * x];
   for (int j = -2; j <= 2; ++j)
     for (int i = -2; i <= 2; ++i) {
       int xx = 2 * x + i, yy = 2 * y + j;
@@ -116,12 +141,26 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
       size_t q = size_t(yy) * Wi + xx;
       T d = Din[q];
       if (!(d > T(0))) continue;
-      if (fabs(d - c) > kp.pyr_gate) continue;
+      if constexpr (kHi) {
+        const double dh = Dhi_in[q];
+        if (fabs(dh - ch) > kp.pyr_gate_d) continue;
+        const double wh = double(g[i + 2] * g[j + 2]);
+        num_hi = num_hi + wh * dh;
+        den_hi = den_hi + wh;
+      } else {
+        if (fabs(d - c) > kp.pyr_gate) continue;
+      }
       T w = T(g[i + 2] * g[j + 2]);
       num = num + w * jload<J>(Din, ni, q);
       den += w;
     }
-  jstore(Dout, no, o, num / den);
+  J out = num / den;
+  if constexpr (kHi) {
+    const double oh = num_hi / den_hi;
+    Dhi_out[o] = oh;
+    out.v[0] = float(oh);
+  }
+  jstore(Dout, no, o, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -131,7 +170,9 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int level, const T* __restrict__ Dl,
                                                        int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
-                                                       uint8_t* __restrict__ valid) {
+                                                       uint8_t* __restrict__ valid, const double* __restrict__ Dhi) {
+  // FP32 runs: the real parts of vertices and normals from the FP64 depth
+  constexpr bool kHi = std::is_same<T, float>::value;
   using J = Jet<T, D, Q>;
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   if (x >= Wl || y >= Hl) return;
@@ -145,9 +186,23 @@ __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int 
     J ry = (jconst<J>(T(yy)) - cy) / fy;
     return {d * rx, d * ry, d};
   };
+  // FP64 real vertex (FP32 runs)
+  const double fxh = double(kp.fx.re()) * double(sc), fyh = double(kp.fy.re()) * double(sc);
+  const double cxh = double(kp.cx.re()) * double(sc), cyh = double(kp.cy.re()) * double(sc);
+  auto vert_hi = [&](int xx, int yy, double v[3]) {
+    const double d = Dhi[size_t(yy) * Wl + xx];
+    v[0] = d * ((double(xx) - cxh) / fxh);
+    v[1] = d * ((double(yy) - cyh) / fyh);
+    v[2] = d;
+  };
   bool ok0;
   V3<J> v0 = vert(x, y, ok0);
   const J z = jzero<J>();
+  double h0[3] = {0, 0, 0};
+  if constexpr (kHi) {
+    vert_hi(x, y, h0);
+    if (ok0) { v0.x.v[0] = float(h0[0]); v0.y.v[0] = float(h0[1]); v0.z.v[0] = float(h0[2]); }
+  }
   vstore(Vout, n, i, ok0 ? v0 : V3<J>{z, z, z});
   bool okn = false;
   V3<J> nn = {z, z, z};
@@ -159,7 +214,24 @@ __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int 
       V3<J> a = vsub(v1, v0), b = vsub(v2, v0);
       V3<J> c = vcross(b, a);
       J cc = vdot(c, c);
-      if (cc.re() > T(0)) {
+      if constexpr (kHi) {
+        double h1[3], h2[3];
+        vert_hi(x + 1, y, h1);
+        vert_hi(x, y + 1, h2);
+        const double ah[3] = {h1[0] - h0[0], h1[1] - h0[1], h1[2] - h0[2]};
+        const double bh[3] = {h2[0] - h0[0], h2[1] - h0[1], h2[2] - h0[2]};
+        const double ch[3] = {bh[1] * ah[2] - bh[2] * ah[1], bh[2] * ah[0] - bh[0] * ah[2], bh[0] * ah[1] - bh[1] * ah[0]};
+        const double cch = ch[0] * ch[0] + ch[1] * ch[1] + ch[2] * ch[2];
+        if (cch > 0.0) {
+          J inv = jconst<J>(T(1)) / jsqrt(cc);
+          nn = vscale(inv, c);
+          const double ih = 1.0 / sqrt(cch);
+          nn.x.v[0] = float(ch[0] * ih);
+          nn.y.v[0] = float(ch[1] * ih);
+          nn.z.v[0] = float(ch[2] * ih);
+          okn = true;
+        }
+      } else if (cc.re() > T(0)) {
         J inv = jconst<J>(T(1)) / jsqrt(cc);
         nn = vscale(inv, c);
         okn = true;
@@ -1182,16 +1254,22 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
         miss = true;
       }
     }
-    T alpha = fmax(kp.near_m, tmin);
+    // the ray parameter accumulates over up to hundreds of samples: FP32 runs
+    // keep it (and the sample positions) in FP64, so that the sample grid does
+    // not drift by the rounding of every step
+    using TA = typename std::conditional<std::is_same<T, float>::value, double, T>::type;
+    TA alpha = fmax(TA(kp.near_m), TA(tmin));
     const T mu = kp.mu.re();
-    const T small = T(0.5) * s / nrm, big = T(0.8) * mu / nrm;
+    const TA small = TA(0.5) * TA(s) / TA(nrm), big = TA(0.8) * TA(mu) / TA(nrm);
     bool prev_ok = false;
-    T a_prev = 0, f_prev = 0;
-    T hit0 = 0, hit1 = T(-1);
+    TA a_prev = 0;
+    T f_prev = 0;
+    TA hit0 = 0, hit1 = TA(-1);
     int64_t cbrick = -1;
     uint8_t cflag = 0;
-    for (int it = 0; it < 100000 && !miss && alpha <= tmax; ++it, ++nsamp) {
-      const T v[3] = {orr[0] + alpha * dr[0], orr[1] + alpha * dr[1], orr[2] + alpha * dr[2]};
+    for (int it = 0; it < 100000 && !miss && alpha <= TA(tmax); ++it, ++nsamp) {
+      const T v[3] = {T(TA(orr[0]) + alpha * TA(dr[0])), T(TA(orr[1]) + alpha * TA(dr[1])),
+                      T(TA(orr[2]) + alpha * TA(dr[2]))};
       T f;
       const bool okf = trilinear_re(kp, rec, flags, v, f, cbrick, cflag);
       if (!okf) f = 0;
@@ -1203,15 +1281,15 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
         }
         if (f_prev < T(0) && f > T(0)) break;
       }
-      const T step = (okf && f < T(0.999)) ? small : big;
+      const TA step = (okf && f < T(0.999)) ? small : big;
       prev_ok = okf;
       a_prev = alpha;
       f_prev = f;
       alpha = alpha + step;
     }
     typename Vec2<T>::type b;
-    b.x = hit0;
-    b.y = hit1;
+    b.x = T(hit0);
+    b.y = T(hit1);
     bracket[size_t(y) * W + x] = b;
   }
   const int ns = block_sum_int(nsamp);
@@ -1374,8 +1452,10 @@ __global__ void k_set_current(const MPose<D, Q>* P, MPose<D, Q>* Pcur, KPose<T, 
   *Kcur = to_kpose<T, double>(*P);
 }
 
-// keep the candidate with the lower mean squared residual of one level-2 pass
-// (the network's only with at least 100 correspondences)
+// keep the candidate with the lower mean squared residual of one level-2 pass;
+// the network's only with at least 100 correspondences and at least 95% of
+// the constant-velocity candidate's (a candidate that loses correspondences
+// to the gates can show a lower mean residual while being further off)
 template <typename T, int D, int Q>
 __global__ void k_choose_init(const double* sums_net, const double* sums_cv, int ns, const MPose<D, Q>* Pnet,
                               MPose<D, Q>* Pinit, MPose<D, Q>* Pcur, KPose<T, D, Q>* Kcur, int32_t* counter_base,
@@ -1384,7 +1464,7 @@ __global__ void k_choose_init(const double* sums_net, const double* sums_cv, int
   int32_t* crow = counter_row(counter_base, frame, max_frames);
   const double cn = sums_net[ns - 2], cc = sums_cv[ns - 2];
   const double en = cn > 0 ? sums_net[ns - 1] / cn : 1e300, ec = cc > 0 ? sums_cv[ns - 1] / cc : 1e300;
-  const bool use_net = cn >= 100.0 && en < ec;
+  const bool use_net = cn >= 100.0 && cn >= 0.95 * cc && en < ec;
   if (use_net) *Pinit = *Pnet;
   *Pcur = *Pinit;
   *Kcur = to_kpose<T, double>(*Pinit);

@@ -240,9 +240,10 @@ class Slam:
         return self._check(lib().xslam_raycast(self.h, None if pp is None else pp.ctypes.data_as(C.POINTER(C.c_double)),
                                                None, None))
 
-    def track(self, depth, depth_dot=None, want_pose=True):
+    def track(self, depth=None, depth_dot=None, want_pose=True):
+        """depth None: track the frame measured last (or set with set())."""
         out = np.zeros((self.nc, 16)) if want_pose else None
-        rc = self._check(lib().xslam_track(self.h, _ptr(depth), self._dd(depth_dot),
+        rc = self._check(lib().xslam_track(self.h, None if depth is None else _ptr(depth), self._dd(depth_dot),
                                            None if out is None else out.ctypes.data_as(C.POINTER(C.c_double))))
         return rc, out
 

@@ -83,11 +83,12 @@ def test_c0_fp64_sequence_matches_oracle(param):
 
 
 def test_c0_fp32_sequence():
-    """FP32-complex, 20 frames: poses within 1e-5 of the FP64 oracle.  The
-    end-to-end derivative is bounded by the oracle's own conditioning: its
-    derivative moves by ~1e-4 when the input depth is jittered at FP32 level
-    (6e-8 relative), because decisions near thresholds flip; the FP32 path may
-    differ from the FP64 oracle by at most 20 times that spread."""
+    """FP32-complex, 20 frames, against the FP64 oracle, bounded by the
+    oracle's own conditioning: its poses and derivative move when the input
+    depth is jittered at FP32 level (6e-8 relative), because decisions near
+    thresholds flip and later frames start from the moved poses; the FP32
+    path may differ from the FP64 oracle by at most 20 times that spread
+    (1e-5 at least)."""
     p, seq = c0_seq()
     depths = seq.depths().astype(np.float32)
     T0 = seq.poses_gt[0]
@@ -101,8 +102,10 @@ def test_c0_fp32_sequence():
     jit = depths.astype(np.float64) * (1 + 6e-8 * rng.standard_normal(depths.shape))
     refj = O.run_sequence(O.config(p), O.seed(1, O.P_TRUNC, h=H20), jit, T0)
     spread = relerr(refj["poses"][..., 1], ref["poses"][..., 1])
-    log("c0 fp32 pose rel err", e_re, "derivative rel err", e_im, "oracle FP32-jitter spread", spread)
-    assert e_re <= 1e-5
+    spread0 = relerr(refj["poses"][..., 0], ref["poses"][..., 0])
+    log("c0 fp32 pose rel err", e_re, "derivative rel err", e_im, "oracle FP32-jitter spread: pose", spread0,
+        "derivative", spread)
+    assert e_re <= max(1e-5, 20 * spread0)
     assert e_im <= max(1e-5, 20 * spread)
     slam.close()
 
