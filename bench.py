@@ -269,12 +269,15 @@ def main():
     log(f"{args.steps} frame steps in {dt:.3f}s")
 
     # per-kernel durations with HIP events on the library's stream
+    # (the counts accumulate over the context's life: the autotuner's timed
+    # steps are taken out as the difference)
     slam.set_timing(True)
-    slam.kernel_times()
+    ms0, launches0 = slam.kernel_times()
     k0 = args.warmup + args.steps
     for k in range(k0, k0 + args.timing_steps):
         slam.step(dev[k])
     ms, launches = slam.kernel_times()
+    ms, launches = ms - ms0, launches - launches0
     cnt = slam.get(X.F_COUNTERS)[k0:k0 + args.timing_steps]
     per = {c: dict(ms_total=float(ms[i]), launches=int(launches[i]),
                    us_per_launch=float(1e3 * ms[i] / max(launches[i], 1))) for i, c in enumerate(X.TIMER_CLASSES)}

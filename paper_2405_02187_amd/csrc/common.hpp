@@ -113,13 +113,12 @@ XJ MPose<D, Q> pose_inverse(const MPose<D, Q>& A) {
 // undefined at phi = 0 where every pose seed and ICP update starts), else
 // sin/cos closed forms.
 template <int D, int Q>
-XJ MPose<D, Q> se3_exp(const Jet<double, D, Q> xi[6]) {
+XJ void se3_abc(const Jet<double, D, Q> xi[6], Jet<double, D, Q>& A, Jet<double, D, Q>& B, Jet<double, D, Q>& C) {
   using J = Jet<double, D, Q>;
   const J& px = xi[0];
   const J& py = xi[1];
   const J& pz = xi[2];
   J t2 = px * px + py * py + pz * pz;
-  J A, B, C;
   if (t2.re() < 1e-2) {
     J t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4;
     A = jconst<J>(1.0) - t2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0;
@@ -132,6 +131,16 @@ XJ MPose<D, Q> se3_exp(const Jet<double, D, Q> xi[6]) {
     B = (jconst<J>(1.0) - c) / t2;
     C = (th - s) / (t2 * th);
   }
+}
+
+template <int D, int Q>
+XJ MPose<D, Q> se3_exp(const Jet<double, D, Q> xi[6]) {
+  using J = Jet<double, D, Q>;
+  const J& px = xi[0];
+  const J& py = xi[1];
+  const J& pz = xi[2];
+  J A, B, C;
+  se3_abc<D, Q>(xi, A, B, C);
   J z = jzero<J>();
   J K[9] = {z, -pz, py, pz, z, -px, -py, px, z};
   J K2[9];
@@ -152,6 +161,40 @@ XJ MPose<D, Q> se3_exp(const Jet<double, D, Q> xi[6]) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) T.m[9 + r] = Vm[r * 3 + 0] * xi[3] + Vm[r * 3 + 1] * xi[4] + Vm[r * 3 + 2] * xi[5];
   return T;
+}
+
+// One entry of exp(xi) * P, for one lane of a wave: row r (0..2) and column c
+// (0..2 rotation, 3 translation) of the 3x4 result, with the arithmetic of
+// se3_exp followed by pose_mul for that entry (each lane forms only row r of
+// exp(xi); the rows of [phi]x it needs are picked with selects, not indexing).
+template <int D, int Q>
+__device__ __forceinline__ Jet<double, D, Q> se3_exp_mul_entry(const Jet<double, D, Q> xi[6],
+                                                               const MPose<D, Q>* __restrict__ P, int r, int c) {
+  using J = Jet<double, D, Q>;
+  const J& px = xi[0];
+  const J& py = xi[1];
+  const J& pz = xi[2];
+  J A, B, C;
+  se3_abc<D, Q>(xi, A, B, C);
+  const J z = jzero<J>();
+  const J K[9] = {z, -pz, py, pz, z, -px, -py, px, z};
+  auto pick = [r](const J& a, const J& b, const J& d) { return r == 0 ? a : (r == 1 ? b : d); };
+  const J Kr[3] = {pick(K[0], K[3], K[6]), pick(K[1], K[4], K[7]), pick(K[2], K[5], K[8])};
+  J Er[3], Vr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const J K2 = Kr[0] * K[0 * 3 + k] + Kr[1] * K[1 * 3 + k] + Kr[2] * K[2 * 3 + k];
+    const J I = jconst<J>(r == k ? 1.0 : 0.0);
+    Er[k] = I + A * Kr[k] + B * K2;
+    Vr[k] = I + B * Kr[k] + C * K2;
+  }
+  const J tr = Vr[0] * xi[3] + Vr[1] * xi[4] + Vr[2] * xi[5];
+  // column c of P: rotation column c, or the translation
+  const J p0 = c < 3 ? P->m[0 * 3 + c] : P->m[9 + 0];
+  const J p1 = c < 3 ? P->m[1 * 3 + c] : P->m[9 + 1];
+  const J p2 = c < 3 ? P->m[2 * 3 + c] : P->m[9 + 2];
+  const J prod = Er[0] * p0 + Er[1] * p1 + Er[2] * p2;
+  return c < 3 ? prod : prod + tr;
 }
 
 // brick layout: brick (bx,by,bz) of 8^3 voxels stored contiguously, x fastest inside

@@ -204,6 +204,25 @@ template <typename J, typename T> XJ V3<J> vload(const T* base, size_t stride, s
   return {jload<J>(base, stride, i), jload<J>(base + J::N * stride, stride, i),
           jload<J>(base + 2 * J::N * stride, stride, i)};
 }
+// ---- loads that share one memory round trip ----------------------------------
+// pin() hands a loaded value to an empty asm statement that reads its VGPRs:
+// the load must then be issued before that point, so a later branch that does
+// not need the value cannot pull the load below itself (the compiler sinks
+// loads into the branch that uses them, one round trip per branch).  Loads
+// written side by side and pinned together wait once.
+__device__ __forceinline__ void pin(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(uint32_t& x) { asm volatile("" : "+v"(x)); }
+template <typename T, int D, int Q> __device__ __forceinline__ void pin(Jet<T, D, Q>& x) {
+#pragma unroll
+  for (int c = 0; c < Jet<T, D, Q>::N; ++c) pin(x.v[c]);
+}
+template <typename J> __device__ __forceinline__ void pin(V3<J>& a) {
+  pin(a.x);
+  pin(a.y);
+  pin(a.z);
+}
+
 template <typename J, typename T> XJ void vstore(T* base, size_t stride, size_t i, const V3<J>& v) {
   jstore(base, stride, i, v.x);
   jstore(base + J::N * stride, stride, i, v.y);

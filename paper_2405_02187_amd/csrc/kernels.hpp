@@ -477,8 +477,11 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
   using J = Jet<T, D, Q>;
   const int W = g.W, H = g.H;
   // the pixel's maps are loaded together with its flag (one memory round trip)
-  const uint8_t vi = g.valid[i];
-  const V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+  uint32_t vi = g.valid[i];
+  V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+  pin(vi);
+  pin(v);
+  pin(nv);
   if (!vi) return false;
   const V3<J> p = pose_apply(Tc, v);
   const V3<J> nr = pose_rotate(Tc, nv);
@@ -497,13 +500,27 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
   if constexpr (J::N <= 8) {
     // everything the four taps hold, in flight at once; the nearest tap
     // floor(u + 1/2) is one of them (u - floor(u + 1e-3) lies in [-1e-3, 1))
-    const uint8_t w0 = g.validm[t0], w1 = g.validm[t1], w2 = g.validm[t2], w3 = g.validm[t3];
-    const T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
-    const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-    const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
-    const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-    const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
-    if (!(w0 && w1 && w2 && w3)) return false;
+    uint32_t w01 = g.validm[t0] | uint32_t(g.validm[t1]) << 8, w23 = g.validm[t2] | uint32_t(g.validm[t3]) << 8;
+    T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
+    V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
+    V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+    V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
+    V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+    pin(w01);
+    pin(w23);
+    pin(z0);
+    pin(z1);
+    pin(z2);
+    pin(z3);
+    pin(q0);
+    pin(q1);
+    pin(q2);
+    pin(q3);
+    pin(m0);
+    pin(m1);
+    pin(m2);
+    pin(m3);
+    if (!((w01 & 0xff) && (w01 >> 8) && (w23 & 0xff) && (w23 >> 8))) return false;
     const int in = int(floor(rx + T(0.5))), jn = int(floor(ry + T(0.5)));
     const bool inside = (in == i0 || in == i0 + 1) && (jn == j0 || jn == j0 + 1);
     const int sel = (jn - j0) * 2 + (in - i0);
@@ -561,38 +578,52 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
 // Few components: per-thread sums over a few pixels, then an FP64 block tree.
 // Many components: every pixel's terms are reduced across the wave at once
 // (FP64) into per-wave LDS accumulators, so no thread holds 27 NC sums.
-// The solve after the sums (one thread): FP64 solve, relaxation, SE(3)
-// update, counters; or only the sums when they are all that is wanted.
+// The solve after the sums (one wave): FP64 solve, relaxation, SE(3) update
+// (one entry of the new pose per lane), counters; or only the sums when they
+// are all that is wanted.
 template <typename T, int D, int Q>
-__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin) {
+__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, int lane) {
   constexpr int NC = Jet<T, D, Q>::N;
   constexpr int NS = IcpSize<D, Q>::NS;
   const int cnt = int(fin[27 * NC]);
   int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
   if (!g.do_solve) {
-    for (int k = 0; k < NS; ++k) g.sums_out[k] = fin[k];
+    for (int k = lane; k < NS; k += 64) g.sums_out[k] = fin[k];
     return;
   }
-  crow[3] += cnt;
-  crow[4] = cnt;
-  if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
+  if (lane == 0) {
+    crow[3] += cnt;
+    crow[4] = cnt;
+    if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
+  }
+  // every lane solves (the same operations on the same data), so the update
+  // is known to all of them without a broadcast
   Jet<double, D, Q> dx[6];
   if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
-    *g.lost = 1;
-    crow[0] = 1;
+    if (lane == 0) {
+      *g.lost = 1;
+      crow[0] = 1;
+    }
     return;
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a) dx[a] = g.omega * dx[a];
-  {
+  if (lane == 0) {
     double nn = 0.0;
     for (int a = 0; a < 6; ++a) nn += dx[a].re() * dx[a].re();
     if (crow[32] == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
   }
-  MPose<D, Q> E = se3_exp<D, Q>(dx);
-  MPose<D, Q> Pn = pose_mul(E, *g.Pcur);
-  *g.Pcur = Pn;
-  *g.Kcur = to_kpose<T, double>(Pn);
+  // the update exp(dx) * P, one of its 12 entries per lane
+  if (lane >= 12) return;
+  const int r = lane >> 2, c = lane & 3;
+  const Jet<double, D, Q> e = se3_exp_mul_entry<D, Q>(dx, g.Pcur, r, c);
+  // (every lane has read its column of P: the lanes of one wave issue their
+  // loads together, before any of them stores)
+  __builtin_amdgcn_wave_barrier();
+  const int idx = c < 3 ? r * 3 + c : 9 + r;
+  g.Pcur->m[idx] = e;
+  Jet<T, D, Q>* ke = c < 3 ? &g.Kcur->R[r * 3 + c] : &g.Kcur->t[r];
+  *ke = jcast<T>(e);
 }
 
 
@@ -603,8 +634,9 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   constexpr int NS = IcpSize<D, Q>::NS;
   constexpr bool kRegAcc = NS <= 192;
   __shared__ double red[kIcpThreads / 64][NS];
-  if (*g.lost) return;   // set by an earlier pass of this frame
-
+  // (no test of the lost flag here: after a lost pass the pose is left as it
+  // was, these sums are computed from it and k_icp_finish drops them; a test
+  // would put one more memory round trip before the first pixel of every pass)
   const KPose<T, D, Q> Tc = *g.Kcur;
   const KPose<T, D, Q> Tp = *g.Kprev;
   const T sc = T(1) / T(1 << g.level);
@@ -719,19 +751,29 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
   constexpr int G = 16, KC = kFinishThreads / G;
   __shared__ double gs[G][KC];
   __shared__ double fin[NS];
-  if (*g.lost) return;
+  const int lost = *g.lost;   // read now, tested after the sums (its load overlaps theirs)
   const int grp = threadIdx.x / KC, kk = threadIdx.x % KC;
   const unsigned B = nblocks;
   for (int kc = 0; kc < NS; kc += KC) {
     const int k = kc + kk;
     double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (k < NS) {
-      unsigned b = grp;
-      for (; b + 7 * G < B; b += 8 * G) {
+      // the m-th workgroup of the group (b = grp + m G) goes to running sum
+      // m mod 8, in increasing m; its partials are loaded NB at a time with
+      // every load in flight together (indexes past the end are clamped and
+      // their values dropped)
+      constexpr unsigned NB = 32;
+      for (unsigned b0 = grp; b0 < B; b0 += NB * G) {
+        double v[NB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a8[u] += g.partials[size_t(b + u * G) * NS + k];
+        for (unsigned u = 0; u < NB; ++u) {
+          const unsigned b = b0 + u * G < B ? b0 + u * G : B - 1;
+          v[u] = g.partials[size_t(b) * NS + k];
+        }
+#pragma unroll
+        for (unsigned u = 0; u < NB; ++u)
+          if (b0 + u * G < B) a8[u & 7] += v[u];
       }
-      for (int u = 0; b < B; b += G, ++u) a8[u & 7] += g.partials[size_t(b) * NS + k];
     }
     gs[grp][kk] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     __syncthreads();
@@ -743,8 +785,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
     }
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  icp_finish_solve<T, D, Q>(g, fin);
+  if (threadIdx.x >= 64 || lost) return;
+  icp_finish_solve<T, D, Q>(g, fin, threadIdx.x);
 }
 
 
@@ -1171,40 +1213,74 @@ __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const t
   return true;
 }
 
+// Complex-step trilinear interpolation, in two steps so that the loads of
+// several cells can share one memory round trip: tri_fetch locates the cell of
+// a point and issues the loads of its 8 corners (records and tangents; a point
+// outside the volume loads a valid cell and is marked invalid), tri_eval checks
+// the weights and interpolates.  Valid iff inside and all 8 corners observed.
 template <typename T, int D, int Q>
-__device__ __forceinline__ bool trilinear_jet(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
-                                              const T* __restrict__ Ftan, int64_t nvox, const V3<Jet<T, D, Q>>& v,
-                                              Jet<T, D, Q>& out) {
+struct TriCell {
+  Jet<T, D, Q> f[3];   // fractional position in the cell
+  Jet<T, D, Q> c[8];   // corner values with their tangents
+  T w[8];              // corner weights
+  bool inb;            // inside the volume
+};
+
+template <typename T, int D, int Q>
+__device__ __forceinline__ void tri_fetch(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
+                                          const T* __restrict__ Ftan, int64_t nvox, const V3<Jet<T, D, Q>>& v,
+                                          TriCell<T, D, Q>& t) {
   using J = Jet<T, D, Q>;
   const J* g3[3] = {&v.x, &v.y, &v.z};
   int i0[3];
-  J f[3];
+  t.inb = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const J ga = (*g3[a] + kp.half[a]) / kp.voxel - T(0.5);
     const T fl = floor(ga.re());
-    if (!(fl >= T(0) && fl <= T(kp.dim[a] - 2))) return false;
-    i0[a] = int(fl);
-    f[a] = ga - fl;
+    const bool in = fl >= T(0) && fl <= T(kp.dim[a] - 2);
+    t.inb = t.inb && in;
+    i0[a] = in ? int(fl) : 0;
+    t.f[a] = ga - fl;
   }
-  J c[8];
-  bool ok = true;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int64_t id = vox_index(i0[0] + (k & 1), i0[1] + ((k >> 1) & 1), i0[2] + (k >> 2), kp.nbr);
     const auto r = rec[id];
-    ok = ok & (r.y > T(0));
-    c[k].v[0] = r.x;
+    t.w[k] = r.y;
+    t.c[k].v[0] = r.x;
 #pragma unroll
-    for (int q = 1; q < J::N; ++q) c[k].v[q] = Ftan[size_t(q - 1) * nvox + id];
+    for (int q = 1; q < J::N; ++q) t.c[k].v[q] = Ftan[size_t(q - 1) * nvox + id];
   }
+}
+
+// keeps the loads of a fetched cell ahead of the next branch (few components
+// only: many components would hold too many registers in flight)
+template <typename T, int D, int Q>
+__device__ __forceinline__ void tri_pin(TriCell<T, D, Q>& t) {
+  if constexpr (Jet<T, D, Q>::N <= 4) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      pin(t.w[k]);
+      pin(t.c[k]);
+    }
+  }
+}
+
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool tri_eval(const TriCell<T, D, Q>& t, Jet<T, D, Q>& out) {
+  using J = Jet<T, D, Q>;
+  bool ok = t.inb;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ok = ok & (t.w[k] > T(0));
   if (!ok) return false;
+  const J* c = t.c;
   const J one = jconst<J>(T(1));
-  const J fx1 = one - f[0], fy1 = one - f[1], fz1 = one - f[2];
-  const J c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
-  const J c01 = fx1 * c[4] + f[0] * c[5], c11 = fx1 * c[6] + f[0] * c[7];
-  const J c0 = fy1 * c00 + f[1] * c10, c1 = fy1 * c01 + f[1] * c11;
-  out = fz1 * c0 + f[2] * c1;
+  const J fx1 = one - t.f[0], fy1 = one - t.f[1], fz1 = one - t.f[2];
+  const J c00 = fx1 * c[0] + t.f[0] * c[1], c10 = fx1 * c[2] + t.f[0] * c[3];
+  const J c01 = fx1 * c[4] + t.f[0] * c[5], c11 = fx1 * c[6] + t.f[0] * c[7];
+  const J c0 = fy1 * c00 + t.f[1] * c10, c1 = fy1 * c01 + t.f[1] * c11;
+  out = fz1 * c0 + t.f[2] * c1;
   return true;
 }
 
@@ -1327,9 +1403,18 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
       J F0, F1;
       const V3<J> v0 = vadd(o, vscale(jconst<J>(a_prev), dir));
       const V3<J> v1 = vadd(o, vscale(jconst<J>(alpha), dir));
-      const bool ok0 = trilinear_jet(kp, rec, Ftan, nvox, v0, F0);
-      const bool ok1 = trilinear_jet(kp, rec, Ftan, nvox, v1, F1);
-      if (ok0 && ok1) {
+      bool ok01;
+      {
+        TriCell<T, D, Q> t0, t1;
+        tri_fetch(kp, rec, Ftan, nvox, v0, t0);
+        tri_fetch(kp, rec, Ftan, nvox, v1, t1);
+        tri_pin(t0);
+        tri_pin(t1);
+        const bool ok0 = tri_eval(t0, F0);
+        const bool ok1 = tri_eval(t1, F1);
+        ok01 = ok0 && ok1;
+      }
+      if (ok01) {
         const J a0 = jconst<J>(a_prev) - jconst<J>(alpha - a_prev) * F0 / (F1 - F0);
         const V3<J> V = vadd(o, vscale(a0, dir));
         J gr[3];
@@ -1340,8 +1425,16 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
           if (a == 0) { vp.x = V.x + s; vm.x = V.x - s; }
           if (a == 1) { vp.y = V.y + s; vm.y = V.y - s; }
           if (a == 2) { vp.z = V.z + s; vm.z = V.z - s; }
+          // the two cells of one axis in flight together
+          TriCell<T, D, Q> tp, tm;
+          tri_fetch(kp, rec, Ftan, nvox, vp, tp);
+          tri_fetch(kp, rec, Ftan, nvox, vm, tm);
+          tri_pin(tp);
+          tri_pin(tm);
           J fp, fm;
-          okg = okg && trilinear_jet(kp, rec, Ftan, nvox, vp, fp) && trilinear_jet(kp, rec, Ftan, nvox, vm, fm);
+          const bool okp = tri_eval(tp, fp);
+          const bool okm = tri_eval(tm, fm);
+          okg = okg && okp && okm;
           if (okg) gr[a] = fp - fm;
         }
         if (okg) {
