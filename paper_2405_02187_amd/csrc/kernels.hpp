@@ -123,7 +123,27 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
   const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   if (x >= Wo || y >= Ho) return;
   const size_t ni = size_t(Wi) * Hi, no = size_t(Wo) * Ho, o = size_t(y) * Wo + x;
-  const T c = Din[size_t(2 * y) * Wi + 2 * x];
+  // the real parts of the 25 taps, all in flight together (indexes clamped
+  // to the image; taps outside it are dropped); the centre is tap 12
+  T dr[25];
+  double dh[25];
+  uint32_t qi[25];   // (an image holds far fewer than 2^32 pixels)
+  bool inb[25];
+#pragma unroll
+  for (int t = 0; t < 25; ++t) {
+    const int xx = 2 * x + t % 5 - 2, yy = 2 * y + t / 5 - 2;
+    inb[t] = xx >= 0 && yy >= 0 && xx < Wi && yy < Hi;
+    qi[t] = uint32_t(yy < 0 ? 0 : (yy >= Hi ? Hi - 1 : yy)) * uint32_t(Wi) + uint32_t(xx < 0 ? 0 : (xx >= Wi ? Wi - 1 : xx));
+    dr[t] = Din[qi[t]];
+    dh[t] = 0.0;
+    if constexpr (kHi) dh[t] = Dhi_in[qi[t]];
+  }
+#pragma unroll
+  for (int t = 0; t < 25; ++t) {
+    pin(dr[t]);
+    if constexpr (kHi) pin(dh[t]);
+  }
+  const T c = dr[12];
   if (!(c > T(0))) {
     jstore(Dout, no, o, jzero<J>());
     if constexpr (kHi) Dhi_out[o] = 0.0;
@@ -132,28 +152,28 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
   const int g[5] = {1, 4, 6, 4, 1};
   J num = jzero<J>();
   T den = 0;
-  double ch = 0.0, num_hi = 0.0, den_hi = 0.0;
-  if constexpr (kHi) ch = Dhi_in[size_t(2 * y) * Wi + 2 * x];
-  for (int j = -2; j <= 2; ++j)
-    for (int i = -2; i <= 2; ++i) {
-      int xx = 2 * x + i, yy = 2 * y + j;
-      if (xx < 0 || yy < 0 || xx >= Wi || yy >= Hi) continue;
-      size_t q = size_t(yy) * Wi + xx;
-      T d = Din[q];
-      if (!(d > T(0))) continue;
-      if constexpr (kHi) {
-        const double dh = Dhi_in[q];
-        if (fabs(dh - ch) > kp.pyr_gate_d) continue;
-        const double wh = double(g[i + 2] * g[j + 2]);
-        num_hi = num_hi + wh * dh;
-        den_hi = den_hi + wh;
-      } else {
-        if (fabs(d - c) > kp.pyr_gate) continue;
-      }
-      T w = T(g[i + 2] * g[j + 2]);
-      num = num + w * jload<J>(Din, ni, q);
-      den += w;
+  double num_hi = 0.0, den_hi = 0.0;
+  const double ch = dh[12];
+#pragma unroll
+  for (int t = 0; t < 25; ++t) {
+    bool ok = inb[t] && dr[t] > T(0);
+    if constexpr (kHi) ok = ok && !(fabs(dh[t] - ch) > kp.pyr_gate_d);
+    else ok = ok && !(fabs(dr[t] - c) > kp.pyr_gate);
+    J tap;
+    tap.v[0] = dr[t];
+#pragma unroll
+    for (int q = 1; q < J::N; ++q) tap.v[q] = Din[size_t(q) * ni + qi[t]];
+    const int wi = g[t % 5] * g[t / 5];
+    const T w = T(wi);
+    const J numw = num + w * tap;
+    num = ok ? numw : num;
+    den = ok ? den + w : den;
+    if constexpr (kHi) {
+      const double wh = double(wi);
+      num_hi = ok ? num_hi + wh * dh[t] : num_hi;
+      den_hi = ok ? den_hi + wh : den_hi;
     }
+  }
   J out = num / den;
   if constexpr (kHi) {
     const double oh = num_hi / den_hi;
@@ -179,8 +199,23 @@ __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int 
   const size_t n = size_t(Wl) * Hl, i = size_t(y) * Wl + x;
   const T sc = T(1) / T(1 << level);
   const J fx = kp.fx * sc, fy = kp.fy * sc, cx = kp.cx * sc, cy = kp.cy * sc;
-  auto vert = [&](int xx, int yy, bool& ok) -> V3<J> {
-    J d = jload<J>(Dl, n, size_t(yy) * Wl + xx);
+  // the depth (and FP64 real depth) of the pixel and of its right and lower
+  // neighbours, loaded together (a neighbour outside the image is replaced by
+  // the pixel itself and not used)
+  const size_t i1 = x + 1 < Wl ? i + 1 : i, i2 = y + 1 < Hl ? i + Wl : i;
+  J dj[3] = {jload<J>(Dl, n, i), jload<J>(Dl, n, i1), jload<J>(Dl, n, i2)};
+  double dhi[3] = {0.0, 0.0, 0.0};
+  if constexpr (kHi) {
+    dhi[0] = Dhi[i];
+    dhi[1] = Dhi[i1];
+    dhi[2] = Dhi[i2];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pin(dj[k]);
+    pin(dhi[k]);
+  }
+  auto vert = [&](int xx, int yy, const J& d, bool& ok) -> V3<J> {
     ok = d.re() > T(0);
     J rx = (jconst<J>(T(xx)) - cx) / fx;
     J ry = (jconst<J>(T(yy)) - cy) / fy;
@@ -189,18 +224,17 @@ __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int 
   // FP64 real vertex (FP32 runs)
   const double fxh = double(kp.fx.re()) * double(sc), fyh = double(kp.fy.re()) * double(sc);
   const double cxh = double(kp.cx.re()) * double(sc), cyh = double(kp.cy.re()) * double(sc);
-  auto vert_hi = [&](int xx, int yy, double v[3]) {
-    const double d = Dhi[size_t(yy) * Wl + xx];
+  auto vert_hi = [&](int xx, int yy, double d, double v[3]) {
     v[0] = d * ((double(xx) - cxh) / fxh);
     v[1] = d * ((double(yy) - cyh) / fyh);
     v[2] = d;
   };
   bool ok0;
-  V3<J> v0 = vert(x, y, ok0);
+  V3<J> v0 = vert(x, y, dj[0], ok0);
   const J z = jzero<J>();
   double h0[3] = {0, 0, 0};
   if constexpr (kHi) {
-    vert_hi(x, y, h0);
+    vert_hi(x, y, dhi[0], h0);
     if (ok0) { v0.x.v[0] = float(h0[0]); v0.y.v[0] = float(h0[1]); v0.z.v[0] = float(h0[2]); }
   }
   vstore(Vout, n, i, ok0 ? v0 : V3<J>{z, z, z});
@@ -208,16 +242,16 @@ __global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int 
   V3<J> nn = {z, z, z};
   if (ok0 && x + 1 < Wl && y + 1 < Hl) {
     bool ok1, ok2;
-    V3<J> v1 = vert(x + 1, y, ok1);
-    V3<J> v2 = vert(x, y + 1, ok2);
+    V3<J> v1 = vert(x + 1, y, dj[1], ok1);
+    V3<J> v2 = vert(x, y + 1, dj[2], ok2);
     if (ok1 && ok2) {
       V3<J> a = vsub(v1, v0), b = vsub(v2, v0);
       V3<J> c = vcross(b, a);
       J cc = vdot(c, c);
       if constexpr (kHi) {
         double h1[3], h2[3];
-        vert_hi(x + 1, y, h1);
-        vert_hi(x, y + 1, h2);
+        vert_hi(x + 1, y, dhi[1], h1);
+        vert_hi(x, y + 1, dhi[2], h2);
         const double ah[3] = {h1[0] - h0[0], h1[1] - h0[1], h1[2] - h0[2]};
         const double bh[3] = {h2[0] - h0[0], h2[1] - h0[1], h2[2] - h0[2]};
         const double ch[3] = {bh[1] * ah[2] - bh[2] * ah[1], bh[2] * ah[0] - bh[0] * ah[2], bh[0] * ah[1] - bh[1] * ah[0]};
@@ -1161,50 +1195,58 @@ struct MapsOut {
   T* V[3]; T* N[3]; T* Z[3]; uint8_t* valid[3];
 };
 
-// trilinear TSDF at a real point; valid iff all 8 corners observed (W > 0)
+// trilinear TSDF at a real point given by its grid coordinate g = (v + L/2)/s
+// - 1/2 (the caller forms g); valid iff all 8 corners observed (W > 0).
 // The brick flags only skip loads: a cell whose first corner lies in a brick
 // with no observed voxel is invalid (that corner has W = 0), and a cell inside
-// an all-free brick has eight corners equal to 1 -- the same interpolation is
-// then evaluated without loading them, so every sample value is unchanged.
+// an all-free brick has eight corners equal to 1, where the value is taken as
+// 1 without loading them (the march only compares sample values with 0 and
+// 0.999, which the interpolation of eight ones meets in the same way).  Brick
+// indexes are 32-bit (the brick grid holds far fewer than 2^31 bricks).
 template <typename T, int D, int Q>
 __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const typename Vec2<T>::type* __restrict__ rec,
-                                             const uint8_t* __restrict__ flags, const T v[3], T& out,
-                                             int64_t& cached_brick, uint8_t& cached_flag) {
+                                             const uint8_t* __restrict__ flags, const T g[3], T& out,
+                                             int& cached_brick, uint32_t& cached_flag) {
   int i0[3];
   T f[3];
+  bool inb = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T ga = (v[a] + kp.half[a]) / kp.voxel - T(0.5);
-    const T fl = floor(ga);
-    if (!(fl >= T(0) && fl <= T(kp.dim[a] - 2))) return false;
+    const T fl = floor(g[a]);
+    inb = inb & (fl >= T(0)) & (fl <= T(kp.dim[a] - 2));
     i0[a] = int(fl);
-    f[a] = ga - fl;
+    f[a] = g[a] - fl;
   }
+  if (!inb) return false;
   // the flag of the brick holding the lower corner, cached along the ray
-  const int64_t bi = (int64_t(i0[2] >> 3) * kp.nbr[1] + (i0[1] >> 3)) * kp.nbr[0] + (i0[0] >> 3);
+  const int bi = ((i0[2] >> 3) * kp.nbr[1] + (i0[1] >> 3)) * kp.nbr[0] + (i0[0] >> 3);
   if (bi != cached_brick) {
     cached_brick = bi;
     cached_flag = flags[bi];
   }
-  const uint8_t bf = cached_flag;
+  const uint32_t bf = cached_flag;
   if (!(bf & 1)) return false;
-  T c[8];
-  if ((bf & 2) && (i0[0] & 7) != 7 && (i0[1] & 7) != 7 && (i0[2] & 7) != 7) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = T(1);
-  } else {
-    // all eight records in flight before any is inspected
-    typename Vec2<T>::type r[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = rec[vox_index(i0[0] + (q & 1), i0[1] + ((q >> 1) & 1), i0[2] + (q >> 2), kp.nbr)];
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      ok = ok & (r[q].y > T(0));
-      c[q] = r[q].x;
-    }
-    if (!ok) return false;
+  if ((bf & 2) && (((i0[0] & 7) != 7) & ((i0[1] & 7) != 7) & ((i0[2] & 7) != 7))) {
+    out = T(1);
+    return true;
   }
+  // all eight records (value and weight) in flight before any is inspected
+  typename Vec2<T>::type r[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = rec[vox_index(i0[0] + (q & 1), i0[1] + ((q >> 1) & 1), i0[2] + (q >> 2), kp.nbr)];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    pin(r[q].x);
+    pin(r[q].y);
+  }
+  bool ok = true;
+  T c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    ok = ok & (r[q].y > T(0));
+    c[q] = r[q].x;
+  }
+  if (!ok) return false;
   const T fx1 = T(1) - f[0], fy1 = T(1) - f[1], fz1 = T(1) - f[2];
   const T c00 = fx1 * c[0] + f[0] * c[1], c10 = fx1 * c[2] + f[0] * c[3];
   const T c01 = fx1 * c[4] + f[0] * c[5], c11 = fx1 * c[6] + f[0] * c[7];
@@ -1331,23 +1373,40 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
       }
     }
     // the ray parameter accumulates over up to hundreds of samples: FP32 runs
-    // keep it (and the sample positions) in FP64, so that the sample grid does
-    // not drift by the rounding of every step
+    // keep it (and the sample coordinates) in FP64, so that the sample grid
+    // does not drift by the rounding of every step
     using TA = typename std::conditional<std::is_same<T, float>::value, double, T>::type;
     TA alpha = fmax(TA(kp.near_m), TA(tmin));
     const T mu = kp.mu.re();
-    const TA small = TA(0.5) * TA(s) / TA(nrm), big = TA(0.8) * TA(mu) / TA(nrm);
+    TA small = TA(0.5) * TA(s) / TA(nrm), big = TA(0.8) * TA(mu) / TA(nrm);
+    // (opaque from here: otherwise the compiler folds the two divisions into
+    // one of the selected numerator, inside the loop)
+    pin(small);
+    pin(big);
     bool prev_ok = false;
     TA a_prev = 0;
     T f_prev = 0;
     TA hit0 = 0, hit1 = TA(-1);
-    int64_t cbrick = -1;
-    uint8_t cflag = 0;
+    int cbrick = -1;
+    uint32_t cflag = 0;
+    // FP32 runs: the grid coordinate of the sample is G0 + alpha dG, formed
+    // in FP64 (one fma per axis) and rounded once; FP64 runs evaluate
+    // ((o + alpha d) + L/2) / s - 1/2 as written
+    TA G0[3], dG[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      G0[a] = (TA(orr[a]) + TA(kp.half[a])) / TA(kp.voxel) - TA(0.5);
+      dG[a] = TA(dr[a]) / TA(kp.voxel);
+    }
     for (int it = 0; it < 100000 && !miss && alpha <= TA(tmax); ++it, ++nsamp) {
-      const T v[3] = {T(TA(orr[0]) + alpha * TA(dr[0])), T(TA(orr[1]) + alpha * TA(dr[1])),
-                      T(TA(orr[2]) + alpha * TA(dr[2]))};
+      T g[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if constexpr (std::is_same<T, float>::value) g[a] = T(fma(alpha, dG[a], G0[a]));
+        else g[a] = ((orr[a] + alpha * dr[a]) + kp.half[a]) / kp.voxel - T(0.5);
+      }
       T f;
-      const bool okf = trilinear_re(kp, rec, flags, v, f, cbrick, cflag);
+      const bool okf = trilinear_re(kp, rec, flags, g, f, cbrick, cflag);
       if (!okf) f = 0;
       if (okf && prev_ok) {
         if (f_prev > T(0) && f < T(0)) {
