@@ -65,10 +65,39 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
   const size_t n = size_t(W) * H;
   const int x0 = blockIdx.x * kBilTile - kBilMaxR, y0 = blockIdx.y * kBilTile - kBilMaxR;
   const int tid = threadIdx.y * kBilTile + threadIdx.x;
-  for (int q = tid; q < S * S; q += kBilTile * kBilTile) {
-    int xx = x0 + q % S, yy = y0 + q / S;
+  // the tile's raw depths and depth tangents, every load in flight together
+  // (coordinates clamped to the image; entries outside it are zero), then
+  // promoted to jets as promote_depth does
+  constexpr int NQ = (S * S + kBilTile * kBilTile - 1) / (kBilTile * kBilTile);
+  T dv[NQ], tv[NQ][D > 0 ? D : 1];
+  bool in[NQ];
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const int q = tid + u * kBilTile * kBilTile;
+    const int xx = x0 + q % S, yy = y0 + q / S;
+    in[u] = q < S * S && xx >= 0 && yy >= 0 && xx < W && yy < H;
+    const size_t qi = size_t(yy < 0 ? 0 : (yy >= H ? H - 1 : yy)) * W + (xx < 0 ? 0 : (xx >= W ? W - 1 : xx));
+    dv[u] = depth[qi];
+#pragma unroll
+    for (int k = 0; k < D; ++k) tv[u][k] = kp.depth_plane[k] >= 0 ? ddot[size_t(kp.depth_plane[k]) * n + qi] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    pin(dv[u]);
+#pragma unroll
+    for (int k = 0; k < D; ++k) pin(tv[u][k]);
+  }
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const int q = tid + u * kBilTile * kBilTile;
+    if (q >= S * S) continue;
     J v = jzero<J>();
-    if (xx >= 0 && yy >= 0 && xx < W && yy < H) v = promote_depth(kp, depth, ddot, n, size_t(yy) * W + xx);
+    if (in[u] && dv[u] > T(0) && isfinite(dv[u])) {
+      v.v[0] = dv[u];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if (kp.depth_plane[k] >= 0) v.v[1 + k] = kp.depth_h[k] * tv[u][k];
+    }
     tile[q] = v;
   }
   __syncthreads();
@@ -91,15 +120,21 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
       if (!(d.re() > T(0))) continue;
       J dd = c - d;
       J arg = jconst<J>(T(dx * dx + dy * dy) * kp.bil_is) + (dd * dd) * kp.bil_ir;
-      J w = jexp(-arg);
-      num = num + w * d;
-      den = den + w;
+      J w;
       if constexpr (kHi) {
+        // one exponential per tap, in FP64; the jet weight takes it rounded
+        // as its value and for the chain rule of its imaginary parts
         const double ddh = double(c.re()) - double(d.re());
         const double wh = exp(-(double(dx * dx + dy * dy) * kp.bil_is_d + (ddh * ddh) * kp.bil_ir_d));
         num_hi = num_hi + wh * double(d.re());
         den_hi = den_hi + wh;
+        const T e = T(wh);
+        w = chain(-arg, e, e, e);
+      } else {
+        w = jexp(-arg);
       }
+      num = num + w * d;
+      den = den + w;
     }
   J out = num / den;
   if constexpr (kHi) {
