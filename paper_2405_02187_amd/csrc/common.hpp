@@ -120,10 +120,13 @@ XJ void se3_abc(const Jet<double, D, Q> xi[6], Jet<double, D, Q>& A, Jet<double,
   const J& pz = xi[2];
   J t2 = px * px + py * py + pz * pz;
   if (t2.re() < 1e-2) {
+    // (the coefficients 1/k! are rounded constants: a product per term
+    // instead of a division, well inside the series' own truncation error)
     J t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4;
-    A = jconst<J>(1.0) - t2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0;
-    B = jconst<J>(0.5) - t2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0;
-    C = jconst<J>(1.0 / 6.0) - t2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0;
+    A = jconst<J>(1.0) - t2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t6 * (1.0 / 5040.0) + t8 * (1.0 / 362880.0);
+    B = jconst<J>(0.5) - t2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t6 * (1.0 / 40320.0) + t8 * (1.0 / 3628800.0);
+    C = jconst<J>(1.0 / 6.0) - t2 * (1.0 / 120.0) + t4 * (1.0 / 5040.0) - t6 * (1.0 / 362880.0) +
+        t8 * (1.0 / 39916800.0);
   } else {
     J th = jsqrt(t2);
     J s = jsin(th), c = jcos(th);

@@ -475,16 +475,19 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
     for (int b = a; b < 6; ++b, ++k) { A0[a][b] = sums[k * NC]; A0[b][a] = sums[k * NC]; }
   double dmax = 0.0;
   for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A0[a][a]);
+  // (one division per pivot: the factor and the solves multiply by 1/d_j)
+  double idd[6];
   for (int j = 0; j < 6; ++j) {
     double s = A0[j][j];
     for (int q = 0; q < j; ++q) s -= L[j][q] * L[j][q] * dd[q];
     if (!(s > 1e-12 * dmax)) return false;
     dd[j] = s;
+    idd[j] = 1.0 / s;
     L[j][j] = 1.0;
     for (int i = j + 1; i < 6; ++i) {
       double t = A0[i][j];
       for (int q = 0; q < j; ++q) t -= L[i][q] * L[j][q] * dd[q];
-      L[i][j] = t / s;
+      L[i][j] = t * idd[j];
     }
   }
   auto solve = [&](const double rhs[6], double x[6]) {
@@ -495,7 +498,7 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
       y[i] = t;
     }
     for (int i = 5; i >= 0; --i) {
-      double t = y[i] / dd[i];
+      double t = y[i] * idd[i];
       for (int q = i + 1; q < 6; ++q) t -= L[q][i] * x[q];
       x[i] = t;
     }
