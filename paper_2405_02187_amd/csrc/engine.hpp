@@ -300,12 +300,21 @@ struct Engine : EngineBase {
     return XSLAM_OK;
   }
 
-  int run_measure() {
+  TrackBegin<T, D, Q> track_begin_args() const {
+    return TrackBegin<T, D, Q>{Pcur, Pprev, Pprev2, Pinit, Kcur, Kprev, lost, counters, dframe, C->cfg.max_frames,
+                               C->cfg.icp.init >= 1 ? 1 : 0};
+  }
+
+  // begin_track: the bilateral launch also starts the tracking of the frame
+  // (k_track_begin's work, folded into the first launch of a tracked frame)
+  int run_measure(bool begin_track = false) {
     int rc;
     dim3 b(16, 16);
     dim3 g0((W[0] + 15) / 16, (H[0] + 15) / 16);
+    TrackBegin<T, D, Q> tb{};
+    if (begin_track) tb = track_begin_args();
     if ((rc = launch(0, "bilateral", [&] {
-           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0]);
+           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0], tb);
          })))
       return rc;
     for (int l = 1; l < 3; ++l) {
@@ -349,15 +358,14 @@ struct Engine : EngineBase {
     });
   }
 
-  int run_track() {
+  // begun: the tracking of the frame was started by run_measure(true)
+  int run_track(bool begun = false) {
     int rc;
     if (!measured) return fail(XSLAM_ERR_STATE, "track: no measured frame");
     if (!have_model) return fail(XSLAM_ERR_STATE, "track: no model maps (raycast first)");
-    if ((rc = launch(4, "track_begin", [&] {
-           hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pprev, Pprev2, Pinit,
-                              Kcur, Kprev, lost, counters, dframe, C->cfg.max_frames,
-                              C->cfg.icp.init >= 1 ? 1 : 0);
-         })))
+    if (!begun && (rc = launch(4, "track_begin", [&] {
+                    hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, track_begin_args());
+                  })))
       return rc;
     if (C->cfg.icp.init == 2 && cnn && (rc = learned_init())) return rc;
     int slot = 0;
@@ -520,14 +528,17 @@ struct Engine : EngineBase {
   }
 
   // fusion: per-tile depth bound, brick culling, list-driven update, brick
-  // flags (the brick count must have been reset by post_track)
-  int run_fuse() {
+  // flags.  The brick count is reset by the end-of-tracking work, which the
+  // first launch here does too (post_track(tracked, store) folded in).
+  int run_fuse(bool tracked, bool store) {
     int rc;
     const int ntx = (W[0] + kTile - 1) / kTile, nty = (H[0] + kTile - 1) / kTile;
     const int ncx = (ntx + kCell - 1) / kCell, ncy = (nty + kCell - 1) / kCell;
+    const PostTrack<T, D, Q> post{Pcur, Pinit, Kcur, tracked ? lost : nullptr, store ? hist : nullptr,
+                                  dframe, C->cfg.max_frames, bcount};
     if ((rc = launch(4, "tile_zmax", [&] {
-           hipLaunchKernelGGL(k_tile_zmax<T>, dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax,
-                              czmax);
+           hipLaunchKernelGGL((k_tile_zmax<T, D, Q>), dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0],
+                              tzmax, czmax, post);
          })))
       return rc;
     if ((rc = launch(7, "brick_cull", [&] {
@@ -541,13 +552,10 @@ struct Engine : EngineBase {
                               Wtan, lost, nvox, blist, bcount, fcounts);
          })))
       return rc;
-    if ((rc = launch(4, "sum_counts", [&] {
-           hipLaunchKernelGGL(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, fcounts, g, nullptr, 0, counters,
-                              dframe, C->cfg.max_frames, 1, 0, bcount, 30);
-         })))
-      return rc;
+    // (the brick flags' workgroup 0 also sums the fusion counts)
     return launch(4, "brick_flags", [&] {
-      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick);
+      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick,
+                         fcounts, g, counters, dframe, C->cfg.max_frames);
     });
   }
 
@@ -555,12 +563,14 @@ struct Engine : EngineBase {
     const int g = std::min(nbrick, 4096);
     int rc = launch(4, "brick_flags_all", [&] {
       hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, nullptr, nullptr,
-                         nbrick);
+                         nbrick, nullptr, 0, nullptr, nullptr, 0);
     });
     return rc ? rc : sync();
   }
 
-  int run_raycast() {
+  // end_frame: the counter sums also advance the frame index (the frame's
+  // last launch)
+  int run_raycast(bool end_frame = false) {
     MapsOut<T, D, Q> o;
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
     dim3 b(ray_bx, ray_by), g((W[0] + ray_bx - 1) / ray_bx, (H[0] + ray_by - 1) / ray_by);
@@ -575,17 +585,12 @@ struct Engine : EngineBase {
     const int nrb = int(g.x * g.y);
     rc = launch(4, "sum_counts", [&] {
       hipLaunchKernelGGL(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, rsamples, nrb, counters,
-                         dframe, C->cfg.max_frames, 2, 31, nullptr, 0);
+                         dframe, C->cfg.max_frames, 2, 31, nullptr, 0, end_frame ? dframe : nullptr);
     });
     if (!rc) have_model = true;
     return rc;
   }
 
-  int frame_end() {
-    return launch(4, "frame_end", [&] {
-      hipLaunchKernelGGL(k_frame_end<T>, dim3(1), dim3(64), 0, C->stream, dframe);
-    });
-  }
 
   int reset_frame_flags() {
     int rc = fill<int>(lost, 0, 1);
@@ -596,12 +601,10 @@ struct Engine : EngineBase {
   // the device work of one tracked frame (captured once into a graph)
   int enqueue_tracked_frame() {
     int rc;
-    if ((rc = run_measure())) return rc;
-    if ((rc = run_track())) return rc;
-    if ((rc = post_track(true, true))) return rc;
-    if ((rc = run_fuse())) return rc;
-    if ((rc = run_raycast())) return rc;
-    return frame_end();
+    if ((rc = run_measure(true))) return rc;
+    if ((rc = run_track(true))) return rc;
+    if ((rc = run_fuse(true, true))) return rc;
+    return run_raycast(true);
   }
 
   // ---- EngineBase ---------------------------------------------------------
@@ -615,8 +618,7 @@ struct Engine : EngineBase {
     if (!measured) return fail(XSLAM_ERR_STATE, "integrate: no measured frame");
     if (pose && (rc = set_real_pose(pose))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
-    if ((rc = post_track(false, false))) return rc;
-    return run_fuse();
+    return run_fuse(false, false);
   }
 
   int raycast(const double* pose, void* vmap, void* nmap) override {
@@ -644,10 +646,8 @@ struct Engine : EngineBase {
     if (frame == 0) {
       if ((rc = reset_frame_flags())) return rc;
       if ((rc = run_measure())) return rc;
-      if ((rc = post_track(false, true))) return rc;
-      if ((rc = run_fuse())) return rc;
-      if ((rc = run_raycast())) return rc;
-      if ((rc = frame_end())) return rc;
+      if ((rc = run_fuse(false, true))) return rc;
+      if ((rc = run_raycast(true))) return rc;
     } else {
       if (!have_model) return fail(XSLAM_ERR_STATE, "step: no model maps");
       measured = true;

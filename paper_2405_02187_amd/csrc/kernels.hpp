@@ -50,10 +50,15 @@ __device__ __forceinline__ Jet<T, D, Q> promote_depth(const KParams<T, D, Q>& kp
 // the depth tangents), one thread per output pixel.
 constexpr int kBilTile = 16;
 constexpr int kBilMaxR = 4;
+template <typename T, int D, int Q> struct TrackBegin;
+template <typename T, int D, int Q> __device__ void track_begin_work(const TrackBegin<T, D, Q>& a);
+// (tb.lost != nullptr: workgroup 0 also starts the tracking of the frame,
+// which only the kernels after this one read; see k_track_begin)
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T* __restrict__ depth,
                                                    const T* __restrict__ ddot, T* __restrict__ Dout,
-                                                   double* __restrict__ Dhi) {
+                                                   double* __restrict__ Dhi, TrackBegin<T, D, Q> tb) {
+  if (tb.lost && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) track_begin_work(tb);
   // FP32 runs evaluate the real part in FP64 as well (Dhi) and store it rounded:
   // normals are differences of neighbouring vertices a few mm apart at metres of
   // depth, which FP32 accumulation would leave with ~1e-4 rad errors
@@ -867,19 +872,32 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
 // both previous frames were tracked (after a lost frame the velocity is
 // unknown, and extrapolating a guess would never re-acquire the camera)
 template <typename T, int D, int Q>
-__global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>* Pprev2, MPose<D, Q>* Pinit,
-                              KPose<T, D, Q>* Kcur, KPose<T, D, Q>* Kprev, int* lost, int32_t* counter_base,
-                              const int* frame, int max_frames, int const_vel) {
-  int32_t* counters = counter_row(counter_base, frame, max_frames);
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  *Pprev2 = *Pprev;
-  *Pprev = *Pcur;
-  MPose<D, Q> init = *Pprev;
-  const int k = *frame;
-  if (const_vel && k > 1 && k - 1 < max_frames) {
+struct TrackBegin {
+  MPose<D, Q>* Pcur;
+  MPose<D, Q>* Pprev;
+  MPose<D, Q>* Pprev2;
+  MPose<D, Q>* Pinit;
+  KPose<T, D, Q>* Kcur;
+  KPose<T, D, Q>* Kprev;
+  int* lost;                // nullptr: nothing to do
+  int32_t* counter_base;
+  const int* frame;
+  int max_frames;
+  int const_vel;
+};
+template <typename T, int D, int Q>
+__device__ void track_begin_work(const TrackBegin<T, D, Q>& a) {
+  int32_t* counters = counter_row(a.counter_base, a.frame, a.max_frames);
+  *a.Pprev2 = *a.Pprev;
+  *a.Pprev = *a.Pcur;
+  MPose<D, Q> init = *a.Pprev;
+  const int k = *a.frame;
+  const int max_frames = a.max_frames;
+  int32_t* counter_base = a.counter_base;
+  if (a.const_vel && k > 1 && k - 1 < max_frames) {
     const bool tracked = counter_base[size_t(kCounters) * (k - 1)] == 0 && counter_base[size_t(kCounters) * (k - 2)] == 0;
     if (tracked) {
-      init = pose_mul(*Pprev, pose_mul(pose_inverse(*Pprev2), *Pprev));
+      init = pose_mul(*a.Pprev, pose_mul(pose_inverse(*a.Pprev2), *a.Pprev));
       // R1 R2^T R1 triples the rotation's departure from orthonormality, and
       // the next prediction starts from it: two Newton steps of the polar
       // decomposition, R <- (3R - R R^T R)/2, keep it at rounding level
@@ -899,12 +917,17 @@ __global__ void k_track_begin(MPose<D, Q>* Pcur, MPose<D, Q>* Pprev, MPose<D, Q>
       }
     }
   }
-  *Pinit = init;
-  *Pcur = init;
-  *Kcur = to_kpose<T, double>(init);
-  *Kprev = to_kpose<T, double>(*Pprev);
-  *lost = 0;
+  *a.Pinit = init;
+  *a.Pcur = init;
+  *a.Kcur = to_kpose<T, double>(init);
+  *a.Kprev = to_kpose<T, double>(*a.Pprev);
+  *a.lost = 0;
   for (int i = 0; i < kCounters; ++i) counters[i] = 0;
+}
+template <typename T, int D, int Q>
+__global__ void k_track_begin(TrackBegin<T, D, Q> a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  track_begin_work(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,9 +948,36 @@ constexpr int kTile = 16;
 // 64x64 cell of 4x4 tiles (cmax): one workgroup per cell, 16 lanes per tile,
 // each lane one tile row.
 constexpr int kCell = 4;   // tiles per coarse cell and axis
-template <typename T>
+
+// End of tracking (a lost frame keeps its initial estimate), pose history, and
+// the reset of the brick list for fusion; one thread.
+template <typename T, int D, int Q>
+struct PostTrack {
+  MPose<D, Q>* Pcur;
+  const MPose<D, Q>* Pinit;
+  KPose<T, D, Q>* Kcur;
+  const int* lost;        // nullptr: the frame was not tracked
+  MPose<D, Q>* history;   // nullptr: no history entry
+  const int* frame;
+  int max_frames;
+  int* count;
+};
+template <typename T, int D, int Q>
+__device__ void post_track_work(const PostTrack<T, D, Q>& a) {
+  if (a.lost && *a.lost) {
+    *a.Pcur = *a.Pinit;
+    *a.Kcur = to_kpose<T, double>(*a.Pinit);
+  }
+  if (a.history) a.history[min(*a.frame, a.max_frames - 1)] = *a.Pcur;
+  *a.count = 0;
+}
+
+// (post.count != nullptr: workgroup 0 also does the end-of-tracking work, which
+// the kernels after this one read)
+template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax,
-                                                   T* __restrict__ cmax) {
+                                                   T* __restrict__ cmax, PostTrack<T, D, Q> post) {
+  if (post.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) post_track_work(post);
   const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
   const int tile = threadIdx.x >> 4, row = threadIdx.x & 15;
   const int tx = blockIdx.x * kCell + (tile & 3), ty = blockIdx.y * kCell + (tile >> 2);
@@ -1168,11 +1218,14 @@ __device__ __forceinline__ int block_sum_int(int v) {
   for (int w = 0; w < nw; ++w) s += ws[w];
   return s;
 }
+// Per-workgroup counts summed into the frame's counter row (integers: any
+// order is exact); advance != nullptr also ends the frame (frame index + 1,
+// after every thread has read it).
 template <typename T>
 __global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, int n, const int* __restrict__ b, int nb,
-                                                     int32_t* __restrict__ counter_base, const int* __restrict__ frame,
+                                                     int32_t* __restrict__ counter_base, const int* frame,
                                                      int max_frames, int slot_a, int slot_b, const int* __restrict__ extra,
-                                                     int slot_extra) {
+                                                     int slot_extra, int* advance) {
   int32_t* counters = counter_row(counter_base, frame, max_frames);
   int sa = 0, sb = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sa += a[i];
@@ -1185,16 +1238,32 @@ __global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, 
     counters[slot_a] = sa;
     if (b) counters[slot_b] = sb;
     if (extra) counters[slot_extra] = *extra;
+    if (advance) *advance += 1;
   }
 }
 
 // Per-brick summary for the raycast: bit 0 = some voxel observed (W > 0),
 // bit 1 = every voxel observed with F exactly 1 (free space).  Recomputed for
 // the bricks fusion visited (list) or for all bricks (list == nullptr).
+// Workgroup 0 also sums the fusion's per-workgroup counts into the frame's
+// counter row (fcounts != nullptr): fused voxels and active bricks.
 template <typename T>
 __global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T>::type* __restrict__ rec,
                                                            uint8_t* __restrict__ flags, const int* __restrict__ list,
-                                                           const int* __restrict__ count, int nbrick) {
+                                                           const int* __restrict__ count, int nbrick,
+                                                           const int* __restrict__ fcounts, int nf,
+                                                           int32_t* __restrict__ counter_base,
+                                                           const int* __restrict__ frame, int max_frames) {
+  if (fcounts && blockIdx.x == 0) {
+    int sf = 0;
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) sf += fcounts[i];
+    sf = block_sum_int(sf);
+    if (threadIdx.x == 0) {
+      int32_t* counters = counter_row(counter_base, frame, max_frames);
+      counters[1] = sf;
+      counters[30] = *count;
+    }
+  }
   const int nact = list ? *count : nbrick;
   for (int q = blockIdx.x; q < nact; q += gridDim.x) {
     const int b = list ? list[q] : q;
@@ -1205,24 +1274,13 @@ __global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T
   }
 }
 
-// end of tracking (a lost frame keeps its initial estimate), pose history,
-// and the reset of the brick list for fusion
 template <typename T, int D, int Q>
 __global__ void k_post_track(MPose<D, Q>* Pcur, const MPose<D, Q>* Pinit, KPose<T, D, Q>* Kcur, const int* lost,
                              MPose<D, Q>* history, const int* frame, int max_frames, int* count) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (lost && *lost) {
-    *Pcur = *Pinit;
-    *Kcur = to_kpose<T, double>(*Pinit);
-  }
-  if (history) history[min(*frame, max_frames - 1)] = *Pcur;
-  *count = 0;
+  post_track_work(PostTrack<T, D, Q>{Pcur, Pinit, Kcur, lost, history, frame, max_frames, count});
 }
 
-template <typename T>
-__global__ void k_frame_end(int* frame) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *frame += 1;
-}
 
 // ---------------------------------------------------------------------------
 // A7. raycast (Sec. 4.1 "Ray casting", eq. "surface_prediction") and the
