@@ -325,14 +325,18 @@ struct Engine : EngineBase {
            })))
         return rc;
     }
+    VNLevels<T> lv;
+    lv.first[0] = 0;
     for (int l = 0; l < 3; ++l) {
-      dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
-      if ((rc = launch(0, "vertex_normal", [&] {
-             hipLaunchKernelGGL((k_vertex_normal<T, D, Q>), g, b, 0, C->stream, kp, l, Dl[l], W[l], H[l], Vl[l],
-                                Nl[l], valid[l], Dhi[l]);
-           })))
-        return rc;
+      lv.D[l] = Dl[l]; lv.Dhi[l] = Dhi[l]; lv.V[l] = Vl[l]; lv.N[l] = Nl[l]; lv.valid[l] = valid[l];
+      lv.W[l] = W[l]; lv.H[l] = H[l];
+      lv.tiles_x[l] = (W[l] + 15) / 16;
+      lv.first[l + 1] = lv.first[l] + lv.tiles_x[l] * ((H[l] + 15) / 16);
     }
+    if ((rc = launch(0, "vertex_normal", [&] {
+           hipLaunchKernelGGL((k_vertex_normal<T, D, Q>), dim3(lv.first[3]), b, 0, C->stream, kp, lv);
+         })))
+      return rc;
     measured = true;
     return XSLAM_OK;
   }

@@ -227,14 +227,39 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
 // A2. vertex and normal maps (eqs. "vertex", "normal"), level l with K / 2^l.
 // N = normalize((V(u_y+) - V(u)) x (V(u_x+) - V(u))) faces the camera.
 // ---------------------------------------------------------------------------
+// The three levels in one launch: a 1-D grid of 16x16 tiles, level 0's
+// first, then level 1's and level 2's.
+template <typename T>
+struct VNLevels {
+  const T* D[3];
+  const double* Dhi[3];
+  T* V[3];
+  T* N[3];
+  uint8_t* valid[3];
+  int W[3], H[3];
+  int tiles_x[3], first[4];   // tiles per row; first tile of each level (first[3] = total)
+};
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, int level, const T* __restrict__ Dl,
-                                                       int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
-                                                       uint8_t* __restrict__ valid, const double* __restrict__ Dhi) {
+__device__ __forceinline__ void vertex_normal_px(const KParams<T, D, Q>& kp, int level, const T* __restrict__ Dl,
+                                                 int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
+                                                 uint8_t* __restrict__ valid, const double* __restrict__ Dhi,
+                                                 int x, int y);
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, VNLevels<T> lv) {
+  const int b = blockIdx.x;
+  const int l = b < lv.first[1] ? 0 : (b < lv.first[2] ? 1 : 2);
+  const int t = b - lv.first[l];
+  const int x = (t % lv.tiles_x[l]) * 16 + threadIdx.x, y = (t / lv.tiles_x[l]) * 16 + threadIdx.y;
+  vertex_normal_px(kp, l, lv.D[l], lv.W[l], lv.H[l], lv.V[l], lv.N[l], lv.valid[l], lv.Dhi[l], x, y);
+}
+template <typename T, int D, int Q>
+__device__ __forceinline__ void vertex_normal_px(const KParams<T, D, Q>& kp, int level, const T* __restrict__ Dl,
+                                                 int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
+                                                 uint8_t* __restrict__ valid, const double* __restrict__ Dhi,
+                                                 int x, int y) {
   // FP32 runs: the real parts of vertices and normals from the FP64 depth
   constexpr bool kHi = std::is_same<T, float>::value;
   using J = Jet<T, D, Q>;
-  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
   if (x >= Wl || y >= Hl) return;
   const size_t n = size_t(Wl) * Hl, i = size_t(y) * Wl + x;
   const T sc = T(1) / T(1 << level);
