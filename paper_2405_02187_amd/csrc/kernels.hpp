@@ -30,19 +30,6 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
 // ---------------------------------------------------------------------------
 // A1. depth promotion (eq. "csfd_depth") and bilateral filter
 // ---------------------------------------------------------------------------
-template <typename T, int D, int Q>
-__device__ __forceinline__ Jet<T, D, Q> promote_depth(const KParams<T, D, Q>& kp, const T* __restrict__ depth,
-                                                      const T* __restrict__ ddot, size_t n, size_t i) {
-  Jet<T, D, Q> r = jzero<Jet<T, D, Q>>();
-  T d = depth[i];
-  if (!(d > T(0) && isfinite(d))) return r;
-  r.v[0] = d;
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-    if (kp.depth_plane[k] >= 0) r.v[1 + k] = kp.depth_h[k] * ddot[size_t(kp.depth_plane[k]) * n + i];
-  return r;
-}
-
 // Bilateral filter (Sec. 4.1 "Surface measurement"): normalised weighted sum
 // over the valid pixels of a (2r+1)^2 window with weights
 // exp(-|u-u'|^2/(2 s_px^2) - (D(u)-D(u'))^2/(2 s_m^2)), complex through D.
@@ -72,7 +59,8 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
   const int tid = threadIdx.y * kBilTile + threadIdx.x;
   // the tile's raw depths and depth tangents, every load in flight together
   // (coordinates clamped to the image; entries outside it are zero), then
-  // promoted to jets as promote_depth does
+  // promoted to jets: D + h_d ddot_d e_d for a finite positive depth (eq.
+  // "csfd_depth"; only the depth directions carry a tangent), else 0
   constexpr int NQ = (S * S + kBilTile * kBilTile - 1) / (kBilTile * kBilTile);
   T dv[NQ], tv[NQ][D > 0 ? D : 1];
   bool in[NQ];
