@@ -484,8 +484,13 @@ __device__ __forceinline__ void icp_tangent_sums(const Jet<T, D, Q> (&jac)[6], c
 
 // 6x6 symmetric solve with a real LDL^T factorisation of the real part and
 // first/second-order parts from A x = -b differentiated (no conjugation).
+// Called by the 64 lanes of one wave with the same sums: every lane factors
+// and solves the real part; with several imaginary parts, direction d is
+// solved on lane d - 1 and pair p on lane p (their right-hand sides need the
+// directions' solutions, exchanged through Xs in LDS), each part with the
+// operations of the serial order.
 template <int D, int Q>
-__device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
+__device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6], int lane, double (*Xs)[6]) {
   constexpr int NC = Jet<double, D, Q>::N;
   double A0[6][6], L[6][6], dd[6];
   int k = 0;
@@ -532,27 +537,53 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6]) {
         if (b != a) out[b] += m * v[a];
       }
   };
-  double X[NC][6];
   double rhs[6], t1[6], t2[6];
-  for (int a = 0; a < 6; ++a) rhs[a] = -sums[(21 + a) * NC];
-  solve(rhs, X[0]);
-  for (int d = 1; d <= D; ++d) {
-    Amul(d, X[0], t1);
-    for (int a = 0; a < 6; ++a) rhs[a] = -(sums[(21 + a) * NC + d] + t1[a]);
-    solve(rhs, X[d]);
-  }
-  int p = 1 + D;
-  for (int a = 0; a < Q; ++a)
-    for (int b = a; b < Q; ++b, ++p) {
-      Amul(p, X[0], t1);
-      for (int i = 0; i < 6; ++i) rhs[i] = -(sums[(21 + i) * NC + p] + t1[i]);
-      Amul(1 + a, X[1 + b], t1);
-      Amul(1 + b, X[1 + a], t2);
-      for (int i = 0; i < 6; ++i) rhs[i] -= t1[i] + t2[i];
-      solve(rhs, X[p]);
+  if constexpr (NC <= 2) {
+    double X[NC][6];
+    for (int a = 0; a < 6; ++a) rhs[a] = -sums[(21 + a) * NC];
+    solve(rhs, X[0]);
+    for (int d = 1; d <= D; ++d) {
+      Amul(d, X[0], t1);
+      for (int a = 0; a < 6; ++a) rhs[a] = -(sums[(21 + a) * NC + d] + t1[a]);
+      solve(rhs, X[d]);
     }
-  for (int a = 0; a < 6; ++a)
-    for (int c = 0; c < NC; ++c) dx[a].v[c] = X[c][a];
+    for (int a = 0; a < 6; ++a)
+      for (int c = 0; c < NC; ++c) dx[a].v[c] = X[c][a];
+  } else {
+    static_assert(D <= 64 && Q * (Q + 1) / 2 <= 64, "one lane per imaginary part");
+    constexpr int P = Q * (Q + 1) / 2;
+    double X0[6], x[6];
+    for (int a = 0; a < 6; ++a) rhs[a] = -sums[(21 + a) * NC];
+    solve(rhs, X0);
+    if (lane == 0)
+      for (int a = 0; a < 6; ++a) Xs[0][a] = X0[a];
+    if (lane < D) {
+      const int d = lane + 1;
+      Amul(d, X0, t1);
+      for (int a = 0; a < 6; ++a) rhs[a] = -(sums[(21 + a) * NC + d] + t1[a]);
+      solve(rhs, x);
+      for (int a = 0; a < 6; ++a) Xs[d][a] = x[a];
+    }
+    // (one wave: its LDS accesses complete in program order)
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    if (lane < P) {
+      const int a = pair_a<Q>(lane), b = pair_b<Q>(lane), p = 1 + D + lane;
+      double Xa[6], Xb[6];
+      for (int i = 0; i < 6; ++i) { Xa[i] = Xs[1 + a][i]; Xb[i] = Xs[1 + b][i]; }
+      Amul(p, X0, t1);
+      for (int i = 0; i < 6; ++i) rhs[i] = -(sums[(21 + i) * NC + p] + t1[i]);
+      Amul(1 + a, Xb, t1);
+      Amul(1 + b, Xa, t2);
+      for (int i = 0; i < 6; ++i) rhs[i] -= t1[i] + t2[i];
+      solve(rhs, x);
+      for (int i = 0; i < 6; ++i) Xs[p][i] = x[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    for (int a = 0; a < 6; ++a)
+      for (int c = 0; c < NC; ++c) dx[a].v[c] = Xs[c][a];
+  }
   return true;
 }
 
@@ -672,7 +703,7 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
 // (one entry of the new pose per lane), counters; or only the sums when they
 // are all that is wanted.
 template <typename T, int D, int Q>
-__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, int lane) {
+__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, int lane, double (*Xs)[6]) {
   constexpr int NC = Jet<T, D, Q>::N;
   constexpr int NS = IcpSize<D, Q>::NS;
   const int cnt = int(fin[27 * NC]);
@@ -689,7 +720,7 @@ __device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, i
   // every lane solves (the same operations on the same data), so the update
   // is known to all of them without a broadcast
   Jet<double, D, Q> dx[6];
-  if (cnt < 6 || !icp_solve<D, Q>(fin, dx)) {
+  if (cnt < 6 || !icp_solve<D, Q>(fin, dx, lane, Xs)) {
     if (lane == 0) {
       *g.lost = 1;
       crow[0] = 1;
@@ -841,6 +872,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
   constexpr int G = 16, KC = kFinishThreads / G;
   __shared__ double gs[G][KC];
   __shared__ double fin[NS];
+  __shared__ double xs[Jet<T, D, Q>::N][6];
   const int lost = *g.lost;   // read now, tested after the sums (its load overlaps theirs)
   const int grp = threadIdx.x / KC, kk = threadIdx.x % KC;
   const unsigned B = nblocks;
@@ -876,7 +908,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> 
     __syncthreads();
   }
   if (threadIdx.x >= 64 || lost) return;
-  icp_finish_solve<T, D, Q>(g, fin, threadIdx.x);
+  icp_finish_solve<T, D, Q>(g, fin, threadIdx.x, xs);
 }
 
 
