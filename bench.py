@@ -211,6 +211,9 @@ def main():
     ap.add_argument("--multi-cap", type=int, default=None, help="cap frames per multi-instance sequence")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
+    ap.add_argument("--null-stream", action="store_true",
+                    help="run on torch's default (legacy null) stream, which cannot be captured: "
+                         "tracked frames then launch eagerly instead of replaying the frame graph")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the frame step runs on a single MI355X "
@@ -220,6 +223,11 @@ def main():
     import torch
     import scenegen as sg
     from paper_2405_02187_amd import xslam as X
+
+    if not args.null_stream:
+        # every tensor and every library call of the run on one created stream,
+        # which the library can capture: tracked frames replay as one graph
+        torch.cuda.set_stream(torch.cuda.Stream())
 
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
@@ -343,6 +351,7 @@ def main():
         "kernel_classes": per, "kernel_rooflines": kern, "per_frame": extra,
         "lost_frames": int(cnt[:, 0].sum()),
         "launch_shapes": slam.get_launch(),
+        "frame_graph": not args.null_stream,
     }
     poses32 = slam.get(X.F_POSES)
     slam.close()

@@ -178,7 +178,10 @@ int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double*
 
 /* Whole frame step: frame 0 fuses and raycasts at the initial pose; later
  * frames measure, track against the previous model maps, fuse (skipped when
- * tracking is lost) and raycast.  pose_out as in xslam_track. */
+ * tracking is lost) and raycast.  pose_out as in xslam_track.  The device
+ * work of a tracked frame is captured once into a graph and replayed, except
+ * on the legacy null stream (stream NULL at xslam_create), which cannot be
+ * captured: there it is launched kernel by kernel (same results). */
 int xslam_step(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out);
 
 /* One association + normal-equation pass (no solve) of ICP level `level`
@@ -230,7 +233,9 @@ int xslam_get_launch(xslam_ctx ctx, xslam_launch* out);
  * changing state, with HIP events (reps launches each, after one untimed
  * launch), and keep the fastest: the raycast tile (re-running the raycast of
  * the current pose rewrites the same model maps) and the ICP grid of each
- * level (association and sums only; the pose is not changed).  The fusion
+ * level (association and sums only; the pose is not changed; the reps passes
+ * are captured into a graph and replayed, so that short passes are not timed
+ * at the host's launch rate).  The fusion
  * grid changes the TSDF when run, so it is not timed here: time real steps
  * with different fuse_blocks instead (no result depends on it).  Requires a
  * measured frame and model maps (after xslam_step).  best (optional)

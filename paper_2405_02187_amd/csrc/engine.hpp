@@ -446,6 +446,44 @@ struct Engine : EngineBase {
   }
 
   // mean time (ms) of reps runs of f after one untimed run, HIP events on the stream
+  // GPU time of reps back-to-back calls of f, captured into a graph and
+  // replayed: eagerly launched short kernels (an ICP pass is two launches of
+  // ~10 us) would time the host's launch rate as much as the kernels
+  template <typename F> int time_graph_ms(int reps, double* ms, F&& f) {
+    // (the legacy null stream cannot be captured: time eager launches there)
+    if (C->stream == nullptr) return time_ms(reps, ms, f);
+    int rc = f();   // warm-up, eager
+    if (rc) return rc;
+    if (hipStreamBeginCapture(C->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return check("autotune capture");
+    for (int r = 0; r < reps && !rc; ++r) rc = f();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(C->stream, &g);
+    if (rc || e != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      return rc ? rc : check("autotune capture");
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(g);
+      return check("autotune graph");
+    }
+    hipGraphDestroy(g);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = check("autotune events");
+    if (!rc && hipGraphLaunch(ge, C->stream) != hipSuccess) rc = check("autotune graph launch");   // warm
+    if (!rc) hipEventRecord(e0, C->stream);
+    if (!rc && hipGraphLaunch(ge, C->stream) != hipSuccess) rc = check("autotune graph launch");
+    if (!rc) hipEventRecord(e1, C->stream);
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = check("autotune sync");
+    float t = 0.f;
+    if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = check("autotune timing");
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipGraphExecDestroy(ge);
+    *ms = double(t) / reps;
+    return rc;
+  }
+
   template <typename F> int time_ms(int reps, double* ms, F&& f) {
     int rc = f();
     if (rc) return rc;
@@ -496,7 +534,7 @@ struct Engine : EngineBase {
         if (gsz > full) continue;
         icp_grid[l] = gsz;
         double ms = 0;
-        if ((rc = time_ms(reps, &ms, [&] { return run_icp_level(l, 0, 0, sums); }))) break;
+        if ((rc = time_graph_ms(reps, &ms, [&] { return run_icp_level(l, 0, 0, sums); }))) break;
         if (ms < best_icp[l]) { best_icp[l] = ms; bestg = gsz; }
       }
       icp_grid[l] = bestg;
