@@ -274,7 +274,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * 1 / dt
-    log(f"{args.steps} frame steps in {dt:.3f}s")
+    graph_used = slam.frame_graph()
+    log(f"{args.steps} frame steps in {dt:.3f}s (frame graph: {graph_used})")
 
     # per-kernel durations with HIP events on the library's stream
     # (the counts accumulate over the context's life: the autotuner's timed
@@ -351,7 +352,7 @@ def main():
         "kernel_classes": per, "kernel_rooflines": kern, "per_frame": extra,
         "lost_frames": int(cnt[:, 0].sum()),
         "launch_shapes": slam.get_launch(),
-        "frame_graph": not args.null_stream,
+        "frame_graph": graph_used,
     }
     poses32 = slam.get(X.F_POSES)
     slam.close()

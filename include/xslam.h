@@ -227,6 +227,11 @@ typedef struct {
 } xslam_launch;
 
 int xslam_set_launch(xslam_ctx ctx, const xslam_launch* shapes);
+/* *active = 1 if tracked frames replay a captured graph (captured at the
+ * first tracked step on a stream that can be captured), 0 if they launch
+ * kernel by kernel (legacy null stream, per-kernel timing on, or before the
+ * first tracked step).  Errors: XSLAM_ERR_ARG for a NULL active. */
+int xslam_frame_graph(xslam_ctx ctx, int32_t* active);
 /* the shapes in use (defaults resolved to numbers) */
 int xslam_get_launch(xslam_ctx ctx, xslam_launch* out);
 /* Time every candidate shape of the stages that can be re-run without

@@ -268,6 +268,13 @@ int xslam_set_launch(xslam_ctx ctx, const xslam_launch* shapes) {
   return ctx->eng->set_launch(*shapes);
 }
 
+int xslam_frame_graph(xslam_ctx ctx, int32_t* active) {
+  XS_CTX_CHECK(ctx);
+  if (!active) return XSLAM_ERR_ARG;
+  *active = ctx->eng->frame_graph() ? 1 : 0;
+  return XSLAM_OK;
+}
+
 int xslam_get_launch(xslam_ctx ctx, xslam_launch* out) {
   XS_CTX_CHECK(ctx);
   if (!out) return XSLAM_ERR_ARG;

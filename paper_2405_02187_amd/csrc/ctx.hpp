@@ -25,6 +25,7 @@ struct EngineBase {
   virtual int cnn_parts(float* depth, float* model) = 0;
   virtual int set_launch(const xslam_launch& l) = 0;
   virtual int get_launch(xslam_launch* l) = 0;
+  virtual bool frame_graph() const = 0;
   virtual int autotune(int reps, double* ms_out) = 0;
 };
 

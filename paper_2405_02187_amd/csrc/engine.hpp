@@ -417,6 +417,8 @@ struct Engine : EngineBase {
     if (graph) { hipGraphDestroy(graph); graph = nullptr; }
   }
 
+  bool frame_graph() const override { return gexec != nullptr && !C->timer.on; }
+
   int set_launch(const xslam_launch& l) override {
     const int bx = l.ray_tile[0], by = l.ray_tile[1];
     if (bx < 1 || by < 1 || bx * by < 64 || bx * by > 256 || (bx * by) % 64 != 0)

@@ -100,6 +100,7 @@ def lib():
             "xslam_cnn_parts": (C.c_int, [vp, vp, vp]),
             "xslam_set_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
             "xslam_get_launch": (C.c_int, [vp, C.POINTER(xslam_launch)]),
+            "xslam_frame_graph": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "xslam_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(xslam_launch), dp]),
             "xslam_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, C.POINTER(vp)]),
             "xslam_batch_step": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int32)]),
@@ -118,7 +119,7 @@ EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xs
            "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
            "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
-           "xslam_autotune", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
+           "xslam_autotune", "xslam_frame_graph", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
            "xslam_batch_last_index", "xslam_batch_destroy"]
 
 
@@ -280,6 +281,12 @@ class Slam:
         m = self.torch.empty((4, H3, W3), dtype=self.torch.float32, device=self.ws.device)
         self._check(lib().xslam_cnn_parts(self.h, C.c_void_p(d.data_ptr()), C.c_void_p(m.data_ptr())))
         return d, m
+
+    def frame_graph(self) -> bool:
+        """True if tracked frames replay the captured frame graph."""
+        v = C.c_int32(0)
+        self._check(lib().xslam_frame_graph(self.h, C.byref(v)))
+        return bool(v.value)
 
     def get_launch(self) -> dict:
         lc = xslam_launch()

@@ -74,3 +74,39 @@ def test_fused_16_directions_and_4x4_hessian_shape():
     ef = relerr(Ff[1:17], F16[1:17])
     log("fused 16+10 vs separate: first order", e1, "second order", e2, "F first order", ef)
     assert e1 <= 1e-5 and e2 <= 1e-5 and ef <= 1e-5
+
+
+def test_frame_graph_equals_eager_launches():
+    """The tracked frame replayed as a captured graph (a context on a created
+    stream) against the same frames launched kernel by kernel (the legacy null
+    stream, which cannot be captured): poses, counters and the volume equal
+    bit for bit (FP32, 2 directions, 12 frames of the 128^3 sequence)."""
+    p = sg.preset("c0")
+    n = 12
+    seq = sg.make_sequence(p, n_frames=n)
+    depths = seq.depths().astype(np.float32)
+
+    def run(stream):
+        with torch.cuda.stream(stream):
+            cfg = X.config_from_preset(p, prec=X.C64, max_frames=n)
+            slam = X.Slam(cfg, X.Perturbation([(X.P_PHI_X, 2.0 ** -20), (X.P_TRUNC, 2.0 ** -20)]),
+                          seq.poses_gt[0])
+            dev = torch.from_numpy(depths).cuda()
+            for k in range(n):
+                slam.step(dev[k])
+            graph = slam.frame_graph()
+            out = slam.get(X.F_POSES), slam.get(X.F_COUNTERS), slam.get(X.F_TSDF), graph
+            slam.close()
+        torch.cuda.synchronize()
+        return out
+
+    assert torch.cuda.default_stream().cuda_stream == 0
+    Pe, Ce, Fe, ge = run(torch.cuda.default_stream())
+    s = torch.cuda.Stream()
+    assert s.cuda_stream != 0
+    Pg, Cg, Fg, gg = run(s)
+    assert not ge and gg
+    log("frame graph vs eager: lost", int(Cg[:, 0].sum()), "hits", Cg[:, 2].tolist()[:4])
+    assert np.array_equal(Pe, Pg)
+    assert np.array_equal(Ce, Cg)
+    assert np.array_equal(Fe, Fg)
