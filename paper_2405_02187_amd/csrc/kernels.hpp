@@ -465,8 +465,12 @@ __device__ __forceinline__ void icp_fill_chunk(const Jet<T, D, Q> (&jac)[6], con
 }
 // Wave sums of every non-real component of one pixel's 27 products, 64 at a
 // time with the half-exchanging butterfly (each sum bit for bit a wave_sum),
-// added into the wave's row of LDS sums.
-template <typename T, int D, int Q, int... CH>
+// added into the wave's row of LDS sums.  The row has NCO parts per product
+// and part c of the jet goes to part PM::at(c) (a chunk of a wider jet).
+struct SameParts {
+  __host__ __device__ static constexpr int at(int c) { return c; }
+};
+template <typename T, int D, int Q, int NCO = Jet<T, D, Q>::N, typename PM = SameParts, int... CH>
 __device__ __forceinline__ void icp_tangent_sums(const Jet<T, D, Q> (&jac)[6], const Jet<T, D, Q>& r, int lane,
                                                  double* red_row, std::integer_sequence<int, CH...>) {
   constexpr int NC = Jet<T, D, Q>::N, NT = NC - 1;
@@ -477,7 +481,7 @@ __device__ __forceinline__ void icp_tangent_sums(const Jet<T, D, Q> (&jac)[6], c
     double tot[1];
     wave_sum_transposed<64>(vals, lane, tot);
     const int f = ch * 64 + lane;
-    if (f < 27 * NT) red_row[(f / NT) * NC + 1 + f % NT] += tot[0];
+    if (f < 27 * NT) red_row[(f / NT) * NCO + PM::at(1 + f % NT)] += tot[0];
   };
   (one(std::integral_constant<int, CH>{}), ...);
 }
@@ -588,18 +592,17 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6], int lane,
 }
 
 // Association, gates, residual and Jacobian of one current pixel; false if
-// the pixel gives no correspondence.
-template <typename T, int D, int Q>
-__device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g,
-                                          const KPose<T, D, Q>& Tc, const KPose<T, D, Q>& Tp,
-                                          const Jet<T, D, Q>& fx, const Jet<T, D, Q>& fy, const Jet<T, D, Q>& cx,
-                                          const Jet<T, D, Q>& cy, size_t n, size_t i, Jet<T, D, Q> jac[6],
-                                          Jet<T, D, Q>& r) {
-  using J = Jet<T, D, Q>;
+// the pixel gives no correspondence.  J is the jet of the computation (the
+// context's, or a chunk of its parts), ld(base, index) loads a 3-vector map
+// entry as a J.
+template <typename J, typename KP, typename LD, typename T, int D, int Q>
+__device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g, const KP& Tc,
+                                               const KP& Tp, const J& fx, const J& fy, const J& cx, const J& cy,
+                                               size_t n, size_t i, J jac[6], J& r, LD&& ld) {
   const int W = g.W, H = g.H;
   // the pixel's maps are loaded together with its flag (one memory round trip)
   uint32_t vi = g.valid[i];
-  V3<J> v = vload<J>(g.V, n, i), nv = vload<J>(g.N, n, i);
+  V3<J> v = ld(g.V, i), nv = ld(g.N, i);
   pin(vi);
   pin(v);
   pin(nv);
@@ -623,10 +626,10 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
     // floor(u + 1/2) is one of them (u - floor(u + 1e-3) lies in [-1e-3, 1))
     uint32_t w01 = g.validm[t0] | uint32_t(g.validm[t1]) << 8, w23 = g.validm[t2] | uint32_t(g.validm[t3]) << 8;
     T z0 = g.Zm[t0], z1 = g.Zm[t1], z2 = g.Zm[t2], z3 = g.Zm[t3];
-    V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-    V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
-    V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-    V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+    V3<J> q0 = ld(g.Vm, t0), q1 = ld(g.Vm, t1);
+    V3<J> q2 = ld(g.Vm, t2), q3 = ld(g.Vm, t3);
+    V3<J> m0 = ld(g.Nm, t0), m1 = ld(g.Nm, t1);
+    V3<J> m2 = ld(g.Nm, t2), m3 = ld(g.Nm, t3);
     pin(w01);
     pin(w23);
     pin(z0);
@@ -653,8 +656,8 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
         q = sel == 0 ? q0 : sel == 1 ? q1 : sel == 2 ? q2 : q3;
         m = sel == 0 ? m0 : sel == 1 ? m1 : sel == 2 ? m2 : m3;
       } else {
-        q = vload<J>(g.Vm, n, tn);
-        m = vload<J>(g.Nm, n, tn);
+        q = ld(g.Vm, tn);
+        m = ld(g.Nm, tn);
       }
     } else {
       const J a = ux - fx0, b = uy - fy0;
@@ -671,16 +674,16 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
     const T zn = g.Zm[tn];
     const T disc = fabs(g.Zm[t0] - zn) + fabs(g.Zm[t1] - zn) + fabs(g.Zm[t2] - zn) + fabs(g.Zm[t3] - zn);
     if (disc >= kp.disc_delta) {
-      q = vload<J>(g.Vm, n, tn);
-      m = vload<J>(g.Nm, n, tn);
+      q = ld(g.Vm, tn);
+      m = ld(g.Nm, tn);
     } else {
       const J a = ux - fx0, b = uy - fy0;
       const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
-      const V3<J> q0 = vload<J>(g.Vm, n, t0), q1 = vload<J>(g.Vm, n, t1);
-      const V3<J> q2 = vload<J>(g.Vm, n, t2), q3 = vload<J>(g.Vm, n, t3);
+      const V3<J> q0 = ld(g.Vm, t0), q1 = ld(g.Vm, t1);
+      const V3<J> q2 = ld(g.Vm, t2), q3 = ld(g.Vm, t3);
       q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
-      const V3<J> m0 = vload<J>(g.Nm, n, t0), m1 = vload<J>(g.Nm, n, t1);
-      const V3<J> m2 = vload<J>(g.Nm, n, t2), m3 = vload<J>(g.Nm, n, t3);
+      const V3<J> m0 = ld(g.Nm, t0), m1 = ld(g.Nm, t1);
+      const V3<J> m2 = ld(g.Nm, t2), m3 = ld(g.Nm, t3);
       V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
       m = vscale(jconst<J>(T(1)) / jsqrt(vdot(mm, mm)), mm);
     }
@@ -693,6 +696,48 @@ __device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpA
   jac[0] = pm.x; jac[1] = pm.y; jac[2] = pm.z; jac[3] = m.x; jac[4] = m.y; jac[5] = m.z;
   return true;
 }
+
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool icp_pixel(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g,
+                                          const KPose<T, D, Q>& Tc, const KPose<T, D, Q>& Tp,
+                                          const Jet<T, D, Q>& fx, const Jet<T, D, Q>& fy, const Jet<T, D, Q>& cx,
+                                          const Jet<T, D, Q>& cy, size_t n, size_t i, Jet<T, D, Q> jac[6],
+                                          Jet<T, D, Q>& r) {
+  return icp_pixel_with(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r,
+                        [&](const T* base, size_t idx) { return vload<Jet<T, D, Q>>(base, n, idx); });
+}
+
+// Parts of a chunk of a jet: part 0 is the real part, parts 1..Dc are the
+// directions d0..d0+Dc-1 of the full jet (D directions, Q pair directions),
+// and a chunk with Qc = Q (then d0 = 0, Dc >= Q) also holds the Q(Q+1)/2 pair
+// parts.  Every part of a chunk is computed with the arithmetic it has in the
+// full jet (a product's part c needs parts 0 and c, a pair part also the parts
+// of its two directions, all in the same chunk).
+template <int D, int Q, int Dc, int Qc, int d0>
+struct SubParts {
+  static_assert(Qc == 0 || (Qc == Q && d0 == 0 && Dc >= Q), "pairs need their directions");
+  static constexpr int NF = 1 + D + Q * (Q + 1) / 2;
+  __host__ __device__ static constexpr int at(int c) { return c == 0 ? 0 : (c <= Dc ? d0 + c : 1 + D + (c - 1 - Dc)); }
+};
+template <typename SP, typename T, int D, int Q, int Dc, int Qc>
+__device__ __forceinline__ void jsub(const Jet<T, D, Q>& x, Jet<T, Dc, Qc>& y) {
+#pragma unroll
+  for (int c = 0; c < Jet<T, Dc, Qc>::N; ++c) y.v[c] = x.v[SP::at(c)];
+}
+template <typename F, int... JJ>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, JJ...>) {
+  (f(std::integral_constant<int, JJ>{}), ...);
+}
+// ICP chunk plan for many parts: chunk 0 holds the pair directions and the
+// pairs (or 6 directions when there are no pairs), then 6 directions each
+template <int D, int Q>
+struct IcpChunks {
+  static constexpr int D0 = Q > 0 ? Q : (D < 6 ? D : 6);
+  static constexpr int count = 1 + (D - D0 + 5) / 6;
+  static constexpr int start(int j) { return j == 0 ? 0 : D0 + 6 * (j - 1); }
+  static constexpr int dirs(int j) { return j == 0 ? D0 : (D - start(j) < 6 ? D - start(j) : 6); }
+  static constexpr int pairs(int j) { return j == 0 ? Q : 0; }
+};
 
 // Per-block sums of the normal equations of one ICP pass (21 entries of
 // A = sum J J^T, 6 of b = sum J r, each with NC components; count; sum r^2).
@@ -815,29 +860,91 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 #pragma unroll
     for (int k = 0; k < 29; ++k) racc[k] = 0;
     for (int k = lane; k < NS; k += 64) red[wv][k] = 0.0;
+    // The pixel is evaluated chunk by chunk of the jet's parts (each chunk's
+    // jets fit in registers; the real part is recomputed, identically, in
+    // every chunk and accumulated from the first); every part keeps the
+    // arithmetic and summation order it has in the full jet.
+    using CP = IcpChunks<D, Q>;
+    auto chunk = [&](auto ji, size_t i, T (&ra)[29]) {
+      constexpr int j = decltype(ji)::value;
+      constexpr int Dc = CP::dirs(j), Qc = CP::pairs(j), d0 = CP::start(j);
+      using SP = SubParts<D, Q, Dc, Qc, d0>;
+      using JC = Jet<T, Dc, Qc>;
+      KPose<T, Dc, Qc> Tcc, Tpc;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        jsub<SP>(Tc.R[q], Tcc.R[q]);
+        jsub<SP>(Tp.R[q], Tpc.R[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        jsub<SP>(Tc.t[q], Tcc.t[q]);
+        jsub<SP>(Tp.t[q], Tpc.t[q]);
+      }
+      JC fxc, fyc, cxc, cyc;
+      jsub<SP>(fx, fxc);
+      jsub<SP>(fy, fyc);
+      jsub<SP>(cx, cxc);
+      jsub<SP>(cy, cyc);
+      auto ld = [&](const T* b, size_t idx) {
+        V3<JC> v;
+        JC* o[3] = {&v.x, &v.y, &v.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < JC::N; ++c) o[a]->v[c] = b[size_t(a * NC + SP::at(c)) * n + idx];
+        return v;
+      };
+      JC jac[6], r;
+      const bool ok = i < p1 && icp_pixel_with(kp, g, Tcc, Tpc, fxc, fyc, cxc, cyc, n, i, jac, r, ld);
+      if (!ok) {
+        r = jzero<JC>();
+#pragma unroll
+        for (int a = 0; a < 6; ++a) jac[a] = jzero<JC>();
+      }
+      if constexpr (j == 0) {
+        if (ok) {
+          int k = 0;
+#pragma unroll
+          for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = a; b < 6; ++b, ++k) ra[k] += jac[a].v[0] * jac[b].v[0];
+#pragma unroll
+          for (int a = 0; a < 6; ++a) ra[21 + a] += jac[a].v[0] * r.v[0];
+          ra[27] += T(1);
+          ra[28] += r.re() * r.re();
+        }
+      }
+      constexpr int NCHK = (27 * (JC::N - 1) + 63) / 64;
+      icp_tangent_sums<T, Dc, Qc, NC, SP>(jac, r, lane, red[wv], std::make_integer_sequence<int, NCHK>{});
+    };
     for (size_t base = p0; base < p1; base += kIcpThreads) {
       const size_t i = base + threadIdx.x;
-      J jac[6], r;
-      const bool ok = i < p1 && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
-      if (!ok) {
-        r = jzero<J>();
+      if constexpr (CP::count > 1) {
+        for_each_index([&](auto ji) { chunk(ji, i, racc); }, std::make_integer_sequence<int, CP::count>{});
+      } else {
+        J jac[6], r;
+        const bool ok = i < p1 && icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r);
+        if (!ok) {
+          r = jzero<J>();
 #pragma unroll
-        for (int a = 0; a < 6; ++a) jac[a] = jzero<J>();
-      }
-      if (ok) {
-        int k = 0;
+          for (int a = 0; a < 6; ++a) jac[a] = jzero<J>();
+        }
+        if (ok) {
+          int k = 0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a)
+          for (int a = 0; a < 6; ++a)
 #pragma unroll
-          for (int b = a; b < 6; ++b, ++k) racc[k] += jac[a].v[0] * jac[b].v[0];
+            for (int b = a; b < 6; ++b, ++k) racc[k] += jac[a].v[0] * jac[b].v[0];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) racc[21 + a] += jac[a].v[0] * r.v[0];
-      }
-      constexpr int NCH = (27 * (NC - 1) + 63) / 64;
-      icp_tangent_sums<T, D, Q>(jac, r, lane, red[wv], std::make_integer_sequence<int, NCH>{});
-      if (ok) {
-        racc[27] += T(1);
-        racc[28] += r.re() * r.re();
+          for (int a = 0; a < 6; ++a) racc[21 + a] += jac[a].v[0] * r.v[0];
+        }
+        constexpr int NCH = (27 * (NC - 1) + 63) / 64;
+        icp_tangent_sums<T, D, Q>(jac, r, lane, red[wv], std::make_integer_sequence<int, NCH>{});
+        if (ok) {
+          racc[27] += T(1);
+          racc[28] += r.re() * r.re();
+        }
       }
     }
 #pragma unroll
