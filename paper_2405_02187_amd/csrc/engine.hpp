@@ -358,7 +358,7 @@ struct Engine : EngineBase {
     });
     if (rc) return rc;
     return launch(5, "icp_finish", [&] {
-      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kFinishThreads), 0, C->stream, a, blocks);
+      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kFinishThreads<T, D, Q>), 0, C->stream, a, blocks);
     });
   }
 

@@ -971,40 +971,48 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 // workgroup partials in the same order whatever the number of components (so
 // real parts do not depend on D, Q): 16 interleaved groups of workgroups
 // (b mod 16), eight running sums each, combined in a fixed tree; components
-// are taken 64 at a time, one (component, group) per thread.
-constexpr int kFinishThreads = 1024;
+// are taken 64 at a time, one (component, group) per thread (1024 threads),
+// or four groups per thread for jets with many parts (256 threads, so that
+// the solving wave may hold 512 registers: the same sums, fewer spills).
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(kFinishThreads) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
+constexpr int kFinishThreads = Jet<T, D, Q>::N > 8 ? 256 : 1024;
+template <typename T, int D, int Q>
+__global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
   constexpr int NS = IcpSize<D, Q>::NS;
-  constexpr int G = 16, KC = kFinishThreads / G;
+  constexpr int NT = kFinishThreads<T, D, Q>;
+  constexpr int G = 16, KC = 64, GPT = G * KC / NT;
   __shared__ double gs[G][KC];
   __shared__ double fin[NS];
   __shared__ double xs[Jet<T, D, Q>::N][6];
   const int lost = *g.lost;   // read now, tested after the sums (its load overlaps theirs)
-  const int grp = threadIdx.x / KC, kk = threadIdx.x % KC;
+  const int grp0 = threadIdx.x / KC, kk = threadIdx.x % KC;
   const unsigned B = nblocks;
   for (int kc = 0; kc < NS; kc += KC) {
     const int k = kc + kk;
-    double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (k < NS) {
-      // the m-th workgroup of the group (b = grp + m G) goes to running sum
-      // m mod 8, in increasing m; its partials are loaded NB at a time with
-      // every load in flight together (indexes past the end are clamped and
-      // their values dropped)
-      constexpr unsigned NB = 32;
-      for (unsigned b0 = grp; b0 < B; b0 += NB * G) {
-        double v[NB];
 #pragma unroll
-        for (unsigned u = 0; u < NB; ++u) {
-          const unsigned b = b0 + u * G < B ? b0 + u * G : B - 1;
-          v[u] = g.partials[size_t(b) * NS + k];
+    for (int gi = 0; gi < GPT; ++gi) {
+      const int grp = grp0 + gi * (NT / KC);
+      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (k < NS) {
+        // the m-th workgroup of the group (b = grp + m G) goes to running sum
+        // m mod 8, in increasing m; its partials are loaded NB at a time with
+        // every load in flight together (indexes past the end are clamped and
+        // their values dropped)
+        constexpr unsigned NB = 32;
+        for (unsigned b0 = grp; b0 < B; b0 += NB * G) {
+          double v[NB];
+#pragma unroll
+          for (unsigned u = 0; u < NB; ++u) {
+            const unsigned b = b0 + u * G < B ? b0 + u * G : B - 1;
+            v[u] = g.partials[size_t(b) * NS + k];
+          }
+#pragma unroll
+          for (unsigned u = 0; u < NB; ++u)
+            if (b0 + u * G < B) a8[u & 7] += v[u];
         }
-#pragma unroll
-        for (unsigned u = 0; u < NB; ++u)
-          if (b0 + u * G < B) a8[u & 7] += v[u];
       }
+      gs[grp][kk] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
-    gs[grp][kk] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     __syncthreads();
     if (threadIdx.x < KC && kc + int(threadIdx.x) < NS) {
       double s8[8];
