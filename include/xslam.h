@@ -240,7 +240,8 @@ int xslam_get_launch(xslam_ctx ctx, xslam_launch* out);
  * the current pose rewrites the same model maps) and the ICP grid of each
  * level (association and sums only; the pose is not changed; the reps passes
  * are captured into a graph and replayed, so that short passes are not timed
- * at the host's launch rate).  The fusion
+ * at the host's launch rate; each candidate is timed in 3 rounds and a smaller
+ * grid replaces a larger one only when 5% faster).  The fusion
  * grid changes the TSDF when run, so it is not timed here: time real steps
  * with different fuse_blocks instead (no result depends on it).  Requires a
  * measured frame and model maps (after xslam_step).  best (optional)
