@@ -4,8 +4,14 @@ The library times the stages it can re-run without changing state (raycast
 tile, ICP grid per level; ``Slam.autotune``).  The fusion grid changes the
 TSDF when it runs, so it is tuned here on real frames: consecutive steps of
 the sequence with different grids, timed by the library's per-kernel event
-timer (no result depends on the fusion grid).  Chosen shapes are cached per
-workload shape (image size, volume, precision, directions, Hessian size).
+timer (no result depends on the fusion grid).  The library's ICP choice per
+level is then checked on real frames too, against the one-pixel-per-thread
+grid: passes timed back to back in isolation do not always rank the grids as
+the frame step, where each pass follows a finish launch and the levels
+alternate, does.  (The ICP grid changes the order of the FP64 partial sums,
+so the poses of those frames may differ by rounding.)  Chosen shapes are
+cached per workload shape (image size, volume, precision, directions, Hessian
+size).
 """
 from __future__ import annotations
 
@@ -15,6 +21,8 @@ import os
 from . import xslam as X
 
 FUSE_GRIDS = (4096, 2048, 1024, 512)
+ICP_FULL = 0          # ICP workgroups value of the one-pixel-per-thread grid
+ICP_PREFER = 0.95     # a grid other than the one-pixel-per-thread one must be 5% faster
 
 
 def key(slam: "X.Slam") -> str:
@@ -43,13 +51,68 @@ def apply(slam: "X.Slam", shapes: dict) -> None:
                     fuse_blocks=int(shapes["fuse_blocks"]))
 
 
-def tune(slam: "X.Slam", frames, reps: int = 20, fuse_frames_per_grid: int = 2) -> dict:
+def _icp_ms(slam: "X.Slam") -> float:
+    """Event-timed ms so far of the ICP passes and their finish launches (the
+    finish reduces one partial per workgroup, so it depends on the grid too)."""
+    ms = slam.kernel_times()[0]
+    return float(ms[X.TIMER_CLASSES.index("k_icp")] + ms[X.TIMER_CLASSES.index("k_icp_finish")])
+
+
+def _icp_on_steps(slam: "X.Slam", it, frames_per_cand: int) -> dict:
+    """Per level (0, 1, 2 in turn): if the library chose a grid other than the
+    one-pixel-per-thread one, step ``frames_per_cand`` frames with each of the
+    two, alternating, and keep the other grid only if its ICP time (passes
+    and finish launches) over those frames is 5% lower.  -> {level: {grid: ms per frame}}."""
+    out = {}
+    for lvl in range(3):
+        cur = list(slam.get_launch()["icp_blocks"])
+        full = list(cur)
+        full[lvl] = ICP_FULL
+        slam.set_launch(icp_blocks=full)
+        full_g = slam.get_launch()["icp_blocks"][lvl]
+        if full_g == cur[lvl]:
+            continue
+        cands = {cur[lvl]: 0.0, full_g: 0.0}
+        for _ in range(frames_per_cand):
+            for g in cands:
+                cfg = list(cur)
+                cfg[lvl] = g
+                slam.set_launch(icp_blocks=cfg)
+                before = _icp_ms(slam)
+                slam.step(next(it))
+                cands[g] += _icp_ms(slam) - before
+        keep = cur[lvl] if cands[cur[lvl]] < ICP_PREFER * cands[full_g] else full_g
+        cfg = list(cur)
+        cfg[lvl] = keep
+        slam.set_launch(icp_blocks=cfg)
+        out[lvl] = {str(g): t / frames_per_cand for g, t in cands.items()}
+    return out
+
+
+def tune(slam: "X.Slam", frames, reps: int = 20, fuse_frames_per_grid: int = 2,
+         icp_frames_per_grid: int | None = None) -> dict:
     """Tune on a context that has stepped at least one frame.  ``frames`` is an
-    iterable of device depth frames that continue the sequence (used for the
-    fusion grid: len(FUSE_GRIDS) * fuse_frames_per_grid of them are stepped).
-    -> dict(ray_tile, icp_blocks, fuse_blocks, ms)."""
+    iterable of device depth frames that continue the sequence, at least
+    ``frames_needed(fuse_frames_per_grid, icp_frames_per_grid)`` of them
+    (fusion grid: len(FUSE_GRIDS) * fuse_frames_per_grid; ICP grids on steps:
+    up to 3 levels x 2 grids x icp_frames_per_grid, default
+    fuse_frames_per_grid; 0 skips that check).
+    -> dict(ray_tile, icp_blocks, fuse_blocks, ms, frames): ``frames`` is the
+    number of frames stepped (the ICP check skips a level whose grid is
+    already the one-pixel-per-thread one), so the sequence continues with
+    the frame after them."""
+    if icp_frames_per_grid is None:
+        icp_frames_per_grid = fuse_frames_per_grid
     shapes, ms = slam.autotune(reps)
-    it = iter(frames)
+    used = 0
+
+    def counted():
+        nonlocal used
+        for f in frames:
+            used += 1
+            yield f
+
+    it = counted()
     t_fuse = {g: 0.0 for g in FUSE_GRIDS}
     slam.set_timing(True)
     for _ in range(fuse_frames_per_grid):
@@ -58,14 +121,17 @@ def tune(slam: "X.Slam", frames, reps: int = 20, fuse_frames_per_grid: int = 2) 
             before = slam.kernel_times()[0][2]
             slam.step(next(it))
             t_fuse[g] += slam.kernel_times()[0][2] - before
-    slam.set_timing(False)
     best_fuse = min(FUSE_GRIDS, key=lambda g: t_fuse[g])
     slam.set_launch(fuse_blocks=best_fuse)
+    icp_steps = _icp_on_steps(slam, it, icp_frames_per_grid) if icp_frames_per_grid > 0 else {}
+    slam.set_timing(False)
     out = slam.get_launch()
     out["ms"] = dict(raycast=float(ms[0]), icp=[float(x) for x in ms[1:]],
-                     fuse={str(g): t_fuse[g] / fuse_frames_per_grid for g in FUSE_GRIDS})
+                     fuse={str(g): t_fuse[g] / fuse_frames_per_grid for g in FUSE_GRIDS},
+                     icp_steps={str(k): v for k, v in icp_steps.items()})
     out["ray_tile"] = list(out["ray_tile"])
     out["icp_blocks"] = list(out["icp_blocks"])
+    out["frames"] = used
     return out
 
 
@@ -84,8 +150,10 @@ def tuned(slam: "X.Slam", frames, cache_path: str | None = None, reps: int = 20)
     return out
 
 
-def frames_needed(fuse_frames_per_grid: int = 2) -> int:
-    return len(FUSE_GRIDS) * fuse_frames_per_grid
+def frames_needed(fuse_frames_per_grid: int = 2, icp_frames_per_grid: int | None = None) -> int:
+    if icp_frames_per_grid is None:
+        icp_frames_per_grid = fuse_frames_per_grid
+    return len(FUSE_GRIDS) * fuse_frames_per_grid + 3 * 2 * icp_frames_per_grid
 
 
 __all__ = ["key", "load", "save", "apply", "tune", "tuned", "frames_needed", "FUSE_GRIDS"]

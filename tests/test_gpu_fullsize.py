@@ -128,7 +128,8 @@ def test_fullsize_fp64_autotuned_launch_shapes(inputs):
     slam.step(dev[0])
     shapes = AT.tune(slam, [dev[k] for k in range(1, n - 1)], reps=3, fuse_frames_per_grid=1)
     log("autotuned shapes", shapes)
-    slam.step(dev[n - 1])
+    for k in range(1 + shapes["frames"], n):   # the tuner may step fewer frames than it was given
+        slam.step(dev[k])
     cnt = slam.get(X.F_COUNTERS)
     st = ref["stats"]
     assert np.array_equal(cnt[:, 1], st[:, 3].astype(int))
