@@ -58,7 +58,7 @@ def _icp_ms(slam: "X.Slam") -> float:
     return float(ms[X.TIMER_CLASSES.index("k_icp")] + ms[X.TIMER_CLASSES.index("k_icp_finish")])
 
 
-def _icp_on_steps(slam: "X.Slam", it, frames_per_cand: int) -> dict:
+def _icp_on_steps(slam: "X.Slam", take, frames_per_cand: int) -> dict:
     """Per level (0, 1, 2 in turn): if the library chose a grid other than the
     one-pixel-per-thread one, step ``frames_per_cand`` frames with each of the
     two, alternating, and keep the other grid only if its ICP time (passes
@@ -79,7 +79,7 @@ def _icp_on_steps(slam: "X.Slam", it, frames_per_cand: int) -> dict:
                 cfg[lvl] = g
                 slam.set_launch(icp_blocks=cfg)
                 before = _icp_ms(slam)
-                slam.step(next(it))
+                slam.step(take())
                 cands[g] += _icp_ms(slam) - before
         keep = cur[lvl] if cands[cur[lvl]] < ICP_PREFER * cands[full_g] else full_g
         cfg = list(cur)
@@ -104,27 +104,34 @@ def tune(slam: "X.Slam", frames, reps: int = 20, fuse_frames_per_grid: int = 2,
     if icp_frames_per_grid is None:
         icp_frames_per_grid = fuse_frames_per_grid
     shapes, ms = slam.autotune(reps)
+    it = iter(frames)
     used = 0
 
-    def counted():
+    def take():
         nonlocal used
-        for f in frames:
-            used += 1
-            yield f
+        try:
+            f = next(it)
+        except StopIteration:
+            raise ValueError(f"autotune.tune: ran out of frames after {used}; pass "
+                             f"frames_needed({fuse_frames_per_grid}, {icp_frames_per_grid}) of them") from None
+        used += 1
+        return f
 
-    it = counted()
+    i_fuse = X.TIMER_CLASSES.index("k_fuse")
     t_fuse = {g: 0.0 for g in FUSE_GRIDS}
     slam.set_timing(True)
-    for _ in range(fuse_frames_per_grid):
-        for g in FUSE_GRIDS:
-            slam.set_launch(fuse_blocks=g)
-            before = slam.kernel_times()[0][2]
-            slam.step(next(it))
-            t_fuse[g] += slam.kernel_times()[0][2] - before
-    best_fuse = min(FUSE_GRIDS, key=lambda g: t_fuse[g])
-    slam.set_launch(fuse_blocks=best_fuse)
-    icp_steps = _icp_on_steps(slam, it, icp_frames_per_grid) if icp_frames_per_grid > 0 else {}
-    slam.set_timing(False)
+    try:
+        for _ in range(fuse_frames_per_grid):
+            for g in FUSE_GRIDS:
+                slam.set_launch(fuse_blocks=g)
+                before = slam.kernel_times()[0][i_fuse]
+                slam.step(take())
+                t_fuse[g] += slam.kernel_times()[0][i_fuse] - before
+        best_fuse = min(FUSE_GRIDS, key=lambda g: t_fuse[g])
+        slam.set_launch(fuse_blocks=best_fuse)
+        icp_steps = _icp_on_steps(slam, take, icp_frames_per_grid) if icp_frames_per_grid > 0 else {}
+    finally:
+        slam.set_timing(False)
     out = slam.get_launch()
     out["ms"] = dict(raycast=float(ms[0]), icp=[float(x) for x in ms[1:]],
                      fuse={str(g): t_fuse[g] / fuse_frames_per_grid for g in FUSE_GRIDS},
