@@ -82,6 +82,10 @@ def lib():
         L.orc_track.restype = C.c_int
         L.orc_run_sequence.argtypes = [cp, sp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_traj_err.argtypes = [sp, C.c_int, dp, dp, dp]
+        L.orc_const_vel.argtypes = [sp, dp, dp, C.c_int32, dp]
+        L.orc_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, dp, u8, dp, dp, i32, dp, u8]
+        L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
+        L.orc_raycast_footprint.restype = C.c_int64
         L.orc_eval_f.argtypes = [sp, C.c_double, dp]
         L.orc_eval_g.argtypes = [sp, C.c_double, C.c_double, C.c_int, C.c_int, dp]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -251,6 +255,65 @@ def traj_err(s, poses, gt):
     poses = _f64(poses)
     lib().orc_traj_err(C.byref(s), poses.shape[0], _p(poses), _p(_f64(gt)), _p(out))
     return out
+
+
+def const_vel(s: OrcSeed, T1, T2, both_tracked: bool = True) -> np.ndarray:
+    """Constant-velocity initial estimate from the poses of the last two frames
+    (arrays (4,4,nc)); T1 when not both were tracked."""
+    out = np.zeros((4, 4, ncomp(s)))
+    lib().orc_const_vel(C.byref(s), _p(_f64(T1)), _p(_f64(T2)), int(bool(both_tracked)), _p(out))
+    return out
+
+
+class State:
+    """The state one frame step reads and writes (for state-loaded steps):
+    volume F, W (N, nc) x-fastest; level-0 model maps of the previous frame
+    (V, N (H, W, 3, nc), Z, valid (H, W)); poses of the last two frames T1, T2
+    (4, 4, nc); lost flags of the last two frames; the next frame's index."""
+
+    def __init__(self, c: OrcConfig, s: OrcSeed, T0=None):
+        nc = ncomp(s)
+        nv = c.dim[0] * c.dim[1] * c.dim[2]
+        H, W = c.height, c.width
+        self.F = np.zeros((nv, nc))
+        self.W = np.zeros((nv, nc))
+        self.V = np.zeros((H, W, 3, nc))
+        self.N = np.zeros((H, W, 3, nc))
+        self.Z = np.zeros((H, W))
+        self.valid = np.zeros((H, W), np.uint8)
+        self.T1 = np.zeros((4, 4, nc)) if T0 is None else np.array(_f64(T0), copy=True)
+        self.T2 = self.T1.copy()
+        self.lost = np.zeros(2, np.int32)
+        self.frame = 0
+
+
+def frame_step(c: OrcConfig, s: OrcSeed, st: State, depth, depth_dot=None, touch=None) -> np.ndarray:
+    """One frame step of the sequence from state ``st`` (updated in place).
+    -> stats (6,) as in run_sequence.  ``touch``: optional uint8 array over
+    the volume, OR-ed with the raycast's footprint bits."""
+    for name in ("F", "W", "V", "N", "Z", "T1", "T2"):
+        a = getattr(st, name)
+        if not (a.dtype == np.float64 and a.flags.c_contiguous):
+            setattr(st, name, np.ascontiguousarray(a, dtype=np.float64))
+    st.valid = np.ascontiguousarray(st.valid, dtype=np.uint8)
+    st.lost = np.ascontiguousarray(st.lost, dtype=np.int32)
+    stats = np.zeros(6)
+    lib().orc_frame_step(C.byref(c), C.byref(s), int(st.frame), _p(_f64(depth)), _p(_f64(depth_dot)),
+                         _p(st.F), _p(st.W), _p(st.V), _p(st.N), _p(st.Z), _p(st.valid, C.c_uint8),
+                         _p(st.T1), _p(st.T2), _p(st.lost, C.c_int32), _p(stats), _p(touch, C.c_uint8))
+    st.frame += 1
+    return stats
+
+
+def raycast_footprint(c: OrcConfig, s: OrcSeed, F, W, T, touch=None):
+    """-> (touch (N,) uint8 with bits 1 = marched cells' corners, 2 = corners of
+    cells evaluated at hits; number of hits)."""
+    nv = c.dim[0] * c.dim[1] * c.dim[2]
+    if touch is None:
+        touch = np.zeros(nv, np.uint8)
+    hits = lib().orc_raycast_footprint(C.byref(c), C.byref(s), _p(_f64(F)), _p(_f64(W)), _p(_f64(T)),
+                                       _p(touch, C.c_uint8))
+    return touch, int(hits)
 
 
 def set_threads(n: int) -> None:

@@ -522,6 +522,10 @@ template <class S> struct Volume {
   int dim[3];
   double s;
   std::vector<S> F, W;
+  // optional footprint of the raycast (measurement only, never read back by
+  // the method): bit 1 = a corner of a marched sample's cell, bit 2 = a corner
+  // of a cell evaluated at a hit (the bracket and the six gradient samples)
+  uint8_t* touch = nullptr;
 };
 
 // depth lookup L(x) for fusion: bilinear over 4 valid taps with the same
@@ -577,7 +581,7 @@ int fuse_voxel(const Ctx& X, const Params<S>& P, const int dim[3], double s, int
 // A7. raycast (Sec. 4.1 "Ray casting", eq. surface_prediction)
 // ---------------------------------------------------------------------------
 // trilinear F at a world point; valid only if all 8 corners are observed (W>0)
-template <class S> bool trilinear(const Volume<S>& Vol, const V3<S>& v, S& out) {
+template <class S> bool trilinear(const Volume<S>& Vol, const V3<S>& v, S& out, uint8_t touch_bit = 1) {
   S g[3] = {v.x, v.y, v.z};
   int i0[3];
   S f[3];
@@ -589,6 +593,15 @@ template <class S> bool trilinear(const Volume<S>& Vol, const V3<S>& v, S& out) 
     f[a] = ga - S(fl);
   }
   int nx = Vol.dim[0], ny = Vol.dim[1];
+  if (Vol.touch) {
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          int64_t id = (int64_t(i0[2] + dz) * ny + (i0[1] + dy)) * nx + (i0[0] + dx);
+#pragma omp atomic update
+          Vol.touch[id] |= touch_bit;
+        }
+  }
   S c[8];
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
@@ -664,15 +677,16 @@ Hit<S> raycast_pixel(const Ctx& X, const Params<S>& P, const Volume<S>& Vol, con
       if (f_prev > 0.0 && f < 0.0) {
         // recompute both samples in S and interpolate the crossing
         S F0, F1;
-        trilinear(Vol, o + S(a_prev) * dir, F0);
+        trilinear(Vol, o + S(a_prev) * dir, F0, 2);
         F1 = Fs;
+        if (Vol.touch) trilinear(Vol, v, F1, 2);   // footprint only: same cell, same value
         S a0 = S(a_prev) - S(alpha - a_prev) * F0 / (F1 - F0);
         V3<S> Vg = o + a0 * dir;
         S gr[3];
         for (int a = 0; a < 3; ++a) {
           V3<S> e(S(a == 0 ? s : 0.0), S(a == 1 ? s : 0.0), S(a == 2 ? s : 0.0));
           S fp, fm;
-          if (!trilinear(Vol, Vg + e, fp) || !trilinear(Vol, Vg - e, fm)) return H;
+          if (!trilinear(Vol, Vg + e, fp, 2) || !trilinear(Vol, Vg - e, fm, 2)) return H;
           gr[a] = fp - fm;
         }
         V3<S> g(gr[0], gr[1], gr[2]);
@@ -754,7 +768,33 @@ template <class S> struct State {
   Maps<S> model[3];
   M4<S> T, Tprev;   // current (after the last frame) and the one before
   int frame = 0;
+  int lost1 = 0, lost2 = 0;   // lost flags of the last frame and the one before
 };
+
+// Constant-velocity initial estimate for the ICP of frame k (config init = 1;
+// the paper starts from the previous pose): T1 T2^-1 T1 from the poses of
+// frames k-1 (T1) and k-2 (T2), used only when both of those frames were
+// tracked -- after a lost frame the velocity is unknown and the previous pose
+// T1 is the estimate.  The extrapolated rotation R1 R2^T R1 roughly triples any
+// departure from orthonormality and each prediction starts from the last, so
+// it is brought back by two Newton steps of the polar decomposition,
+// R <- 1.5 R - 0.5 R (R^T R) (quadratic convergence to the nearest rotation);
+// the translation is left as extrapolated.
+template <class S> M4<S> const_velocity(const M4<S>& T1, const M4<S>& T2, bool both_tracked) {
+  if (!both_tracked) return T1;
+  M4<S> P = mul(T1, mul(inverse(T2), T1));
+  for (int it = 0; it < 2; ++it) {
+    S G[3][3], N[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) G[r][c] = P(0, r) * P(0, c) + P(1, r) * P(1, c) + P(2, r) * P(2, c);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        N[r][c] = S(1.5) * P(r, c) - S(0.5) * (P(r, 0) * G[0][c] + P(r, 1) * G[1][c] + P(r, 2) * G[2][c]);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) P(r, c) = N[r][c];
+  }
+  return P;
+}
 
 template <class S>
 M4<S> track(const Ctx& X, const Params<S>& P, const Measured<S>& meas, const Maps<S> model[3],
@@ -795,7 +835,7 @@ void frame_step(const Ctx& X, const Params<S>& P, State<S>& St, const double* D,
   fs = FrameStats{0, 0, 0.0, 0, 0, 0};
   if (St.frame > 0) {
     M4<S> Tinit = St.T;
-    if (X.c.init == 1 && St.frame > 1) Tinit = mul(St.T, mul(inverse(St.Tprev), St.T));
+    if (X.c.init == 1 && St.frame > 1) Tinit = const_velocity(St.T, St.Tprev, !St.lost1 && !St.lost2);
     Normal<S> last;
     int32_t lost = 0;
     M4<S> T = track(X, P, meas, St.model, St.T, Tinit, lost, &last, &fs.cnt_sum);
@@ -803,6 +843,8 @@ void frame_step(const Ctx& X, const Params<S>& P, State<S>& St, const double* D,
     St.Tprev = St.T;
     St.T = T;
   }
+  St.lost2 = St.lost1;
+  St.lost1 = fs.lost;
   if (!fs.lost) fs.n_fused = fuse(X, P, St.vol, meas.Dl[0], St.T);
   St.model[0] = raycast(X, P, St.vol, St.T, sc);
   fs.n_hits = 0;
@@ -1090,6 +1132,80 @@ int orc_track(const OrcConfig* c, const OrcSeed* seed, const double* depth, cons
     if (r2_last) *r2_last = last.r2;
   });
   return lost;
+}
+
+// Constant-velocity initial estimate from the poses of the last two frames
+// (T1 previous, T2 the one before; 16 x ncomp each) and whether both were
+// tracked.  out: 16 x ncomp.
+void orc_const_vel(const OrcSeed* seed, const double* T1, const double* T2, int32_t both_tracked, double* out) {
+  ORC_DISPATCH(seed, {
+    store_pose(out, const_velocity(load_pose<S>(T1), load_pose<S>(T2), both_tracked != 0));
+  });
+}
+
+// One frame step (frame index `frame` >= 1) from a given state, the step the
+// sequence runs: measure, track against the previous frame's level-0 model
+// maps (levels 1, 2 sub-sampled), fuse unless lost, raycast.  In/out: F, Wt
+// (x-fastest volume, ncomp per scalar); Vm, Nm (H x W x 3 x ncomp), Zm, validm
+// (level-0 model maps of the previous frame, replaced by this frame's); T1, T2
+// (poses of the last two frames, replaced by this frame's and the previous);
+// lost12[2] (lost flags of the last two frames, shifted likewise).
+// stats_out[6] as in orc_run_sequence.  touch (optional, one byte per voxel,
+// OR-ed): the raycast's footprint, bit 1 marched cells, bit 2 cells at hits.
+void orc_frame_step(const OrcConfig* c, const OrcSeed* seed, int32_t frame, const double* depth,
+                    const double* depth_dot, double* F, double* Wt, double* Vm, double* Nm, double* Zm,
+                    uint8_t* validm, double* T1, double* T2, int32_t* lost12, double* stats_out,
+                    uint8_t* touch) {
+  Ctx X{*c, *seed};
+  ORC_DISPATCH(seed, {
+    Params<S> P = make_params<S>(X);
+    State<S> St;
+    state_init(X, St);
+    vol_in(St.vol, F, Wt);
+    St.model[0] = maps_in<S>(c->width, c->height, Vm, Nm, Zm, validm);
+    St.model[1] = subsample(St.model[0], 1);
+    St.model[2] = subsample(St.model[0], 2);
+    St.T = load_pose<S>(T1);
+    St.Tprev = load_pose<S>(T2);
+    St.frame = frame;
+    St.lost1 = lost12[0];
+    St.lost2 = lost12[1];
+    St.vol.touch = touch;
+    FrameStats fs;
+    frame_step(X, P, St, depth, depth_dot, fs);
+    vol_out(St.vol, F, Wt);
+    maps_out(St.model[0], Vm, Nm, Zm, validm);
+    store_pose(T1, St.T);
+    store_pose(T2, St.Tprev);
+    lost12[0] = St.lost1;
+    lost12[1] = St.lost2;
+    if (stats_out) {
+      stats_out[0] = fs.lost; stats_out[1] = fs.cnt_last; stats_out[2] = fs.r2_last;
+      stats_out[3] = double(fs.n_fused); stats_out[4] = double(fs.n_hits); stats_out[5] = double(fs.cnt_sum);
+    }
+  });
+}
+
+// Footprint of the raycast of (F, W) at pose T (one byte per voxel, OR-ed):
+// bit 1 = a corner of a marched sample's cell, bit 2 = a corner of a cell
+// evaluated at a hit.  Returns the number of hits.
+int64_t orc_raycast_footprint(const OrcConfig* c, const OrcSeed* seed, const double* F, const double* Wt,
+                              const double* T, uint8_t* touch) {
+  Ctx X{*c, *seed};
+  int64_t hits = 0;
+  ORC_DISPATCH(seed, {
+    Params<S> P = make_params<S>(X);
+    Volume<S> Vol;
+    for (int a = 0; a < 3; ++a) Vol.dim[a] = c->dim[a];
+    Vol.s = c->voxel;
+    int64_t nv = int64_t(c->dim[0]) * c->dim[1] * c->dim[2];
+    Vol.F.resize(nv); Vol.W.resize(nv);
+    vol_in(Vol, F, Wt);
+    Vol.touch = touch;
+    Maps<S> M = raycast(X, P, Vol, load_pose<S>(T));
+    for (uint8_t v : M.valid) hits += v;
+  });
+  return hits;
 }
 
 // Whole sequence: frame 0 at exp(seed) T0, then track/fuse/raycast per frame.
