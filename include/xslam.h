@@ -118,7 +118,7 @@ typedef struct {
 /* get/set fields */
 enum xslam_field {
   XSLAM_F_POSE = 0,      /* current pose: [NC][16] double                                    */
-  XSLAM_F_POSES = 1,     /* pose history: [frames][NC][16] double (get only)                 */
+  XSLAM_F_POSES = 1,     /* pose history: [frames][NC][16] double; set writes rows 0..n-1    */
   XSLAM_F_TSDF = 2,      /* F: [NC][N] in the context precision, N = dims product, x fastest */
   XSLAM_F_WEIGHT = 3,    /* W: [NC][N] (only the re and weight-cap parts can be nonzero)     */
   XSLAM_F_VMAP = 4,      /* model vertex map level 0 (world): [3][NC][H*W]                   */
@@ -135,7 +135,7 @@ enum xslam_field {
                             fusion, 31 raycast samples, 32 first ICP pass (1-based) whose
                             update norm |xi| fell below 1e-6 (0: none),
                             33 initialiser used (1 network, 0 constant velocity),
-                            34..39 reserved (0)                                             */
+                            34..39 reserved (0); set writes rows 0..n-1 (resume)            */
   XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
   XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
 };
@@ -195,7 +195,12 @@ int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out);
  * FP64), no alignment; out (host): NC doubles (value and its parts).  FP64. */
 int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out);
 
-/* host <-> context state copies (host buffers; synchronising) */
+/* host <-> context state copies (host buffers; synchronising).  A checkpoint
+ * that resumes a sequence bit for bit is the set of fields every later frame
+ * reads: TSDF, WEIGHT, VMAP, NMAP, ZMAP, MVALID, POSE, PREV_POSE, POSES,
+ * COUNTERS and FRAME, written back into a context created with the same
+ * configuration and perturbation (brick flags and the level 1-2 model maps
+ * are rebuilt from them). */
 int xslam_get(xslam_ctx ctx, int32_t field, void* dst, size_t bytes);
 int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
 

@@ -86,6 +86,7 @@ def lib():
         L.orc_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, dp, u8, dp, dp, i32, dp, u8]
         L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
         L.orc_raycast_footprint.restype = C.c_int64
+        L.orc_fuse_margin.argtypes = [cp, sp, dp, dp, i64, C.c_int64, dp]
         L.orc_eval_f.argtypes = [sp, C.c_double, dp]
         L.orc_eval_g.argtypes = [sp, C.c_double, C.c_double, C.c_int, C.c_int, dp]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -314,6 +315,15 @@ def raycast_footprint(c: OrcConfig, s: OrcSeed, F, W, T, touch=None):
     hits = lib().orc_raycast_footprint(C.byref(c), C.byref(s), _p(_f64(F)), _p(_f64(W)), _p(_f64(T)),
                                        _p(touch, C.c_uint8))
     return touch, int(hits)
+
+
+def fuse_margin(c: OrcConfig, s: OrcSeed, Df, T, idx) -> np.ndarray:
+    """re(eta) + re(mu) of fusion's update test for the listed voxels (NaN
+    where the voxel is decided before that test)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(len(idx))
+    lib().orc_fuse_margin(C.byref(c), C.byref(s), _p(_f64(Df)), _p(_f64(T)), _p(idx, C.c_int64), len(idx), _p(out))
+    return out
 
 
 def set_threads(n: int) -> None:

@@ -1083,6 +1083,40 @@ int64_t orc_fuse(const OrcConfig* c, const OrcSeed* seed, double* F, double* Wt,
   return count;
 }
 
+// Decision margins of fusion for the listed voxels (measurement of mask
+// mismatches only): out[q] = re(eta) + re(mu), the distance of the update test
+// eta >= -mu from its threshold, for voxels whose projection and depth taps
+// are usable; NaN for voxels decided before that test (behind the camera,
+// outside the image, an invalid tap).
+void orc_fuse_margin(const OrcConfig* c, const OrcSeed* seed, const double* Df, const double* T,
+                     const int64_t* idx, int64_t n_idx, double* out) {
+  Ctx X{*c, *seed};
+  ORC_DISPATCH(seed, {
+    const int nc = NC<S>::n;
+    Params<S> P = make_params<S>(X);
+    int n = c->width * c->height;
+    std::vector<S> D(n);
+    for (int i = 0; i < n; ++i) D[i] = get<S>(Df + i * nc);
+    M4<S> Tp = load_pose<S>(T);
+    int nx = c->dim[0], ny = c->dim[1];
+    double sv = c->voxel;
+    for (int64_t q = 0; q < n_idx; ++q) {
+      int64_t id = idx[q];
+      int i = int(id % nx), j = int((id / nx) % ny), k = int(id / (int64_t(nx) * ny));
+      V3<S> ctr(S((i + 0.5) * sv - 0.5 * nx * sv), S((j + 0.5) * sv - 0.5 * ny * sv),
+                S((k + 0.5) * sv - 0.5 * c->dim[2] * sv));
+      V3<S> x = apply_inv(Tp, ctr);
+      out[q] = std::nan("");
+      if (!(re(x.z) > 0.0)) continue;
+      S ux = P.fx * x.x / x.z + P.cx;
+      S uy = P.fy * x.y / x.z + P.cy;
+      S L;
+      if (!depth_lookup(D, c->width, c->height, ux, uy, c->disc_delta, L)) continue;
+      out[q] = re(L - x.z) + re(P.mu);
+    }
+  });
+}
+
 // Raycast of (F, W) at pose T into level-0 model maps.  If pix != NULL only
 // the n_pix listed pixels (y*W + x) are cast and the outputs hold them in list
 // order; otherwise all pixels.

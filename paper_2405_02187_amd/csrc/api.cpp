@@ -170,12 +170,12 @@ int xslam_raycast(xslam_ctx ctx, const double* pose, void* vmap, void* nmap) {
   return ctx->eng->raycast(pose, vmap, nmap);
 }
 
-static int finish_pose(xslam_ctx ctx, double* pose_out) {
+static int finish_pose(xslam_ctx ctx, double* pose_out, bool stepped) {
   if (!pose_out) return XSLAM_OK;
   int rc = ctx->eng->current_pose(pose_out);
   if (rc) return rc;
   int lost = 0;
-  rc = ctx->eng->frame_lost(&lost);
+  rc = ctx->eng->frame_lost(&lost, stepped);
   if (rc) return rc;
   return lost ? XSLAM_WARN_TRACK_LOST : XSLAM_OK;
 }
@@ -186,14 +186,14 @@ int xslam_track(xslam_ctx ctx, const void* depth, const void* depth_dot, double*
   if (rc) return rc;
   rc = ctx->eng->track();
   if (rc) return rc;
-  return finish_pose(ctx, pose_out);
+  return finish_pose(ctx, pose_out, false);
 }
 
 int xslam_step(xslam_ctx ctx, const void* depth, const void* depth_dot, double* pose_out) {
   XS_CTX_CHECK(ctx);
   int rc = ctx->eng->step(depth, depth_dot);
   if (rc) return rc;
-  return finish_pose(ctx, pose_out);
+  return finish_pose(ctx, pose_out, true);
 }
 
 int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out) {

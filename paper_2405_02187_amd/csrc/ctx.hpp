@@ -20,7 +20,9 @@ struct EngineBase {
   virtual int get(int field, void* dst, size_t bytes) = 0;
   virtual int set(int field, const void* src, size_t bytes) = 0;
   virtual int current_pose(double* out) = 0;
-  virtual int frame_lost(int* lost) = 0;
+  // lost flag of the frame just stepped (stepped) or of the frame tracked
+  // stage by stage, whose counter row is the current frame index
+  virtual int frame_lost(int* lost, bool stepped) = 0;
   virtual int set_cnn(xslam_cnn cnn) = 0;
   virtual int cnn_parts(float* depth, float* model) = 0;
   virtual int set_launch(const xslam_launch& l) = 0;

@@ -782,9 +782,9 @@ struct Engine : EngineBase {
     return sync();
   }
 
-  int frame_lost(int* l) override {
+  int frame_lost(int* l, bool stepped) override {
     int32_t row[kCounters];
-    int f = std::min(frame - 1, C->cfg.max_frames - 1);
+    int f = std::min(stepped ? frame - 1 : frame, C->cfg.max_frames - 1);
     if (f < 0) { *l = 0; return XSLAM_OK; }
     if (hipMemcpyAsync(row, counters + size_t(kCounters) * f, sizeof(row), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
       return check("counters copy");
@@ -884,13 +884,21 @@ struct Engine : EngineBase {
         return put_pose(P, K, pose_from_host(static_cast<const double*>(buf)));
       }
       case XSLAM_F_POSES: {
-        if (!get) return fail(XSLAM_ERR_ARG, "poses: get only");
-        int nf = std::min(frame, C->cfg.max_frames);
-        if (!need(size_t(nf) * NC * 16 * sizeof(double))) return fail(XSLAM_ERR_ARG, "poses: size");
+        if (get) {
+          int nf = std::min(frame, C->cfg.max_frames);
+          if (!need(size_t(nf) * NC * 16 * sizeof(double))) return fail(XSLAM_ERR_ARG, "poses: size");
+          std::vector<MPose<D, Q>> h(nf);
+          int rc = nf ? copy(true, h.data(), hist, nf * sizeof(MPose<D, Q>)) : 0;
+          for (int k = 0; k < nf && !rc; ++k) pose_to_host(h[k], static_cast<double*>(buf) + size_t(k) * NC * 16);
+          return rc;
+        }
+        // resume: rows 0 .. n-1 of the history, n = bytes / (NC*16 doubles)
+        size_t row = size_t(NC) * 16 * sizeof(double);
+        if (bytes % row || bytes / row > size_t(C->cfg.max_frames)) return fail(XSLAM_ERR_ARG, "poses: size");
+        size_t nf = bytes / row;
         std::vector<MPose<D, Q>> h(nf);
-        int rc = nf ? copy(true, h.data(), hist, nf * sizeof(MPose<D, Q>)) : 0;
-        for (int k = 0; k < nf && !rc; ++k) pose_to_host(h[k], static_cast<double*>(buf) + size_t(k) * NC * 16);
-        return rc;
+        for (size_t k = 0; k < nf; ++k) h[k] = pose_from_host(static_cast<const double*>(buf) + k * NC * 16);
+        return nf ? copy(false, h.data(), hist, nf * sizeof(MPose<D, Q>)) : XSLAM_OK;
       }
       case XSLAM_F_TSDF:
       case XSLAM_F_WEIGHT: {
@@ -945,10 +953,16 @@ struct Engine : EngineBase {
         return XSLAM_OK;
       }
       case XSLAM_F_COUNTERS: {
-        if (!get) return fail(XSLAM_ERR_ARG, "counters: get only");
-        int nf = std::min(frame, C->cfg.max_frames);
-        if (!need(size_t(nf) * kCounters * sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "counters: size");
-        return nf ? copy(true, buf, counters, bytes) : XSLAM_OK;
+        size_t row = size_t(kCounters) * sizeof(int32_t);
+        if (get) {
+          int nf = std::min(frame, C->cfg.max_frames);
+          if (!need(size_t(nf) * row)) return fail(XSLAM_ERR_ARG, "counters: size");
+          return nf ? copy(true, buf, counters, bytes) : XSLAM_OK;
+        }
+        // resume: rows 0 .. n-1 (the lost flags of the last two frames decide
+        // whether constant velocity extrapolates)
+        if (bytes % row || bytes / row > size_t(C->cfg.max_frames)) return fail(XSLAM_ERR_ARG, "counters: size");
+        return bytes ? copy(false, buf, counters, bytes) : XSLAM_OK;
       }
       case XSLAM_F_FRAME: {
         if (!need(sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "frame: size");

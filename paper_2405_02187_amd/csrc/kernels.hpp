@@ -1887,11 +1887,23 @@ __global__ void k_traj_err(const MPose<D, Q>* hist, const double* gt, int n, dou
   using J = Jet<double, D, Q>;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   J acc = jzero<J>();
+  double ss[D > 0 ? D : 1] = {};
   for (int k = 0; k < n; ++k)
     for (int r = 0; r < 3; ++r) {
       J d = hist[k].m[9 + r] - gt[k * 16 + r * 4 + 3];
       acc = acc + d * d;
+      for (int a = 0; a < D; ++a) ss[a] = fma(d.v[1 + a], d.v[1 + a], ss[a]);
     }
+  if (acc.v[0] == 0.0) {
+    // the trajectory equals the reference: E = |d|/sqrt(n) has a kink at d = 0
+    // and sqrt's derivative is unbounded there.  The derivative along +theta_a
+    // is the one-sided |d_a|/sqrt(n) (what full complex arithmetic gives:
+    // sqrt(-sum d_a^2 / n) = i |d_a|/sqrt(n)); second-order parts are 0.
+    out[0] = 0.0;
+    for (int a = 0; a < D; ++a) out[1 + a] = sqrt(ss[a] / double(n));
+    for (int c = 1 + D; c < J::N; ++c) out[c] = 0.0;
+    return;
+  }
   J e = jsqrt(acc / double(n));
   for (int c = 0; c < J::N; ++c) out[c] = e.v[c];
 }

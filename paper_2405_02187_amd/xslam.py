@@ -359,8 +359,25 @@ class Slam:
 
     def set(self, field, value):
         shape, dt = self._field_shape(field)
+        if field in (F_POSES, F_COUNTERS):       # any number of history rows
+            shape = (-1,) + shape[1:]
         v = np.ascontiguousarray(value, dtype=dt).reshape(shape)
         self._check(lib().xslam_set(self.h, field, v.ctypes.data_as(C.c_void_p), v.nbytes))
+
+    STATE_FIELDS = (F_TSDF, F_WEIGHT, F_VMAP, F_NMAP, F_ZMAP, F_MVALID, F_POSE, F_PREV_POSE, F_POSES, F_COUNTERS)
+
+    def save_state(self) -> dict:
+        """Host copy of everything later frame steps read (checkpoint)."""
+        st = {f: self.get(f) for f in self.STATE_FIELDS}
+        st[F_FRAME] = self.frame()
+        return st
+
+    def load_state(self, st: dict) -> None:
+        """Resume from a checkpoint taken with save_state on a context of the
+        same configuration and perturbation."""
+        for f in self.STATE_FIELDS:
+            self.set(f, st[f])
+        self.set_frame(st[F_FRAME])
 
     def set_frame(self, k):
         v = np.array([k], np.int32)

@@ -40,3 +40,20 @@ def oracle_map_to_gpu(M):
 def torch_dev(a, dtype):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to("cuda:0")
+
+
+class created_stream:
+    """Run the block on a freshly created stream (contexts created inside
+    replay their captured frame graph; torch's default stream cannot be
+    captured)."""
+
+    def __enter__(self):
+        import torch
+        self.s = torch.cuda.Stream()
+        self.ctx = torch.cuda.stream(self.s)
+        self.ctx.__enter__()
+        return self.s
+
+    def __exit__(self, *exc):
+        self.s.synchronize()
+        return self.ctx.__exit__(*exc)

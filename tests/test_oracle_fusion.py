@@ -103,3 +103,18 @@ def test_identical_frames_fixed_point_and_weight_cap():
         assert np.all(Wt[upd, 0] == min(k + 1, cap))
         dW = Wt[upd, 1] / h
         assert np.all(dW == (1.0 if k + 1 >= cap else 0.0))  # dW/dWcap is 0 until the cap binds
+
+
+def test_fuse_margin_is_the_update_test():
+    """The margin diagnostic (re eta + re mu for voxels reaching the update
+    test) equals the plane's closed form and is >= 0 exactly on the updated
+    voxels."""
+    s = O.seed(0)
+    F, Wt, n = fuse_once(s)
+    idx = np.arange(DIM ** 3)
+    m = O.fuse_margin(cfg(), s, O.lift(np.full((H, W), DEPTH), s), O.lift(pose(), s), idx)
+    upd = Wt[:, 0] > 0
+    reach = ~np.isnan(m)
+    assert np.array_equal(upd, reach & (m >= 0))
+    eta = DEPTH - (centres()[:, 2] + 1.0)
+    assert np.abs(m[reach] - (eta[reach] + MU)).max() < 1e-14
