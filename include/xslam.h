@@ -299,6 +299,16 @@ int xslam_cnn_get_weights(xslam_cnn cnn, float* host, size_t n);
 int xslam_cnn_get_grads(xslam_cnn cnn, float* host, size_t n);           /* of the last train step */
 /* x_dev: n x 5 x 60 x 80 FP32 device; xi_dev: n x 6 FP32 device */
 int xslam_cnn_forward(xslam_cnn cnn, const float* x_dev, int32_t n, float* xi_dev);
+/* xslam_cnn_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the forward activations in a fixed device
+ * array of the library (about 3.9 MB, one per GPU, held until the process
+ * ends) instead of the handle's workspace, so any handle (also one created
+ * with max_batch 1) serves batches of up to 32.  n > 32: XSLAM_ERR_WORKSPACE
+ * with the reason in xslam_cnn_last_error.  Nothing is allocated.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+int xslam_cnn_forward_noalloc(xslam_cnn cnn, const float* x_dev, int32_t n, float* xi_dev);
 /* one Adam step on a batch; label_dev n x 6 FP32 device; loss_out host or NULL */
 int xslam_cnn_train_step(xslam_cnn cnn, const float* x_dev, const float* label_dev, int32_t n, float lr,
                          float* loss_out);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+#include <mutex>
 #include <string>
 #include <vector>
 #include "../../include/xslam.h"
@@ -350,7 +351,62 @@ __global__ void k_sum(const float* __restrict__ a, int n, float* __restrict__ ou
   if (threadIdx.x == 0) *out = s[0];
 }
 
-inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+inline constexpr size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Buffers of one forward pass: the bf16 input and convolution outputs, the
+// pooled features, the hidden layer and the se(3) output (FP32).
+struct FwdBufs {
+  bf16* act[5];
+  float *g, *h5, *xi;
+};
+constexpr size_t fwd_bytes(int B) {
+  size_t s = 0;
+  for (int l = 0; l < 5; ++l) s += al(sizeof(bf16) * size_t(B) * kCh[l] * kH[l] * kW[l]);
+  return s + al(sizeof(float) * size_t(B) * kFc0) + al(sizeof(float) * size_t(B) * kFc1) +
+         al(sizeof(float) * size_t(B) * kFc2);
+}
+inline FwdBufs fwd_plan(int B, char* base) {
+  FwdBufs b;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* q = base + off; off = al(off + bytes); return q; };
+  for (int l = 0; l < 5; ++l) b.act[l] = (bf16*)take(sizeof(bf16) * size_t(B) * kCh[l] * kH[l] * kW[l]);
+  b.g = (float*)take(sizeof(float) * size_t(B) * kFc0);
+  b.h5 = (float*)take(sizeof(float) * size_t(B) * kFc1);
+  b.xi = (float*)take(sizeof(float) * size_t(B) * kFc2);
+  return b;
+}
+
+// Forward buffers of xslam_cnn_forward_noalloc: a fixed device array (about
+// 3.9 MB for 32 samples), one copy per GPU, held until the process ends and
+// shared by every call on that GPU.  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress, per device.
+constexpr int kNoallocMaxBatch = 32;
+constexpr size_t kScratchBytes = fwd_bytes(kNoallocMaxBatch);
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+inline int scratch_address(char** out, std::string& err) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    err = "scratch: no current device";
+    return XSLAM_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+      return XSLAM_ERR_HIP;
+    }
+    g_scratch_dev[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return XSLAM_OK;
+}
 
 struct Cnn {
   int max_batch = 0;
@@ -359,6 +415,7 @@ struct Cnn {
   Offs o;
   int nchunk = 64;
   int64_t step = 0;
+  char* scratch_dev = nullptr;   // device address of the static forward scratch (this handle's GPU)
   // device buffers
   float *prm, *grad, *m, *v, *dxi, *lpart, *loss, *g, *h5, *xi, *part;
   bf16 *wb, *act[5], *dz[5];
@@ -414,19 +471,26 @@ struct Cnn {
     return check("pack");
   }
 
-  template <int L> void conv_fwd(int N) {
+  template <int L> void conv_fwd(int N, bf16* const* a) {
     const int M = N * kH[L + 1] * kW[L + 1];
-    hipLaunchKernelGGL(k_conv_fwd<L>, dim3((M + 63) / 64, kCh[L + 1] / 16), dim3(256), 0, stream, act[L], wl(L),
-                       prm + o.b[L], act[L + 1], N);
+    hipLaunchKernelGGL(k_conv_fwd<L>, dim3((M + 63) / 64, kCh[L + 1] / 16), dim3(256), 0, stream, a[L], wl(L),
+                       prm + o.b[L], a[L + 1], N);
   }
-  int forward(const float* x, int N) {
+  FwdBufs own() {
+    FwdBufs b;
+    for (int l = 0; l < 5; ++l) b.act[l] = act[l];
+    b.g = g; b.h5 = h5; b.xi = xi;
+    return b;
+  }
+  int forward(const float* x, int N) { return forward(x, N, own()); }
+  int forward(const float* x, int N, const FwdBufs& b) {
     const int64_t nin = int64_t(N) * 5 * 60 * 80;
-    hipLaunchKernelGGL(k_to_bf16, dim3((nin + 255) / 256), dim3(256), 0, stream, x, act[0], nin);
-    conv_fwd<0>(N);
-    conv_fwd<1>(N);
-    conv_fwd<2>(N);
-    conv_fwd<3>(N);
-    hipLaunchKernelGGL(k_head_fwd, dim3(N), dim3(128), 0, stream, act[4], prm, o, g, h5, xi);
+    hipLaunchKernelGGL(k_to_bf16, dim3((nin + 255) / 256), dim3(256), 0, stream, x, b.act[0], nin);
+    conv_fwd<0>(N, b.act);
+    conv_fwd<1>(N, b.act);
+    conv_fwd<2>(N, b.act);
+    conv_fwd<3>(N, b.act);
+    hipLaunchKernelGGL(k_head_fwd, dim3(N), dim3(128), 0, stream, b.act[4], prm, o, b.g, b.h5, b.xi);
     return check("cnn forward");
   }
 
@@ -500,6 +564,10 @@ int xslam_cnn_create(void* ws, size_t bytes, void* stream, int32_t max_batch, xs
   h->c.max_batch = max_batch;
   h->c.stream = static_cast<hipStream_t>(stream);
   Cnn::plan(max_batch, &h->c, static_cast<char*>(ws));
+  if (scratch_address(&h->c.scratch_dev, h->c.err) != XSLAM_OK) {
+    delete h;
+    return XSLAM_ERR_HIP;
+  }
   const size_t pb = sizeof(float) * h->c.o.total;
   if (hipMemsetAsync(h->c.m, 0, pb, h->c.stream) != hipSuccess || hipMemsetAsync(h->c.v, 0, pb, h->c.stream) != hipSuccess ||
       hipMemsetAsync(h->c.prm, 0, pb, h->c.stream) != hipSuccess || hipStreamSynchronize(h->c.stream) != hipSuccess) {
@@ -544,6 +612,25 @@ int xslam_cnn_forward(xslam_cnn h, const float* x_dev, int32_t n, float* xi_dev)
   int rc = h->c.forward(x_dev, n);
   if (rc) return rc;
   if (hipMemcpyAsync(xi_dev, h->c.xi, sizeof(float) * 6 * n, hipMemcpyDeviceToDevice, h->c.stream) != hipSuccess)
+    return h->c.check("xi copy");
+  return XSLAM_OK;
+}
+
+int xslam_cnn_forward_noalloc(xslam_cnn h, const float* x_dev, int32_t n, float* xi_dev) {
+  if (!h || !x_dev || !xi_dev || n < 1) return XSLAM_ERR_ARG;
+  if (n > kNoallocMaxBatch) {
+    h->c.err = "forward_noalloc: batch of " + std::to_string(n) + " exceeds the static scratch's maximum of " +
+               std::to_string(kNoallocMaxBatch);
+    return XSLAM_ERR_WORKSPACE;
+  }
+  if (!h->c.scratch_dev) {
+    h->c.err = "forward_noalloc: no scratch address";
+    return XSLAM_ERR_STATE;
+  }
+  const FwdBufs b = fwd_plan(n, h->c.scratch_dev);
+  int rc = h->c.forward(x_dev, n, b);
+  if (rc) return rc;
+  if (hipMemcpyAsync(xi_dev, b.xi, sizeof(float) * 6 * n, hipMemcpyDeviceToDevice, h->c.stream) != hipSuccess)
     return h->c.check("xi copy");
   return XSLAM_OK;
 }

@@ -406,7 +406,8 @@ class Slam:
 # learned ICP initialiser
 # --------------------------------------------------------------------------
 CNN_EXPORTS = ["xslam_cnn_param_count", "xslam_cnn_workspace_bytes", "xslam_cnn_create", "xslam_cnn_set_weights",
-               "xslam_cnn_get_weights", "xslam_cnn_get_grads", "xslam_cnn_forward", "xslam_cnn_train_step",
+               "xslam_cnn_get_weights", "xslam_cnn_get_grads", "xslam_cnn_forward", "xslam_cnn_forward_noalloc",
+               "xslam_cnn_train_step",
                "xslam_cnn_last_error", "xslam_cnn_destroy"]
 
 
@@ -422,6 +423,7 @@ def _cnn_lib():
             "xslam_cnn_get_weights": (C.c_int, [vp, fp, C.c_size_t]),
             "xslam_cnn_get_grads": (C.c_int, [vp, fp, C.c_size_t]),
             "xslam_cnn_forward": (C.c_int, [vp, vp, C.c_int32, vp]),
+            "xslam_cnn_forward_noalloc": (C.c_int, [vp, vp, C.c_int32, vp]),
             "xslam_cnn_train_step": (C.c_int, [vp, vp, vp, C.c_int32, C.c_float, fp]),
             "xslam_cnn_last_error": (C.c_char_p, [vp]),
             "xslam_cnn_destroy": (C.c_int, [vp]),
@@ -526,6 +528,12 @@ class Cnn:
         out = self.torch.empty((x.shape[0], 6), dtype=self.torch.float32, device=x.device)
         self._chk(_cnn_lib().xslam_cnn_forward(self.h, C.c_void_p(x.data_ptr()), x.shape[0], C.c_void_p(out.data_ptr())))
         return out
+
+    def forward_noalloc(self, x, out):
+        """xslam_cnn_forward_noalloc: x (n,5,60,80), out (n,6) float32 device
+        tensors, n <= 32; the activations live in the library's fixed array."""
+        return self._chk(_cnn_lib().xslam_cnn_forward_noalloc(self.h, C.c_void_p(x.data_ptr()), x.shape[0],
+                                                               C.c_void_p(out.data_ptr())))
 
     def train_step(self, x, label, lr=1e-3, want_loss=True):
         loss = C.c_float(0)
