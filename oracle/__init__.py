@@ -49,7 +49,7 @@ class OrcConfig(C.Structure):
                 ("iters", C.c_int32 * 3), ("dgate", C.c_double), ("agate_deg", C.c_double),
                 ("level_w", C.c_double * 3), ("disc_delta", C.c_double),
                 ("bilateral_radius", C.c_int32), ("sigma_px", C.c_double), ("sigma_m", C.c_double),
-                ("near_m", C.c_double), ("init", C.c_int32)]
+                ("near_m", C.c_double), ("init", C.c_int32), ("update", C.c_int32), ("solver", C.c_int32)]
 
 
 class OrcSeed(C.Structure):
@@ -83,6 +83,8 @@ def lib():
         L.orc_run_sequence.argtypes = [cp, sp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_traj_err.argtypes = [sp, C.c_int, dp, dp, dp]
         L.orc_const_vel.argtypes = [sp, dp, dp, C.c_int32, dp]
+        L.orc_small_angle_update.argtypes = [sp, dp, dp, dp]
+        L.orc_icp_energy.argtypes = [cp, C.c_int, dp, dp, u8, dp, dp, dp, u8, dp, dp, C.c_int, C.c_int, dp]
         L.orc_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, dp, u8, dp, dp, i32, dp, u8]
         L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
         L.orc_raycast_footprint.restype = C.c_int64
@@ -101,7 +103,7 @@ def config(p: dict | None = None, **kw) -> OrcConfig:
     d = dict(width=160, height=120, fx=130.0, fy=130.0, cx=79.5, cy=59.5, dim=(128, 128, 128),
              voxel=0.02, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
              level_w=(1.0, 1.0, 1.0), disc_delta=0.1, bilateral_radius=3, sigma_px=4.5,
-             sigma_m=0.03, near_m=0.1, init=0)
+             sigma_m=0.03, near_m=0.1, init=0, update=0, solver=0)
     if p is not None:
         cam = p["camera"]
         d.update(width=cam["width"], height=cam["height"], fx=cam["fx"], fy=cam["fy"],
@@ -221,6 +223,7 @@ def raycast(c, s, F, W, T, pix=None, sched_pose=None, sched_params=None):
 
 
 def track(c, s, depth, depth_dot, model0, Tprev, Tinit):
+    _check_solver(c, s)
     nc = ncomp(s)
     Tout = np.zeros((4, 4, nc))
     cnt = C.c_int64(0); r2 = C.c_double(0)
@@ -231,9 +234,15 @@ def track(c, s, depth, depth_dot, model0, Tprev, Tinit):
     return Tout, lost, cnt.value, r2.value
 
 
+def _check_solver(c, s):
+    if c.solver >= 1 and s.kind != 0:
+        raise ValueError("the Newton solver (solver=1) runs on real seeds only")
+
+
 def run_sequence(c, s, depths, T0, depth_dots=None, want_volume=False, sched_poses=None,
                  sched_params=None):
     """-> dict(poses (n,4,4,nc), stats (n,6), F, W (N,nc) if want_volume)."""
+    _check_solver(c, s)
     nc = ncomp(s)
     depths = _f64(depths)
     n = depths.shape[0]
@@ -266,6 +275,38 @@ def const_vel(s: OrcSeed, T1, T2, both_tracked: bool = True) -> np.ndarray:
     return out
 
 
+def icp_energy(c: OrcConfig, level: int, cur, model, Tprev, T, order: int = 2, through: bool = False):
+    """Newton ICP objective of one pass (real run): E = sum r^2 at pose T (4x4
+    real), its gradient g (6) and Hessian H (6x6) in the left increment, and
+    the correspondence count, with the correspondences held fixed (the
+    objective of one ICP pass) or, ``through``, differentiated through the
+    projective association.  cur/model: maps of that level with one
+    component (as from measure/raycast with a real seed, or lifted).  order
+    0 / 1 skips the Hessian / both derivatives (returned as 0)."""
+    out = np.zeros(29)
+    f = lambda a: _f64(np.asarray(a)[..., :1] if np.asarray(a).ndim >= 3 else a)  # noqa: E731
+    lib().orc_icp_energy(C.byref(c), int(level), _p(f(cur["V"])), _p(f(cur["N"])),
+                         _p(np.ascontiguousarray(cur["valid"], np.uint8), C.c_uint8),
+                         _p(f(model["V"])), _p(f(model["N"])), _p(_f64(model["Z"])),
+                         _p(np.ascontiguousarray(model["valid"], np.uint8), C.c_uint8),
+                         _p(_f64(np.asarray(Tprev)[..., 0] if np.asarray(Tprev).ndim == 3 else Tprev)),
+                         _p(_f64(np.asarray(T)[..., 0] if np.asarray(T).ndim == 3 else T)), int(bool(through)),
+                         int(order), _p(out))
+    H = np.zeros((6, 6))
+    iu = np.triu_indices(6)
+    H[iu] = out[7:28]
+    H = H + np.triu(H, 1).T
+    return out[0], out[1:7].copy(), H, int(out[28])
+
+
+def small_angle_update(s: OrcSeed, xi, T) -> np.ndarray:
+    """The original KinectFusion pose update: small-angle transform of the
+    increment xi (6, nc) composed with T (4, 4, nc), rotation re-orthonormalised."""
+    out = np.zeros((4, 4, ncomp(s)))
+    lib().orc_small_angle_update(C.byref(s), _p(_f64(xi)), _p(_f64(T)), _p(out))
+    return out
+
+
 class State:
     """The state one frame step reads and writes (for state-loaded steps):
     volume F, W (N, nc) x-fastest; level-0 model maps of the previous frame
@@ -292,6 +333,7 @@ def frame_step(c: OrcConfig, s: OrcSeed, st: State, depth, depth_dot=None, touch
     """One frame step of the sequence from state ``st`` (updated in place).
     -> stats (6,) as in run_sequence.  ``touch``: optional uint8 array over
     the volume, OR-ed with the raycast's footprint bits."""
+    _check_solver(c, s)
     for name in ("F", "W", "V", "N", "Z", "T1", "T2"):
         a = getattr(st, name)
         if not (a.dtype == np.float64 and a.flags.c_contiguous):

@@ -223,6 +223,18 @@ template <class S> M4<S> se3_exp(const S xi[6]) {
   return T;
 }
 
+// Small-angle transform of eq. icp_approx (the original KinectFusion
+// linearisation): cos of each angle taken as 1 and sin as the angle, i.e.
+// rotation I + [phi]x and translation rho.
+template <class S> M4<S> small_angle(const S xi[6]) {
+  M4<S> T;
+  T(0, 1) = -xi[2]; T(0, 2) = xi[1];
+  T(1, 0) = xi[2];  T(1, 2) = -xi[0];
+  T(2, 0) = -xi[1]; T(2, 1) = xi[0];
+  for (int r = 0; r < 3; ++r) T(r, 3) = xi[3 + r];
+  return T;
+}
+
 // ---------------------------------------------------------------------------
 // configuration and seeding
 // ---------------------------------------------------------------------------
@@ -249,6 +261,9 @@ struct OrcConfig {
   double sigma_px, sigma_m;  // bilateral spatial (pixels) and range (m) sigmas
   double near_m;             // raycast near plane
   int32_t init;              // 0 previous pose, 1 constant velocity
+  int32_t update;            // 0 exact exponential, 1 small-angle matrix (eq. icp_approx) + polar steps
+  int32_t solver;            // 0 Gauss-Newton; Newton with the complex-step Hessian (real runs only):
+                             // 1 correspondences held fixed per pass, 2 through the association
 };
 struct OrcSeed {
   int32_t kind;  // 0 real, 1 complex (direction pa), 2 bicomplex (pa on i1, pb on i2)
@@ -429,7 +444,7 @@ template <class S> struct Lookup { V3<S> q, m; };
 const double kTapBias = 1e-3;
 
 template <class S>
-bool model_lookup(const Maps<S>& M, const S& ux, const S& uy, double delta, Lookup<S>& out) {
+bool model_lookup(const Maps<S>& M, const S& ux, const S& uy, double delta, Lookup<S>& out, bool hold = false) {
   double rx = re(ux), ry = re(uy);
   double fx0 = std::floor(rx + kTapBias), fy0 = std::floor(ry + kTapBias);
   if (!(fx0 >= 0.0 && fy0 >= 0.0 && fx0 <= double(M.W - 2) && fy0 <= double(M.H - 2))) return false;
@@ -446,7 +461,11 @@ bool model_lookup(const Maps<S>& M, const S& ux, const S& uy, double delta, Look
     out.m = M.N[tn];
     return true;
   }
-  S a = ux - S(double(i0)), b = uy - S(double(j0));
+  // hold: the fractional position taken from the real parts, so the
+  // looked-up point and normal do not move with the pose (the Newton step of
+  // one ICP pass with its correspondences held fixed)
+  S a = hold ? S(rx - double(i0)) : ux - S(double(i0));
+  S b = hold ? S(ry - double(j0)) : uy - S(double(j0));
   S a1 = S(1.0) - a, b1 = S(1.0) - b;
   out.q = b1 * (a1 * M.V[t[0]] + a * M.V[t[1]]) + b * (a1 * M.V[t[2]] + a * M.V[t[3]]);
   V3<S> m = b1 * (a1 * M.N[t[0]] + a * M.N[t[1]]) + b * (a1 * M.N[t[2]] + a * M.N[t[3]]);
@@ -454,31 +473,43 @@ bool model_lookup(const Maps<S>& M, const S& ux, const S& uy, double delta, Look
   return true;
 }
 
+// Point-to-plane residual of current pixel i at pose T (eq. icp): false if the
+// pixel has no correspondence (invalid, behind, outside, invalid taps, gates).
+// J = [p x m; m] is the Jacobian of the residual for the left increment with
+// the correspondence held fixed (the Gauss-Newton linearisation).
+template <class S>
+bool icp_residual(const Ctx& X, const Params<S>& P, const Maps<S>& cur, const Maps<S>& model, const Intr<S>& K,
+                  const M4<S>& Tprev, const M4<S>& T, int i, S& r, S J[6], bool hold = false) {
+  double dg = re(P.dgate);
+  double dg2 = dg * dg;
+  double cosa = std::cos(re(P.agate) * M_PI / 180.0);
+  if (!cur.valid[i]) return false;
+  V3<S> p = apply(T, cur.V[i]);
+  V3<S> n = rotate(T, cur.N[i]);
+  V3<S> xc = apply_inv(Tprev, p);
+  if (!(re(xc.z) > 0.0)) return false;
+  S ux = K.fx * xc.x / xc.z + K.cx;
+  S uy = K.fy * xc.y / xc.z + K.cy;
+  Lookup<S> L;
+  if (!model_lookup(model, ux, uy, X.c.disc_delta, L, hold)) return false;
+  V3<S> d = p - L.q;
+  if (!(re(dot(d, d)) <= dg2)) return false;
+  if (!(re(dot(n, L.m)) >= cosa)) return false;
+  r = dot(d, L.m);
+  V3<S> pm = cross(p, L.m);
+  J[0] = pm.x; J[1] = pm.y; J[2] = pm.z; J[3] = L.m.x; J[4] = L.m.y; J[5] = L.m.z;
+  return true;
+}
+
 template <class S>
 Normal<S> icp_reduce(const Ctx& X, const Params<S>& P, const Maps<S>& cur, const Maps<S>& model,
                      const Intr<S>& K, const M4<S>& Tprev, const M4<S>& T) {
   Normal<S> E;
-  double dg = re(P.dgate);
-  double dg2 = dg * dg;
-  double cosa = std::cos(re(P.agate) * M_PI / 180.0);
   for (int y = 0; y < cur.H; ++y)
     for (int x = 0; x < cur.W; ++x) {
       int i = y * cur.W + x;
-      if (!cur.valid[i]) continue;
-      V3<S> p = apply(T, cur.V[i]);
-      V3<S> n = rotate(T, cur.N[i]);
-      V3<S> xc = apply_inv(Tprev, p);
-      if (!(re(xc.z) > 0.0)) continue;
-      S ux = K.fx * xc.x / xc.z + K.cx;
-      S uy = K.fy * xc.y / xc.z + K.cy;
-      Lookup<S> L;
-      if (!model_lookup(model, ux, uy, X.c.disc_delta, L)) continue;
-      V3<S> d = p - L.q;
-      if (!(re(dot(d, d)) <= dg2)) continue;
-      if (!(re(dot(n, L.m)) >= cosa)) continue;
-      S r = dot(d, L.m);
-      V3<S> pm = cross(p, L.m);
-      S J[6] = {pm.x, pm.y, pm.z, L.m.x, L.m.y, L.m.z};
+      S r, J[6];
+      if (!icp_residual(X, P, cur, model, K, Tprev, T, i, r, J)) continue;
       int k = 0;
       for (int a = 0; a < 6; ++a)
         for (int b = a; b < 6; ++b) E.A[k++] += J[a] * J[b];
@@ -513,6 +544,113 @@ template <class S> bool solve6(const S Au[21], const S b[6], S x[6]) {
     x[r] = s / A[r][r];
   }
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Newton ICP (Sec. 4.1: a second-order ICP with Newton's method at each ICP
+// step, its Hessian by the multicomplex step of eq. csfd_hessian, and no
+// small-angle approximation).  The objective of one pass is
+// E(delta) = sum r(exp(delta) T)^2 over the correspondences, every term
+// evaluated through the whole association (projection, bilinear model lookup
+// with its fractional weights, gates decided on real parts), so its
+// derivatives include how the looked-up model point and normal move with the
+// pose.  The gradient comes from 6 complex-step runs (delta_a = i h), the
+// Hessian from 21 bicomplex runs (delta_a on i1, delta_b on i2; a = b carries
+// both), exact to rounding at h = 1e-20.
+// ---------------------------------------------------------------------------
+template <class S>
+S icp_energy(const Ctx& X, const Params<S>& P, const Maps<S>& cur, const Maps<S>& model, const Intr<S>& K,
+             const M4<S>& Tprev, const M4<S>& T, int64_t* cnt, bool hold) {
+  S E(0.0);
+  int64_t c = 0;
+  for (int i = 0; i < cur.W * cur.H; ++i) {
+    S r, J[6];
+    if (!icp_residual(X, P, cur, model, K, Tprev, T, i, r, J, hold)) continue;
+    E = E + r * r;
+    c += 1;
+  }
+  if (cnt) *cnt = c;
+  return E;
+}
+
+template <class S> Maps<S> lift_maps(const Maps<double>& M) {
+  Maps<S> O;
+  O.W = M.W; O.H = M.H; O.valid = M.valid; O.vvalid = M.vvalid; O.Z = M.Z;
+  O.V.resize(M.V.size()); O.N.resize(M.N.size());
+  for (size_t i = 0; i < M.V.size(); ++i) {
+    O.V[i] = V3<S>(S(M.V[i].x), S(M.V[i].y), S(M.V[i].z));
+    O.N[i] = V3<S>(S(M.N[i].x), S(M.N[i].y), S(M.N[i].z));
+  }
+  return O;
+}
+template <class S> M4<S> lift_pose(const M4<double>& T) {
+  M4<S> O;
+  for (int k = 0; k < 16; ++k) O.m[k] = S(T.m[k]);
+  return O;
+}
+
+struct Derivs { double E; double g[6]; double H[21]; int64_t cnt; };
+
+// E, its gradient and Hessian in the left increment delta at delta = 0, for a
+// real pose T (real parameters: the configuration's own seed is not applied).
+inline Derivs icp_energy_derivs(const Ctx& X, int level, const Maps<double>& cur, const Maps<double>& model,
+                                const M4<double>& Tprev, const M4<double>& T, bool hold, int order = 2) {
+  const double h = 1e-20;
+  Derivs D;
+  for (int a = 0; a < 6; ++a) D.g[a] = 0.0;
+  for (int k = 0; k < 21; ++k) D.H[k] = 0.0;
+  Ctx X0 = X;
+  X0.s = OrcSeed{0, -1, -1, 0.0};
+  Params<double> P0 = make_params<double>(X0);
+  D.E = icp_energy(X0, P0, cur, model, level_intr(P0, X0.c, level), Tprev, T, &D.cnt, hold);
+  if (order < 1) return D;
+  Maps<cd> curc = lift_maps<cd>(cur), modc = lift_maps<cd>(model);
+  for (int a = 0; a < 6; ++a) {
+    Ctx Xa = X;
+    Xa.s = OrcSeed{1, a, -1, h};
+    Params<cd> Pa = make_params<cd>(Xa);
+    cd dx[6];
+    for (int c = 0; c < 6; ++c) dx[c] = Xa.par<cd>(0.0, c);
+    cd E = icp_energy(Xa, Pa, curc, modc, level_intr(Pa, Xa.c, level), lift_pose<cd>(Tprev),
+                      mul(se3_exp(dx), lift_pose<cd>(T)), nullptr, hold);
+    D.g[a] = E.imag() / h;
+  }
+  if (order < 2) return D;
+  Maps<Bicomplex> curb = lift_maps<Bicomplex>(cur), modb = lift_maps<Bicomplex>(model);
+  int k = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b, ++k) {
+      Ctx Xb = X;
+      Xb.s = OrcSeed{2, a, b, h};
+      Params<Bicomplex> Pb = make_params<Bicomplex>(Xb);
+      Bicomplex dx[6];
+      for (int c = 0; c < 6; ++c) dx[c] = Xb.par<Bicomplex>(0.0, c);
+      Bicomplex E = icp_energy(Xb, Pb, curb, modb, level_intr(Pb, Xb.c, level), lift_pose<Bicomplex>(Tprev),
+                               mul(se3_exp(dx), lift_pose<Bicomplex>(T)), nullptr, hold);
+      D.H[k] = E.b.imag() / (h * h);
+    }
+  return D;
+}
+
+// One Newton pass: delta = -H^-1 g when the Hessian's LDL^T pivots pass the
+// solver's test (positive definite), else the Gauss-Newton step of the same
+// pass (classic J, correspondences held fixed).  false: lost.
+inline bool newton_step(const Ctx& X, int level, const Maps<double>& cur, const Maps<double>& model,
+                        const M4<double>& Tprev, const M4<double>& T, double dx[6], int64_t* cnt, double* r2) {
+  // solver 1: correspondences held fixed within the pass; 2: through the association
+  Derivs D = icp_energy_derivs(X, level, cur, model, Tprev, T, X.c.solver == 1);
+  *cnt = D.cnt;
+  *r2 = D.E;
+  if (D.cnt < 6) return false;
+  double Ah[21], bh[6];
+  for (int k = 0; k < 21; ++k) Ah[k] = 0.5 * D.H[k];
+  for (int a = 0; a < 6; ++a) bh[a] = 0.5 * D.g[a];
+  if (solve6(Ah, bh, dx)) return true;
+  Ctx X0 = X;
+  X0.s = OrcSeed{0, -1, -1, 0.0};
+  Params<double> P0 = make_params<double>(X0);
+  Normal<double> G = icp_reduce(X0, P0, cur, model, level_intr(P0, X0.c, level), Tprev, T);
+  return solve6(G.A, G.b, dx);
 }
 
 // ---------------------------------------------------------------------------
@@ -780,9 +918,7 @@ template <class S> struct State {
 // it is brought back by two Newton steps of the polar decomposition,
 // R <- 1.5 R - 0.5 R (R^T R) (quadratic convergence to the nearest rotation);
 // the translation is left as extrapolated.
-template <class S> M4<S> const_velocity(const M4<S>& T1, const M4<S>& T2, bool both_tracked) {
-  if (!both_tracked) return T1;
-  M4<S> P = mul(T1, mul(inverse(T2), T1));
+template <class S> void polar2(M4<S>& P) {
   for (int it = 0; it < 2; ++it) {
     S G[3][3], N[3][3];
     for (int r = 0; r < 3; ++r)
@@ -793,6 +929,11 @@ template <class S> M4<S> const_velocity(const M4<S>& T1, const M4<S>& T2, bool b
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) P(r, c) = N[r][c];
   }
+}
+template <class S> M4<S> const_velocity(const M4<S>& T1, const M4<S>& T2, bool both_tracked) {
+  if (!both_tracked) return T1;
+  M4<S> P = mul(T1, mul(inverse(T2), T1));
+  polar2(P);
   return P;
 }
 
@@ -806,13 +947,39 @@ M4<S> track(const Ctx& X, const Params<S>& P, const Measured<S>& meas, const Map
   for (int l = 2; l >= 0 && !lost; --l) {
     Intr<S> K = level_intr(P, X.c, l);
     for (int it = 0; it < X.c.iters[l]; ++it) {
+      S dx[6];
+      if constexpr (std::is_same<S, double>::value) {
+        if (X.c.solver >= 1) {
+          // Newton pass with the complex-step gradient and Hessian
+          int64_t cnt = 0;
+          double r2 = 0.0;
+          const bool ok = newton_step(X, l, meas.M[l], model[l], Tprev, T, dx, &cnt, &r2);
+          if (last) { last->cnt = cnt; last->r2 = r2; }
+          if (cnt_sum) *cnt_sum += cnt;
+          if (!ok) { lost = 1; break; }
+          for (int a = 0; a < 6; ++a) dx[a] = P.w[l] * dx[a];
+          if (X.c.update == 1) {
+            T = mul(small_angle(dx), T);
+            polar2(T);
+          } else {
+            T = mul(se3_exp(dx), T);
+          }
+          continue;
+        }
+      }
       Normal<S> E = icp_reduce(X, P, meas.M[l], model[l], K, Tprev, T);
       if (last) *last = E;
       if (cnt_sum) *cnt_sum += E.cnt;
-      S dx[6];
       if (E.cnt < 6 || !solve6(E.A, E.b, dx)) { lost = 1; break; }
       for (int a = 0; a < 6; ++a) dx[a] = P.w[l] * dx[a];
-      T = mul(se3_exp(dx), T);
+      if (X.c.update == 1) {
+        // original KinectFusion form: the linearised increment, then the
+        // rotation brought back to orthonormal
+        T = mul(small_angle(dx), T);
+        polar2(T);
+      } else {
+        T = mul(se3_exp(dx), T);
+      }
     }
   }
   if (lost) T = Tinit;
@@ -995,6 +1162,42 @@ void orc_se3_exp(const OrcSeed* seed, const double* xi, double* T) {
     for (int a = 0; a < 6; ++a) x[a] = get<S>(xi + a * NC<S>::n);
     store_pose(T, se3_exp(x));
   });
+}
+
+// Pose increment of the original KinectFusion form: the small-angle transform
+// of eq. icp_approx composed with T (16 x ncomp each), then two polar steps
+// on the rotation.  out: 16 x ncomp.
+void orc_small_angle_update(const OrcSeed* seed, const double* xi, const double* T, double* out) {
+  ORC_DISPATCH(seed, {
+    S x[6];
+    for (int a = 0; a < 6; ++a) x[a] = get<S>(xi + a * NC<S>::n);
+    M4<S> P = mul(small_angle(x), load_pose<S>(T));
+    polar2(P);
+    store_pose(out, P);
+  });
+}
+
+// Newton ICP objective of one pass at level `level` (real run): E = sum r^2 at
+// pose T against the model maps of that level (projection reference Tprev),
+// with the correspondences held fixed (through 0) or differentiated through
+// the association (through 1),
+// its gradient and Hessian in the left increment (order 0: E only, 1: and the
+// gradient, 2: and the Hessian; the others are returned as 0).  out[29]: E,
+// g[6], H (21, upper triangle row-major), correspondence count.
+void orc_icp_energy(const OrcConfig* c, int level, const double* Vc, const double* Nc, const uint8_t* validc,
+                    const double* Vm, const double* Nm, const double* Zm, const uint8_t* validm,
+                    const double* Tprev, const double* T, int through, int order, double* out) {
+  OrcSeed s0{0, -1, -1, 0.0};
+  Ctx X{*c, s0};
+  Params<double> P = make_params<double>(X);
+  Intr<double> K = level_intr(P, X.c, level);
+  Maps<double> cur = maps_in<double>(K.W, K.H, Vc, Nc, nullptr, validc);
+  Maps<double> mod = maps_in<double>(K.W, K.H, Vm, Nm, Zm, validm);
+  Derivs D = icp_energy_derivs(X, level, cur, mod, load_pose<double>(Tprev), load_pose<double>(T), through == 0, order);
+  out[0] = D.E;
+  for (int a = 0; a < 6; ++a) out[1 + a] = D.g[a];
+  for (int k = 0; k < 21; ++k) out[7 + k] = D.H[k];
+  out[28] = double(D.cnt);
 }
 
 // Surface measurement of one frame: filtered depth per level and V/N maps.
