@@ -103,6 +103,26 @@ typedef struct {
                             keeps >= 100 and >= 95% of the correspondences
                             (640 x 480 only; without an attached network it
                             behaves as 1)                                      */
+  int32_t update;        /* pose update of a pass: 0 T <- exp(delta) T, the exact
+                            SE(3) exponential (Sec. 4.1 eqs. lie, rotvector,
+                            rotation_jacobi); 1 the small-angle matrix of eq.
+                            icp_approx (rotation I + [phi]x, translation rho)
+                            composed with T, its rotation then brought back to
+                            orthonormal by two polar Newton steps -- the
+                            original KinectFusion linearisation, kept as a
+                            comparison form                                    */
+  int32_t solver;        /* 0 Gauss-Newton (normal equations of the residual
+                            linearised with the correspondences held fixed);
+                            Newton (Sec. 4.1, the second-order ICP step): per
+                            pass the gradient and Hessian of E = sum r^2 in the
+                            increment from six hyper-dual directions and their
+                            21 pairs (eq. csfd_hessian), with the pass's
+                            correspondences held fixed (1) or differentiated
+                            through the projective association (2);
+                            delta = -H^-1 g when H passes the solver's pivot
+                            test, else the Gauss-Newton step (counter slot 34
+                            counts those passes).  Newton needs a perturbation
+                            of no directions (XSLAM_ERR_ARG otherwise)         */
 } xslam_icp;
 typedef struct {
   int32_t prec;          /* enum xslam_prec                                       */
@@ -135,7 +155,8 @@ enum xslam_field {
                             fusion, 31 raycast samples, 32 first ICP pass (1-based) whose
                             update norm |xi| fell below 1e-6 (0: none),
                             33 initialiser used (1 network, 0 constant velocity),
-                            34..39 reserved (0); set writes rows 0..n-1 (resume)            */
+                            34 Newton passes that took the Gauss-Newton step,
+                            35..39 reserved (0); set writes rows 0..n-1 (resume)            */
   XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
   XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
 };
@@ -190,6 +211,19 @@ int xslam_step(xslam_ctx ctx, const void* depth, const void* depth_dot, double* 
  * doubles (21 upper-triangle entries of A row-major, then b), followed by
  * 2 doubles: correspondence count and sum of squared real residuals. */
 int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out);
+
+/* The Newton objective of one ICP pass at level `level` (Sec. 4.1, the
+ * second-order ICP step): E = sum of squared point-to-plane residuals between
+ * the measured maps and the model maps of that level at the current pose
+ * (projection reference: XSLAM_F_PREV_POSE), with its gradient and Hessian in
+ * the left increment exp(delta) T.  through 0: the pass's correspondences
+ * held fixed (the looked-up model point and normal are constants); through 1:
+ * every residual differentiated through the projection, the bilinear model
+ * lookup and its fractional weights (gates decided on real parts).  out
+ * (host, 29 doubles): E, g[6], H (21, upper triangle row-major, order phi_x
+ * phi_y phi_z rho_x rho_y rho_z), count.  Only for contexts with no
+ * directions (XSLAM_ERR_UNSUPPORTED otherwise). */
+int xslam_icp_energy(xslam_ctx ctx, int32_t level, int32_t through, double* out);
 
 /* Translational RMSE of the pose history against gt_poses (host, n x 16
  * FP64), no alignment; out (host): NC doubles (value and its parts).  FP64. */

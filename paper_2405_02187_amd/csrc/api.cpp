@@ -53,6 +53,8 @@ static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, 
   if (c->icp.iters[0] + c->icp.iters[1] + c->icp.iters[2] > 25) return bad("icp iterations: at most 25 passes");
   if (!(c->icp.dgate > 0)) return bad("dgate");
   if (c->icp.init < 0 || c->icp.init > 2) return bad("icp.init must be 0, 1 or 2");
+  if (c->icp.update < 0 || c->icp.update > 1) return bad("icp.update must be 0 or 1");
+  if (c->icp.solver < 0 || c->icp.solver > 2) return bad("icp.solver must be 0, 1 or 2");
   if (c->icp.init == 2 && (c->cam.width % 64 || c->cam.height % 32 || c->cam.width / 8 != 80 || c->cam.height / 8 != 60))
     return bad("icp.init 2 (network) needs 640 x 480 depth (a 80 x 60 level-3 input)");
   if (c->bilateral_radius < 0 || c->bilateral_radius > 4) return bad("bilateral radius must be 0..4");
@@ -62,6 +64,9 @@ static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, 
   int nd = p ? p->n_dirs : 0, np = p ? p->n_pairs : 0;
   if (nd < 0 || nd > kMaxDirsApi) return bad("n_dirs must be 0..16");
   if (nd > 0 && !p->dirs) return bad("dirs is NULL");
+  if (c->icp.solver >= 1 && (nd > 0 || np > 0))
+    return bad("icp.solver 1 or 2 (Newton) needs a perturbation with no directions: the increment's six directions "
+               "and their pairs fill the jet");
   if (np > 0 && !p->pairs) return bad("pairs is NULL");
   *ndd = 0;
   *wtan = false;
@@ -200,6 +205,12 @@ int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out) {
   XS_CTX_CHECK(ctx);
   if (!sums_out) return XSLAM_ERR_ARG;
   return ctx->eng->icp_pass(level, sums_out);
+}
+
+int xslam_icp_energy(xslam_ctx ctx, int32_t level, int32_t through, double* out) {
+  XS_CTX_CHECK(ctx);
+  if (!out || through < 0 || through > 1) return XSLAM_ERR_ARG;
+  return ctx->eng->icp_energy(level, through, out);
 }
 
 int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out) {

@@ -200,6 +200,48 @@ __device__ __forceinline__ Jet<double, D, Q> se3_exp_mul_entry(const Jet<double,
   return c < 3 ? prod : prod + tr;
 }
 
+// Entry (r, c) of T_sa(xi) * P with T_sa the small-angle transform of eq.
+// icp_approx: rotation I + [phi]x (cos taken as 1, sin as the angle),
+// translation rho.
+template <int D, int Q>
+__device__ __forceinline__ Jet<double, D, Q> smallangle_mul_entry(const Jet<double, D, Q> xi[6],
+                                                                  const MPose<D, Q>* __restrict__ P, int r, int c) {
+  using J = Jet<double, D, Q>;
+  const J z = jzero<J>();
+  const J K[9] = {z, -xi[2], xi[1], xi[2], z, -xi[0], -xi[1], xi[0], z};
+  J Er[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Er[k] = jconst<J>(r == k ? 1.0 : 0.0) + K[r * 3 + k];
+  const J p0 = c < 3 ? P->m[0 * 3 + c] : P->m[9 + 0];
+  const J p1 = c < 3 ? P->m[1 * 3 + c] : P->m[9 + 1];
+  const J p2 = c < 3 ? P->m[2 * 3 + c] : P->m[9 + 2];
+  const J prod = Er[0] * p0 + Er[1] * p1 + Er[2] * p2;
+  return c < 3 ? prod : prod + xi[3 + r];
+}
+
+// Two Newton steps of the polar decomposition, R <- 1.5 R - 0.5 R (R^T R),
+// on a row-major 3x3 rotation estimate (quadratic convergence to the nearest
+// rotation).
+template <int D, int Q>
+__device__ __forceinline__ void polar_steps(Jet<double, D, Q> R[9]) {
+  using J = Jet<double, D, Q>;
+  for (int it = 0; it < 2; ++it) {
+    J G[9], N[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) G[a * 3 + b] = R[0 * 3 + a] * R[0 * 3 + b] + R[1 * 3 + a] * R[1 * 3 + b] + R[2 * 3 + a] * R[2 * 3 + b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        N[a * 3 + b] = 1.5 * R[a * 3 + b] -
+                       0.5 * (R[a * 3 + 0] * G[0 * 3 + b] + R[a * 3 + 1] * G[1 * 3 + b] + R[a * 3 + 2] * G[2 * 3 + b]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R[q] = N[q];
+  }
+}
+
 // brick layout: brick (bx,by,bz) of 8^3 voxels stored contiguously, x fastest inside
 XJ int64_t vox_index(int i, int j, int k, const int nbr[3]) {
   int64_t b = (int64_t(k >> 3) * nbr[1] + (j >> 3)) * nbr[0] + (i >> 3);

@@ -1,5 +1,6 @@
 // Host-side context of the C ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
@@ -7,6 +8,19 @@
 #include "../../include/xslam.h"
 
 namespace xs {
+
+// Event pair of the launch in progress (timing mode; null otherwise).  With
+// events the kernel goes through hipExtLaunchKernelGGL, whose dispatch stamps
+// them with the kernel's own start and end.
+inline thread_local hipEvent_t tl_ev0 = nullptr;
+inline thread_local hipEvent_t tl_ev1 = nullptr;
+#define XS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                                   \
+  do {                                                                                                      \
+    if (::xs::tl_ev0)                                                                                       \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ::xs::tl_ev0, ::xs::tl_ev1, 0, __VA_ARGS__); \
+    else                                                                                                    \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                                  \
+  } while (0)
 
 struct EngineBase {
   virtual ~EngineBase() {}
@@ -16,6 +30,7 @@ struct EngineBase {
   virtual int track() = 0;
   virtual int step(const void* depth, const void* ddot) = 0;
   virtual int icp_pass(int level, double* out) = 0;
+  virtual int icp_energy(int level, int through, double* out) = 0;
   virtual int traj_err(const double* gt, int n, double* out) = 0;
   virtual int get(int field, void* dst, size_t bytes) = 0;
   virtual int set(int field, const void* src, size_t bytes) = 0;

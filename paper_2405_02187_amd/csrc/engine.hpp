@@ -9,6 +9,7 @@
 #include <vector>
 #include "ctx.hpp"
 #include "kernels.hpp"
+#include "newton.hpp"
 
 namespace xs {
 
@@ -104,7 +105,8 @@ struct Engine : EngineBase {
     double* dhi[3] = {nullptr, nullptr, nullptr};
     if (std::is_same<T, float>::value)
       for (int l = 0; l < 3; ++l) dhi[l] = cv.take<double>(size_t(c.cam.width >> l) * (c.cam.height >> l));
-    double* partials = cv.take<double>(size_t(kMaxIcpBlocks) * NS);
+    // (real runs may use the Newton pass, whose partials are wider)
+    double* partials = cv.take<double>(size_t(kMaxIcpBlocks) * ((D == 0 && Q == 0 && kNewtonNS > NS) ? kNewtonNS : NS));
     int* lost = cv.take<int>(1);
     MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
     MPose<D, Q>* hist = cv.take<MPose<D, Q>>(c.max_frames);
@@ -172,20 +174,21 @@ struct Engine : EngineBase {
 
   // kernel launch with optional event timing; cls: 0 measurement, 1 k_icp, 2 k_fuse, 3 k_raymarch,
   // 4 other, 5 k_icp_finish, 6 k_rayhit, 7 k_brick_cull
+  // (timing: the dispatch itself stamps the event pair with its kernel's
+  // start and end, so the pair brackets that kernel and nothing else)
   template <typename F> int launch(int cls, const char* what, F&& f) {
     Timer& tm = C->timer;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm.on && tm.next + 2 <= tm.pool.size()) {
       e0 = tm.pool[tm.next++];
       e1 = tm.pool[tm.next++];
-      hipEventRecord(e0, C->stream);
     }
+    tl_ev0 = e0;
+    tl_ev1 = e1;
     f();
+    tl_ev0 = tl_ev1 = nullptr;
     int rc = check(what);
-    if (e1) {
-      hipEventRecord(e1, C->stream);
-      tm.pending.push_back({cls, {e0, e1}});
-    }
+    if (e1) tm.pending.push_back({cls, {e0, e1}});
     return rc;
   }
 
@@ -275,7 +278,7 @@ struct Engine : EngineBase {
   template <typename P> int fill(P* p, P v, int64_t n) {
     if (n <= 0) return XSLAM_OK;
     int blocks = int(std::min<int64_t>((n + 255) / 256, 4096));
-    return launch(4, "fill", [&] { hipLaunchKernelGGL(k_fill<P>, dim3(blocks), dim3(256), 0, C->stream, p, v, n); });
+    return launch(4, "fill", [&] { XS_LAUNCH(k_fill<P>, dim3(blocks), dim3(256), 0, C->stream, p, v, n); });
   }
 
   int put_pose(MPose<D, Q>* dst, KPose<T, D, Q>* kdst, const MPose<D, Q>& P) {
@@ -314,13 +317,13 @@ struct Engine : EngineBase {
     TrackBegin<T, D, Q> tb{};
     if (begin_track) tb = track_begin_args();
     if ((rc = launch(0, "bilateral", [&] {
-           hipLaunchKernelGGL((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0], tb);
+           XS_LAUNCH((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0], tb);
          })))
       return rc;
     for (int l = 1; l < 3; ++l) {
       dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
       if ((rc = launch(0, "pyrdown", [&] {
-             hipLaunchKernelGGL((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l],
+             XS_LAUNCH((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l],
                                 Dhi[l - 1], Dhi[l]);
            })))
         return rc;
@@ -334,7 +337,7 @@ struct Engine : EngineBase {
       lv.first[l + 1] = lv.first[l] + lv.tiles_x[l] * ((H[l] + 15) / 16);
     }
     if ((rc = launch(0, "vertex_normal", [&] {
-           hipLaunchKernelGGL((k_vertex_normal<T, D, Q>), dim3(lv.first[3]), b, 0, C->stream, kp, lv);
+           XS_LAUNCH((k_vertex_normal<T, D, Q>), dim3(lv.first[3]), b, 0, C->stream, kp, lv);
          })))
       return rc;
     measured = true;
@@ -348,17 +351,33 @@ struct Engine : EngineBase {
     a.V = Vl[l]; a.N = Nl[l]; a.valid = valid[l];
     a.Vm = Vm[l]; a.Nm = Nm[l]; a.Zm = Zm[l]; a.validm = mvalid[l];
     a.W = W[l]; a.H = H[l]; a.level = l; a.iter_slot = iter_slot; a.do_solve = do_solve;
-    a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l];
+    a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l]; a.update = C->cfg.icp.update;
     a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums_out ? sums_out : sums;
     a.frame = dframe; a.max_frames = C->cfg.max_frames;
     int blocks = icp_grid[l] > 0 ? icp_grid[l]
                                  : int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+    if (C->cfg.icp.solver >= 1) {
+      if constexpr (D == 0 && Q == 0) {
+        int rc = launch(1, "icp_newton", [&] {
+          if (C->cfg.icp.solver == 1)
+            XS_LAUNCH((k_icp_newton<T, D, Q, true>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
+          else
+            XS_LAUNCH((k_icp_newton<T, D, Q, false>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
+        });
+        if (rc) return rc;
+        return launch(5, "icp_newton_finish", [&] {
+          XS_LAUNCH((k_icp_newton_finish<T, D, Q>), dim3(1), dim3(256), 0, C->stream, a, blocks);
+        });
+      } else {
+        return fail(XSLAM_ERR_UNSUPPORTED, "icp: the Newton solver needs a perturbation with no directions");
+      }
+    }
     int rc = launch(1, "icp", [&] {
-      hipLaunchKernelGGL((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
+      XS_LAUNCH((k_icp<T, D, Q>), dim3(blocks), dim3(kIcpThreads), 0, C->stream, kp, a);
     });
     if (rc) return rc;
     return launch(5, "icp_finish", [&] {
-      hipLaunchKernelGGL((k_icp_finish<T, D, Q>), dim3(1), dim3(kFinishThreads<T, D, Q>), 0, C->stream, a, blocks);
+      XS_LAUNCH((k_icp_finish<T, D, Q>), dim3(1), dim3(kFinishThreads<T, D, Q>), 0, C->stream, a, blocks);
     });
   }
 
@@ -368,7 +387,7 @@ struct Engine : EngineBase {
     if (!measured) return fail(XSLAM_ERR_STATE, "track: no measured frame");
     if (!have_model) return fail(XSLAM_ERR_STATE, "track: no model maps (raycast first)");
     if (!begun && (rc = launch(4, "track_begin", [&] {
-                    hipLaunchKernelGGL((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, track_begin_args());
+                    XS_LAUNCH((k_track_begin<T, D, Q>), dim3(1), dim3(64), 0, C->stream, track_begin_args());
                   })))
       return rc;
     if (C->cfg.icp.init == 2 && cnn && (rc = learned_init())) return rc;
@@ -383,7 +402,7 @@ struct Engine : EngineBase {
   int enqueue_cnn_parts(const KPose<T, D, Q>* K, float* out_depth, float* out_model) {
     dim3 b(16, 16), g(((W[0] >> 3) + 15) / 16, ((H[0] >> 3) + 15) / 16);
     return launch(4, "cnn_parts", [&] {
-      hipLaunchKernelGGL((k_cnn_parts<T, D, Q>), g, b, 0, C->stream, kp, Dl[2], Nm[0], Zm[0], mvalid[0], K,
+      XS_LAUNCH((k_cnn_parts<T, D, Q>), g, b, 0, C->stream, kp, Dl[2], Nm[0], Zm[0], mvalid[0], K,
                          out_depth, out_model);
     });
   }
@@ -396,18 +415,18 @@ struct Engine : EngineBase {
     if ((rc = enqueue_cnn_parts(Kprev, cnn_in, cnn_in + n3))) return rc;
     if ((rc = xslam_cnn_forward(cnn, cnn_in, 1, cnn_xi))) return fail(rc, "learned init: network forward");
     if ((rc = launch(4, "init_candidates", [&] {
-           hipLaunchKernelGGL((k_init_candidates<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pprev, Pinit, cnn_xi,
+           XS_LAUNCH((k_init_candidates<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pprev, Pinit, cnn_xi,
                               Pcand, Pcur, Kcur);
          })))
       return rc;
     if ((rc = run_icp_level(2, 0, 0, sums_net))) return rc;
     if ((rc = launch(4, "set_current", [&] {
-           hipLaunchKernelGGL((k_set_current<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pinit, Pcur, Kcur);
+           XS_LAUNCH((k_set_current<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pinit, Pcur, Kcur);
          })))
       return rc;
     if ((rc = run_icp_level(2, 0, 0, sums_cv))) return rc;
     return launch(4, "choose_init", [&] {
-      hipLaunchKernelGGL((k_choose_init<T, D, Q>), dim3(1), dim3(64), 0, C->stream, sums_net, sums_cv, NS, Pcand,
+      XS_LAUNCH((k_choose_init<T, D, Q>), dim3(1), dim3(64), 0, C->stream, sums_net, sums_cv, NS, Pcand,
                          Pinit, Pcur, Kcur, counters, dframe, C->cfg.max_frames);
     });
   }
@@ -581,7 +600,7 @@ struct Engine : EngineBase {
   // lost fallback + pose history (tracked frames), reset of the brick list
   int post_track(bool tracked, bool store) {
     return launch(4, "post_track", [&] {
-      hipLaunchKernelGGL((k_post_track<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pinit, Kcur,
+      XS_LAUNCH((k_post_track<T, D, Q>), dim3(1), dim3(64), 0, C->stream, Pcur, Pinit, Kcur,
                          tracked ? lost : nullptr, store ? hist : nullptr, dframe, C->cfg.max_frames, bcount);
     });
   }
@@ -596,24 +615,24 @@ struct Engine : EngineBase {
     const PostTrack<T, D, Q> post{Pcur, Pinit, Kcur, tracked ? lost : nullptr, store ? hist : nullptr,
                                   dframe, C->cfg.max_frames, bcount};
     if ((rc = launch(4, "tile_zmax", [&] {
-           hipLaunchKernelGGL((k_tile_zmax<T, D, Q>), dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0],
+           XS_LAUNCH((k_tile_zmax<T, D, Q>), dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0],
                               tzmax, czmax, post);
          })))
       return rc;
     if ((rc = launch(7, "brick_cull", [&] {
-           hipLaunchKernelGGL((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
+           XS_LAUNCH((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
                               tzmax, czmax, nbrick, blist, bcount, lost);
          })))
       return rc;
     const int g = std::min(nbrick, fuse_grid);
     if ((rc = launch(2, "fuse", [&] {
-           hipLaunchKernelGGL((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
+           XS_LAUNCH((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
                               Wtan, lost, nvox, blist, bcount, fcounts);
          })))
       return rc;
     // (the brick flags' workgroup 0 also sums the fusion counts)
     return launch(4, "brick_flags", [&] {
-      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick,
+      XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick,
                          fcounts, g, counters, dframe, C->cfg.max_frames);
     });
   }
@@ -621,7 +640,7 @@ struct Engine : EngineBase {
   int all_brick_flags() {
     const int g = std::min(nbrick, 4096);
     int rc = launch(4, "brick_flags_all", [&] {
-      hipLaunchKernelGGL(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, nullptr, nullptr,
+      XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, nullptr, nullptr,
                          nbrick, nullptr, 0, nullptr, nullptr, 0);
     });
     return rc ? rc : sync();
@@ -634,16 +653,16 @@ struct Engine : EngineBase {
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
     dim3 b(ray_bx, ray_by), g((W[0] + ray_bx - 1) / ray_bx, (H[0] + ray_by - 1) / ray_by);
     int rc = launch(3, "raymarch", [&] {
-      hipLaunchKernelGGL((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
+      XS_LAUNCH((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
     });
     if (rc) return rc;
     rc = launch(6, "rayhit", [&] {
-      hipLaunchKernelGGL((k_rayhit<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, bracket, o, rhits);
+      XS_LAUNCH((k_rayhit<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, bracket, o, rhits);
     });
     if (rc) return rc;
     const int nrb = int(g.x * g.y);
     rc = launch(4, "sum_counts", [&] {
-      hipLaunchKernelGGL(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, rsamples, nrb, counters,
+      XS_LAUNCH(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, rsamples, nrb, counters,
                          dframe, C->cfg.max_frames, 2, 31, nullptr, 0, end_frame ? dframe : nullptr);
     });
     if (!rc) have_model = true;
@@ -769,12 +788,34 @@ struct Engine : EngineBase {
     return sync();
   }
 
+  // E, gradient, Hessian and count of the Newton objective of one pass at the
+  // current pose (no solve); real runs only
+  int icp_energy(int level, int through, double* out) override {
+    if (level < 0 || level > 2) return fail(XSLAM_ERR_ARG, "icp_energy: level");
+    if constexpr (D == 0 && Q == 0) {
+      if (!measured) return fail(XSLAM_ERR_STATE, "icp_energy: no measured frame");
+      if (!have_model) return fail(XSLAM_ERR_STATE, "icp_energy: no model maps");
+      const int solver = C->cfg.icp.solver;
+      C->cfg.icp.solver = through ? 2 : 1;
+      int rc = fill<int>(lost, 0, 1);
+      if (!rc) rc = run_icp_level(level, 0, 0);
+      C->cfg.icp.solver = solver;
+      if (rc) return rc;
+      if (hipMemcpyAsync(out, sums, kNewtonOut * sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+        return check("sums copy");
+      return sync();
+    } else {
+      (void)out;
+      return fail(XSLAM_ERR_UNSUPPORTED, "icp_energy: real runs only (a perturbation with no directions)");
+    }
+  }
+
   int traj_err(const double* gtp, int n, double* out) override {
     if (n <= 0 || n > frame || n > C->cfg.max_frames) return fail(XSLAM_ERR_ARG, "traj_err: n");
     if (hipMemcpyAsync(gt, gtp, size_t(16) * n * sizeof(double), hipMemcpyHostToDevice, C->stream) != hipSuccess)
       return check("gt upload");
     int rc = launch(4, "traj_err", [&] {
-      hipLaunchKernelGGL((k_traj_err<D, Q>), dim3(1), dim3(64), 0, C->stream, hist, gt, n, traj);
+      XS_LAUNCH((k_traj_err<D, Q>), dim3(1), dim3(64), 0, C->stream, hist, gt, n, traj);
     });
     if (rc) return rc;
     if (hipMemcpyAsync(out, traj, NC * sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
@@ -837,7 +878,7 @@ struct Engine : EngineBase {
       int rc;
       if (get) {
         if ((rc = launch(4, "vol_gather", [&] {
-               hipLaunchKernelGGL(k_vol_gather<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
+               XS_LAUNCH(k_vol_gather<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
                                   nvox, kp.dim[0], kp.dim[1], kp.nbr[0], kp.nbr[1], s0, cnt, stage);
              })))
           return rc;
@@ -848,7 +889,7 @@ struct Engine : EngineBase {
         if (hipMemcpyAsync(stage, host + s0, cnt * sizeof(T), hipMemcpyHostToDevice, C->stream) != hipSuccess)
           return check("vol copy");
         if ((rc = launch(4, "vol_scatter", [&] {
-               hipLaunchKernelGGL(k_vol_scatter<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
+               XS_LAUNCH(k_vol_scatter<T>, dim3(blocks), dim3(256), 0, C->stream, rec, Ftan, Wtan, kind, comp,
                                   nvox, kp.dim[0], kp.dim[1], kp.nbr[0], kp.nbr[1], s0, cnt, stage);
              })))
           return rc;

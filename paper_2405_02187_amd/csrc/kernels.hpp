@@ -338,6 +338,7 @@ struct IcpArgs {
   const T* V; const T* N; const uint8_t* valid;               // current level (camera frame)
   const T* Vm; const T* Nm; const T* Zm; const uint8_t* validm;  // model level (world frame)
   int W, H, level, iter_slot, do_solve;
+  int update;                  // 0 exact exponential, 1 small-angle matrix + polar steps
   KPose<T, D, Q>* Kcur;        // current estimate (kernel precision), updated by the last block
   const KPose<T, D, Q>* Kprev; // projection reference T_{k-1}
   MPose<D, Q>* Pcur;           // current estimate (FP64 master)
@@ -595,7 +596,10 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6], int lane,
 // the pixel gives no correspondence.  J is the jet of the computation (the
 // context's, or a chunk of its parts), ld(base, index) loads a 3-vector map
 // entry as a J.
-template <typename J, typename KP, typename LD, typename T, int D, int Q>
+// kHold: the bilinear lookup's fractional position is taken from the real
+// parts, so the looked-up model point and normal do not move with the jet's
+// directions (the correspondences of a pass held fixed).
+template <bool kHold = false, typename J, typename KP, typename LD, typename T, int D, int Q>
 __device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g, const KP& Tc,
                                                const KP& Tp, const J& fx, const J& fy, const J& cx, const J& cy,
                                                size_t n, size_t i, J jac[6], J& r, LD&& ld) {
@@ -660,7 +664,7 @@ __device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const
         m = ld(g.Nm, tn);
       }
     } else {
-      const J a = ux - fx0, b = uy - fy0;
+      const J a = kHold ? jconst<J>(rx - fx0) : ux - fx0, b = kHold ? jconst<J>(ry - fy0) : uy - fy0;
       const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
       q = vadd(vscale(b1, vadd(vscale(a1, q0), vscale(a, q1))), vscale(b, vadd(vscale(a1, q2), vscale(a, q3))));
       V3<J> mm = vadd(vscale(b1, vadd(vscale(a1, m0), vscale(a, m1))), vscale(b, vadd(vscale(a1, m2), vscale(a, m3))));
@@ -677,7 +681,7 @@ __device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const
       q = ld(g.Vm, tn);
       m = ld(g.Nm, tn);
     } else {
-      const J a = ux - fx0, b = uy - fy0;
+      const J a = kHold ? jconst<J>(rx - fx0) : ux - fx0, b = kHold ? jconst<J>(ry - fy0) : uy - fy0;
       const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - b;
       const V3<J> q0 = ld(g.Vm, t0), q1 = ld(g.Vm, t1);
       const V3<J> q2 = ld(g.Vm, t2), q3 = ld(g.Vm, t3);
@@ -782,7 +786,23 @@ __device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, i
   // the update exp(dx) * P, one of its 12 entries per lane
   if (lane >= 12) return;
   const int r = lane >> 2, c = lane & 3;
-  const Jet<double, D, Q> e = se3_exp_mul_entry<D, Q>(dx, g.Pcur, r, c);
+  Jet<double, D, Q> e = g.update ? smallangle_mul_entry<D, Q>(dx, g.Pcur, r, c)
+                                 : se3_exp_mul_entry<D, Q>(dx, g.Pcur, r, c);
+  if (g.update) {
+    // the composed rotation back to orthonormal: every lane gathers the nine
+    // rotation entries and runs the same two polar Newton steps on them
+    using JD = Jet<double, D, Q>;
+    __shared__ JD Rsh[9];
+    if (c < 3) Rsh[r * 3 + c] = e;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    JD R[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R[q] = Rsh[q];
+    polar_steps<D, Q>(R);
+    if (c < 3) e = R[r * 3 + c];
+  }
   // (every lane has read its column of P: the lanes of one wave issue their
   // loads together, before any of them stores)
   __builtin_amdgcn_wave_barrier();
@@ -1060,21 +1080,8 @@ __device__ void track_begin_work(const TrackBegin<T, D, Q>& a) {
       init = pose_mul(*a.Pprev, pose_mul(pose_inverse(*a.Pprev2), *a.Pprev));
       // R1 R2^T R1 triples the rotation's departure from orthonormality, and
       // the next prediction starts from it: two Newton steps of the polar
-      // decomposition, R <- (3R - R R^T R)/2, keep it at rounding level
-      for (int it = 0; it < 2; ++it) {
-        using JD = Jet<double, D, Q>;
-        JD RtR[9], N[9];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c)
-            RtR[r * 3 + c] = init.m[0 * 3 + r] * init.m[0 * 3 + c] + init.m[1 * 3 + r] * init.m[1 * 3 + c] +
-                             init.m[2 * 3 + r] * init.m[2 * 3 + c];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c)
-            N[r * 3 + c] = 1.5 * init.m[r * 3 + c] -
-                           0.5 * (init.m[r * 3 + 0] * RtR[0 * 3 + c] + init.m[r * 3 + 1] * RtR[1 * 3 + c] +
-                                  init.m[r * 3 + 2] * RtR[2 * 3 + c]);
-        for (int q = 0; q < 9; ++q) init.m[q] = N[q];
-      }
+      // decomposition keep it at rounding level
+      polar_steps<D, Q>(init.m);
     }
   }
   *a.Pinit = init;

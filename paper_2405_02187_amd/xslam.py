@@ -52,7 +52,8 @@ class xslam_volume(C.Structure):
 
 class xslam_icp(C.Structure):
     _fields_ = [("iters", C.c_int32 * 3), ("dgate", C.c_double), ("agate_deg", C.c_double),
-                ("level_w", C.c_double * 3), ("disc_delta", C.c_double), ("init", C.c_int32)]
+                ("level_w", C.c_double * 3), ("disc_delta", C.c_double), ("init", C.c_int32),
+                ("update", C.c_int32), ("solver", C.c_int32)]
 
 
 class xslam_launch(C.Structure):
@@ -89,6 +90,7 @@ def lib():
             "xslam_step": (C.c_int, [vp, vp, vp, dp]),
             "xslam_icp_pass": (C.c_int, [vp, C.c_int32, dp]),
             "xslam_traj_err": (C.c_int, [vp, dp, C.c_int32, dp]),
+            "xslam_icp_energy": (C.c_int, [vp, C.c_int32, C.c_int32, dp]),
             "xslam_get": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
             "xslam_set": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
             "xslam_set_timing": (C.c_int, [vp, C.c_int32]),
@@ -116,7 +118,7 @@ def lib():
 
 
 EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
-           "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_traj_err", "xslam_get",
+           "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_icp_energy", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
            "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
            "xslam_autotune", "xslam_frame_graph", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
@@ -130,8 +132,8 @@ class XslamError(RuntimeError):
 # --------------------------------------------------------------------------
 def make_config(prec=C64, width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5, dim=(512, 512, 512),
                 voxel=0.01, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
-                level_w=(1.0, 1.0, 1.0), disc_delta=0.1, init=0, bilateral_radius=3, sigma_px=4.5, sigma_m=0.03,
-                near_m=0.1, max_frames=512) -> xslam_config:
+                level_w=(1.0, 1.0, 1.0), disc_delta=0.1, init=0, update=0, solver=0, bilateral_radius=3, sigma_px=4.5,
+                sigma_m=0.03, near_m=0.1, max_frames=512) -> xslam_config:
     c = xslam_config()
     c.prec = prec
     c.cam = xslam_camera(width, height, fx, fy, cx, cy)
@@ -140,7 +142,7 @@ def make_config(prec=C64, width=640, height=480, fx=525.0, fy=525.0, cx=319.5, c
     c.icp.iters[:] = list(iters)
     c.icp.dgate, c.icp.agate_deg = dgate, agate_deg
     c.icp.level_w[:] = list(level_w)
-    c.icp.disc_delta, c.icp.init = disc_delta, init
+    c.icp.disc_delta, c.icp.init, c.icp.update, c.icp.solver = disc_delta, init, update, solver
     c.bilateral_radius, c.bilateral_sigma_px, c.bilateral_sigma_m = bilateral_radius, sigma_px, sigma_m
     c.near_m, c.max_frames = near_m, max_frames
     return c
@@ -259,6 +261,19 @@ class Slam:
         out = np.zeros(ns)
         self._check(lib().xslam_icp_pass(self.h, level, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out[:27 * self.nc].reshape(27, self.nc), out[27 * self.nc], out[27 * self.nc + 1]
+
+    def icp_energy(self, level, through=False):
+        """Newton objective of one ICP pass at the current pose, correspondences
+        held fixed (or differentiated through the association): -> (E,
+        gradient (6,), Hessian (6, 6), count)."""
+        out = np.zeros(29)
+        self._check(lib().xslam_icp_energy(self.h, int(level), int(bool(through)),
+                                           out.ctypes.data_as(C.POINTER(C.c_double))))
+        H = np.zeros((6, 6))
+        iu = np.triu_indices(6)
+        H[iu] = out[7:28]
+        H = H + np.triu(H, 1).T
+        return out[0], out[1:7].copy(), H, int(out[28])
 
     def traj_err(self, gt):
         gt = np.ascontiguousarray(gt, np.float64).reshape(-1, 16)

@@ -1,0 +1,70 @@
+"""GPU parity of the comparison forms of the ICP against the oracle, and the
+frame-step robustness study.
+
+* The original-KinectFusion update (eq. icp_approx: the small-angle
+  increment, rotation re-orthonormalised) on the 20-frame 128^3 FP64-complex
+  sequence: counts equal, poses and derivative within 1e-10 of the oracle.
+* Frame steps 1/2/3 (Sec. 5.1's robustness comparison, on the synthetic
+  640x480 / 512^3 spline): the exact-exponential, small-angle and Newton forms
+  run through the library on the subsampled sequence; their trajectory errors
+  are logged (a measurement, not a parity claim).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as sg
+from gpu_util import created_stream, gpu_pose_to_oracle, log, relerr, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_02187_amd import xslam as X  # noqa: E402
+
+H20 = 1e-20
+
+
+@pytest.mark.parametrize("param", [O.P_TRUNC, O.P_PHI_Z])
+def test_small_angle_form_matches_oracle(param):
+    p = sg.preset("c0")
+    seq = sg.make_sequence(p)
+    d = seq.depths().astype(np.float64)
+    T0 = seq.poses_gt[0]
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=len(d), update=1)
+        slam = X.Slam(cfg, X.Perturbation([(param, H20)]), T0)
+        dev = torch_dev(d, np.float64)
+        for k in range(len(d)):
+            slam.step(dev[k])
+        cnt = slam.get(X.F_COUNTERS)
+        P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+        assert slam.frame_graph()
+        slam.close()
+    ref = O.run_sequence(O.config(p, update=1), O.seed(1, param, h=H20), d, T0)
+    st = ref["stats"]
+    assert np.array_equal(cnt[:, 0], st[:, 0].astype(int))
+    assert np.array_equal(cnt[:, 1], st[:, 3].astype(int))
+    assert np.array_equal(cnt[:, 2], st[:, 4].astype(int))
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
+    e0, e1 = relerr(P[..., 0], ref["poses"][..., 0]), relerr(P[..., 1], ref["poses"][..., 1])
+    log("small-angle form fp64 vs oracle: pose", e0, "derivative", e1)
+    assert e0 <= 1e-10 and e1 <= 1e-10
+
+
+def test_frame_step_robustness_study_runs():
+    from paper_2405_02187_amd import robustness as RB
+    p = sg.preset("c1")
+    n = 30
+    seq = sg.make_sequence(p, n_frames=1 + 3 * (n - 1))
+    d = seq.depths(workers=min(16, os.cpu_count() or 1)).astype(np.float32)
+    with created_stream():
+        res = RB.run(p, d, seq.poses_gt, steps=(1, 2, 3), n_frames=n)
+    for r in res:
+        log("frame step", r)
+        assert np.isfinite(r["ate_m"])
+    assert len(res) == 12
