@@ -41,50 +41,92 @@ def fusion_bytes_per_voxel(nc: int, wtan: bool, tsize: int = 4) -> int:
     return 2 * per
 
 
-def cpu_baseline(p, seq, n_ray_stride=32):
-    """Oracle (plain C++ FP64-complex, one thread) on a bounded sample of one
-    frame step: full measurement, 19 full ICP passes against model maps built
-    from the previous frame, full fusion, raycast of every n-th pixel (scaled)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cmul4(A, B):
+    """(4,4,2) complex 4x4 product (re, im planes)."""
+    c = (A[..., 0] + 1j * A[..., 1]) @ (B[..., 0] + 1j * B[..., 1])
+    return np.stack([c.real, c.imag], -1)
+
+
+def cpu_baseline(p, seq, setup_threads=16):
+    """The oracle (plain C++ FP64-complex loops, one thread) timed on this
+    host: the 128^3 / 160x120 / 20-frame sequence in full, and one whole frame
+    step of the headline workload (frame 1 at 640x480 / 512^3: measurement,
+    19 ICP passes, fusion of the whole volume, raycast of every pixel) from
+    the oracle's own state after frame 0 (built untimed with
+    ``setup_threads`` threads)."""
     import oracle as O
+    import scenegen as sg
+    nproc = os.cpu_count() or 1
+    out = dict(unit="frames·directions/s", cores=1, kind="oracle", nproc=nproc, cpu_model=_cpu_model())
+    # the 20-frame 128^3 sequence, one direction (truncation), in full
+    p0 = sg.preset("c0")
+    s0 = sg.make_sequence(p0)
+    d0 = s0.depths().astype(np.float64)
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    O.run_sequence(O.config(p0), O.seed(1, O.P_TRUNC, h=1e-20), d0, s0.poses_gt[0])
+    t_c0 = time.perf_counter() - t0
+    out["seq128_full"] = dict(value=len(d0) / t_c0, frames=len(d0), seconds=t_c0,
+                              workload="seq160x120_tsdf128_2cm_fp64complex_1dir")
+    # headline workload: frame 1 from the oracle's state after frame 0
     c = O.config(p)
     s = O.seed(1, O.P_PHI_X, h=1e-20)
-    d0, d1 = seq.frame(0)[0].astype(np.float64), seq.frame(1)[0].astype(np.float64)
-    T0 = seq.poses_gt[0]
-    t = {}
+    xi = np.zeros((6, 2))
+    xi[0, 1] = 1e-20
+    T0 = _cmul4(O.se3_exp(s, xi), O.lift(seq.poses_gt[0], s))
+    st = O.State(c, s)
+    st.T1 = T0
+    st.T2 = T0.copy()
+    f0, f1 = seq.frame(0)[0].astype(np.float64), seq.frame(1)[0].astype(np.float64)
+    O.set_threads(min(setup_threads, nproc))
+    O.frame_step(c, s, st, f0)
+    O.set_threads(1)
     t0 = time.perf_counter()
-    m1 = O.measure(c, s, d1)
-    t["measure"] = time.perf_counter() - t0
-    m0 = O.measure(c, s, d0)
-    # model maps of the previous frame in world coordinates (stand-in for its raycast)
-    R, tr = T0[:3, :3], T0[:3, 3]
-    models = []
-    for l in range(3):
-        V = np.einsum("ij,hwjc->hwic", R, m0[l]["V"])
-        V[..., 0] += tr
-        N = np.einsum("ij,hwjc->hwic", R, m0[l]["N"])
-        models.append(dict(V=V, N=N, Z=m0[l]["D"][..., 0].copy(), valid=m0[l]["valid"]))
-    Tl = O.lift(T0, s)
+    stats = O.frame_step(c, s, st, f1)
+    t1 = time.perf_counter() - t0
+    del st
+    out["value"] = 1.0 / t1
+    out["sample"] = (f"one whole 640x480/512^3 frame step (frame 1, 1 complex direction) on 1 of {nproc} host "
+                     f"cores: measurement, 19 ICP passes ({int(stats[5])} correspondences), fusion of the "
+                     f"whole volume ({int(stats[3])} voxels updated), raycast of all 307200 pixels "
+                     f"({int(stats[4])} hits): {t1:.1f}s; the oracle's state after frame 0 was built untimed")
+    return out
+
+
+def raycast_footprint(X, slam, p, threads=16):
+    """Distinct voxels the raycast of the context's current state touches:
+    the oracle's footprint bitset (every corner of every marched sample's
+    cell) on the TSDF and pose the context holds.  Measurement only: no
+    result of the benchmark is taken from the oracle here."""
+    import oracle as O
     t0 = time.perf_counter()
-    for l, iters in ((2, 4), (1, 5), (0, 10)):
-        for _ in range(iters):
-            O.icp_reduce(c, s, l, m1[l], models[l], Tl, Tl)
-    t["icp"] = time.perf_counter() - t0
-    nv = c.dim[0] * c.dim[1] * c.dim[2]
-    F = np.zeros((nv, 2))
-    W = np.zeros((nv, 2))
-    t0 = time.perf_counter()
-    F, W, nfused = O.fuse(c, s, F, W, m1[0]["D"], Tl)
-    t["fuse"] = time.perf_counter() - t0
-    pix = np.arange(0, c.width * c.height, n_ray_stride, dtype=np.int32)
-    t0 = time.perf_counter()
-    O.raycast(c, s, F, W, Tl, pix=pix)
-    t["raycast_sample"] = time.perf_counter() - t0
-    total = t["measure"] + t["icp"] + t["fuse"] + t["raycast_sample"] * n_ray_stride
-    return dict(value=1.0 / total, unit="frames·directions/s", cores=1, kind="oracle",
-                sample=(f"one 640x480/512^3 frame step, 1 complex direction: full measurement "
-                        f"({t['measure']:.2f}s), 19 full ICP passes ({t['icp']:.2f}s), full fusion "
-                        f"({t['fuse']:.2f}s, {nfused} voxels updated), raycast of every {n_ray_stride}th pixel "
-                        f"({t['raycast_sample']:.2f}s, scaled x{n_ray_stride}); estimated {total:.1f}s per frame"))
+    F = slam.get(X.F_TSDF)
+    Wt = slam.get(X.F_WEIGHT)
+    s = O.seed(0)                      # real parts decide every sample: the real march's footprint
+    Fo = np.ascontiguousarray(F[0], dtype=np.float64)[:, None]
+    del F
+    Wo = np.ascontiguousarray(Wt[0], dtype=np.float64)[:, None]
+    del Wt
+    T = slam.get(X.F_POSE)[0][..., None]   # real part of the pose, (4, 4, 1)
+    O.set_threads(min(threads, os.cpu_count() or 1))
+    touch, hits = O.raycast_footprint(O.config(p), s, Fo, Wo, T)
+    del Fo, Wo
+    n1 = int(np.count_nonzero(touch & 1))
+    n2 = int(np.count_nonzero(touch & 2))
+    n = int(np.count_nonzero(touch))
+    log(f"raycast footprint: {n} voxels ({n1} marched, {n2} at hits), {hits} hits, "
+        f"{time.perf_counter() - t0:.1f}s")
+    return dict(voxels=n, marched=n1, at_hits=n2, hits=hits, frame=slam.frame() - 1)
 
 
 def pmc_traffic(kernel: str):
@@ -211,6 +253,10 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=24)
     ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--fill-steps", type=int, default=20,
+                    help="graph-replayed frames queued ahead of the event-timed ones")
+    ap.add_argument("--no-footprint", dest="footprint", action="store_false",
+                    help="skip the oracle's count of the voxels the raycast touches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
     ap.add_argument("--no-forms", action="store_true", help="only the headline workload")
@@ -245,7 +291,7 @@ def main():
         del src, dst
 
     p = sg.preset("c1")
-    n_frames = args.warmup + args.steps + args.timing_steps
+    n_frames = args.warmup + args.steps + args.fill_steps + args.timing_steps
     assert n_frames <= p["n_frames"], "the sequence has 500 frames"
     t0 = time.perf_counter()
     seq = sg.make_sequence(p, n_frames=n_frames)
@@ -261,6 +307,7 @@ def main():
 
     from paper_2405_02187_amd import autotune as AT
     shapes = None
+    k_start = 0
     if not args.no_autotune and args.warmup >= 2 + AT.frames_needed(2):
         slam.step(dev[0])
         t0 = time.perf_counter()
@@ -268,8 +315,14 @@ def main():
         shapes = {k: tuned[k] for k in ("ray_tile", "icp_blocks", "fuse_blocks")}
         log(f"autotuned in {time.perf_counter() - t0:.1f}s: {tuned}")
         k_start = 1 + tuned["frames"]
-    else:
-        k_start = 0
+    elif not args.no_autotune:
+        # warm-up too short to tune: the shapes the tuner chose for this
+        # workload on an MI355X, committed with the package
+        cached = AT.load(AT.SHAPES_FILE).get(AT.key(slam))
+        if cached:
+            shapes = {k: cached[k] for k in ("ray_tile", "icp_blocks", "fuse_blocks")}
+            AT.apply(slam, shapes)
+            log(f"launch shapes from {os.path.basename(AT.SHAPES_FILE)}: {shapes}")
     for k in range(k_start, args.warmup):
         slam.step(dev[k])
     slam.sync()
@@ -284,55 +337,69 @@ def main():
     graph_used = slam.frame_graph()
     log(f"{args.steps} frame steps in {dt:.3f}s (frame graph: {graph_used})")
 
-    # per-kernel durations with HIP events on the library's stream
-    # (the counts accumulate over the context's life: the autotuner's timed
-    # steps are taken out as the difference)
-    slam.set_timing(True)
+    # per-kernel durations with HIP events on the library's stream.  The
+    # host first queues `fill` graph-replayed frames, then the timed frames
+    # launch eagerly with an event pair around every kernel: they are queued
+    # behind the fill frames, so the GPU runs them back to back and each
+    # event pair brackets its kernel (not the host's launch latency).
     ms0, launches0 = slam.kernel_times()
     k0 = args.warmup + args.steps
-    for k in range(k0, k0 + args.timing_steps):
+    for k in range(k0, k0 + args.fill_steps):
+        slam.step(dev[k])
+    slam.set_timing(True)
+    k1 = k0 + args.fill_steps
+    for k in range(k1, k1 + args.timing_steps):
         slam.step(dev[k])
     ms, launches = slam.kernel_times()
+    slam.set_timing(False)
     ms, launches = ms - ms0, launches - launches0
-    cnt = slam.get(X.F_COUNTERS)[k0:k0 + args.timing_steps]
+    cnt = slam.get(X.F_COUNTERS)[k1:k1 + args.timing_steps]
     per = {c: dict(ms_total=float(ms[i]), launches=int(launches[i]),
                    us_per_launch=float(1e3 * ms[i] / max(launches[i], 1))) for i, c in enumerate(X.TIMER_CLASSES)}
     fused = float(cnt[:, 1].mean())
     tsize = 4 if prec == X.C64 else 8
     nc = pert.ncomp
-    bpv = fusion_bytes_per_voxel(nc, False, tsize)
+    D = nc - 1
     npx = cfg.cam.width * cfg.cam.height
 
-    def avg_s(i):
-        return ms[i] / max(launches[i], 1) / 1e3
+    def avg_us(i):
+        return 1e3 * ms[i] / max(launches[i], 1)
 
-    # k_fuse: read + write of every updated voxel, plus the filtered depth
+    # algorithmic bytes per unit of work, as the hot-path table states them:
+    # fusion: read + write of every updated voxel's (F_re, D F parts, W), plus
+    #   the filtered depth (re + D parts) it reads
+    bpv = fusion_bytes_per_voxel(nc, False, tsize)
     fuse_bytes = fused * bpv + npx * nc * tsize
-    # k_icp: each pass reads the current maps (V, N with nc components, validity)
-    # and the model maps of its level (V, N, depth, validity) once; averaged
-    # over the passes of a frame (10 at level 0, 5 at level 1, 4 at level 2)
+    # ICP: per pixel-iteration the current pixel and its 4 model taps, each a
+    #   vertex and a normal of (1 + D) components: 5 * 6 * (4 + 4D) B at FP32;
+    #   3,532,800 pixel-iterations per frame (10/5/4 passes at levels 0/1/2),
+    #   averaged over the 19 launches
     iters = list(cfg.icp.iters)
-    bpp = (12 * nc + 1) * tsize + 2
-    icp_bytes = sum(iters[l] * (npx >> (2 * l)) * bpp for l in range(3)) / sum(iters)
-    # k_raymarch: the voxels its samples touch are not counted here; the bytes
-    # it must write (the bracket of every ray) are a lower bound
-    march_bytes = npx * 2 * tsize
-    # k_rayhit: the model maps it writes (levels 0-2) plus the 8 records and
-    # nc - 1 tangents of the two bracketing samples of every hit
-    hits = float(cnt[:, 2].mean())
-    hit_bytes = sum(npx >> (2 * l) for l in range(3)) * (6 * nc * tsize + tsize + 1) + hits * 2 * 8 * (
-        2 * tsize + (nc - 1) * tsize)
+    pix_iters = sum(iters[l] * (npx >> (2 * l)) for l in range(3))
+    icp_bytes = pix_iters * 5 * 6 * nc * tsize / sum(iters)
+    # raycast (march + hit): every distinct voxel a sample neighbourhood
+    #   touches, (F_re, D parts, W) each, plus the level-0 model maps written;
+    #   the voxels are counted exactly by the oracle's footprint bitset on the
+    #   state of the last timed frame
+    touched = raycast_footprint(X, slam, p) if args.footprint else None
+    ray_bytes = None if touched is None else touched["voxels"] * (tsize + D * tsize + tsize) + npx * 6 * nc * tsize
+    ray_us = avg_us(3) + avg_us(6)
     kern = {
-        "k_fuse": dict(bytes=fuse_bytes, us=avg_s(2) * 1e6, frame_ms=ms[2] / args.timing_steps),
-        "k_icp": dict(bytes=icp_bytes, us=avg_s(1) * 1e6, frame_ms=ms[1] / args.timing_steps,
-                      note="maps of the pass's level read once; they stay in the 256 MB last-level cache across "
-                           "passes, so the kernel is latency-bound and this is its HBM-equivalent rate"),
-        "k_icp_finish": dict(bytes=None, us=avg_s(5) * 1e6, frame_ms=ms[5] / args.timing_steps,
+        "k_icp": dict(bytes=icp_bytes, us=avg_us(1), frame_ms=ms[1] / args.timing_steps,
+                      unit="5 x 6 x (4+4D) B per pixel-iteration", units_per_launch=pix_iters / sum(iters),
+                      note="the 4 model taps are mostly served by the 256 MB last-level cache: a latency- and "
+                           "cache-bound kernel, reported against HBM peak"),
+        "k_fuse": dict(bytes=fuse_bytes, us=avg_us(2), frame_ms=ms[2] / args.timing_steps,
+                       unit=f"{bpv} B per updated voxel + filtered depth", units_per_launch=fused),
+        "raycast": dict(bytes=ray_bytes, us=ray_us, frame_ms=(ms[3] + ms[6]) / args.timing_steps,
+                        unit=f"{2 * tsize + D * tsize} B per distinct voxel touched + level-0 maps",
+                        units_per_launch=None if touched is None else touched["voxels"], footprint=touched,
+                        kernels="k_raymarch + k_rayhit"),
+        "k_icp_finish": dict(bytes=None, us=avg_us(5), frame_ms=ms[5] / args.timing_steps,
                              note="one workgroup: cross-workgroup FP64 sum, 6x6 solve, SE(3) update (latency)"),
-        "k_raymarch": dict(bytes=march_bytes, us=avg_s(3) * 1e6, frame_ms=ms[3] / args.timing_steps,
-                           note="bracket writes only (lower bound: the voxels the samples touch are not counted)"),
-        "k_rayhit": dict(bytes=hit_bytes, us=avg_s(6) * 1e6, frame_ms=ms[6] / args.timing_steps),
-        "k_brick_cull": dict(bytes=None, us=avg_s(7) * 1e6, frame_ms=ms[7] / args.timing_steps),
+        "k_raymarch": dict(bytes=None, us=avg_us(3), frame_ms=ms[3] / args.timing_steps),
+        "k_rayhit": dict(bytes=None, us=avg_us(6), frame_ms=ms[6] / args.timing_steps),
+        "k_brick_cull": dict(bytes=None, us=avg_us(7), frame_ms=ms[7] / args.timing_steps),
     }
     for k in kern.values():
         if k["bytes"] is not None and k["us"] > 0:

@@ -21,6 +21,9 @@ import os
 from . import xslam as X
 
 FUSE_GRIDS = (4096, 2048, 1024, 512)
+# shapes the tuner chose on an MI355X, per workload key (used when there is no
+# time to tune, e.g. a short benchmark warm-up)
+SHAPES_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_shapes.json")
 ICP_FULL = 0          # ICP workgroups value of the one-pixel-per-thread grid
 ICP_PREFER = 0.95     # a grid other than the one-pixel-per-thread one must be 5% faster
 
