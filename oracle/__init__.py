@@ -85,6 +85,7 @@ def lib():
         L.orc_const_vel.argtypes = [sp, dp, dp, C.c_int32, dp]
         L.orc_small_angle_update.argtypes = [sp, dp, dp, dp]
         L.orc_icp_energy.argtypes = [cp, C.c_int, dp, dp, u8, dp, dp, dp, u8, dp, dp, C.c_int, C.c_int, dp]
+        L.orc_reloc_energy.argtypes = [cp, dp, dp, dp, dp, C.c_int, dp]
         L.orc_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, dp, u8, dp, dp, i32, dp, u8]
         L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
         L.orc_raycast_footprint.restype = C.c_int64
@@ -292,6 +293,29 @@ def icp_energy(c: OrcConfig, level: int, cur, model, Tprev, T, order: int = 2, t
                          _p(_f64(np.asarray(Tprev)[..., 0] if np.asarray(Tprev).ndim == 3 else Tprev)),
                          _p(_f64(np.asarray(T)[..., 0] if np.asarray(T).ndim == 3 else T)), int(bool(through)),
                          int(order), _p(out))
+    H = np.zeros((6, 6))
+    iu = np.triu_indices(6)
+    H[iu] = out[7:28]
+    H = H + np.triu(H, 1).T
+    return out[0], out[1:7].copy(), H, int(out[28])
+
+
+def reloc_energy(c: OrcConfig, F, W, Df, T, order: int = 2):
+    """Relocalisation objective (Sec. 5.2): E(T) = sum over the voxels of
+    (F_r - F_q)^2, F_q the reference volume (F, W: real, (N,) or (N, nc),
+    x-fastest) after fusing the query's filtered level-0 depth Df (H, W) at
+    the real pose T (4x4), with its gradient g (6) and Hessian H (6x6) in the
+    left increment exp(delta) T (6 complex-step and 21 bicomplex evaluations),
+    and the number of contributing voxels.  order 0 / 1 skips the Hessian /
+    both derivatives (returned as 0)."""
+    F = np.asarray(F)
+    W = np.asarray(W)
+    f = lambda a: _f64(a[:, 0] if a.ndim == 2 else a)  # noqa: E731
+    Df = np.asarray(Df)
+    Df = Df[..., 0] if Df.ndim == 3 else Df
+    out = np.zeros(29)
+    lib().orc_reloc_energy(C.byref(c), _p(f(F)), _p(f(W)), _p(_f64(Df)),
+                           _p(_f64(np.asarray(T)[..., 0] if np.asarray(T).ndim == 3 else T)), int(order), _p(out))
     H = np.zeros((6, 6))
     iu = np.triu_indices(6)
     H[iu] = out[7:28]

@@ -716,6 +716,54 @@ int fuse_voxel(const Ctx& X, const Params<S>& P, const int dim[3], double s, int
 }
 
 // ---------------------------------------------------------------------------
+// Camera relocalisation objective (Sec. 5.2, eq. of E(T_{g,q})): with a
+// reference volume M_r = (F_r, W_r) and a query depth D_q fused at the
+// candidate pose T_q, F_q = surface_update(M_r, T_q, D_q) and
+// E(T_q) = sum_p (F_r(p) - F_q(p))^2.  A voxel the update leaves alone
+// contributes 0; an updated voxel has F_q = (W_r F_r + F_D) / (W_r + 1), so it
+// contributes ((F_r - F_D) / (W_r + 1))^2.  Voxels the reference never
+// observed (W_r = 0) carry no reference value and are left out.  The update's
+// decisions and F_D are those of fuse_voxel (decisions on real parts).
+// ---------------------------------------------------------------------------
+template <class S>
+bool reloc_voxel(const Ctx& X, const Params<S>& P, const int dim[3], double s, int64_t idx, double Fr, double Wr,
+                 const std::vector<S>& D, const M4<S>& T, S& contrib) {
+  if (!(Wr > 0.0)) return false;
+  int nx = dim[0], ny = dim[1];
+  int i = int(idx % nx), j = int((idx / nx) % ny), k = int(idx / (int64_t(nx) * ny));
+  V3<S> c(S((i + 0.5) * s - 0.5 * nx * s), S((j + 0.5) * s - 0.5 * ny * s), S((k + 0.5) * s - 0.5 * dim[2] * s));
+  V3<S> x = apply_inv(T, c);
+  if (!(re(x.z) > 0.0)) return false;
+  S ux = P.fx * x.x / x.z + P.cx;
+  S uy = P.fy * x.y / x.z + P.cy;
+  S L;
+  if (!depth_lookup(D, X.c.width, X.c.height, ux, uy, X.c.disc_delta, L)) return false;
+  S eta = L - x.z;
+  if (re(eta) < -re(P.mu)) return false;
+  S Fd = (re(eta) >= re(P.mu)) ? S(1.0) : eta / P.mu;
+  S d = (S(Fr) - Fd) / S(Wr + 1.0);
+  contrib = d * d;
+  return true;
+}
+
+// E over the whole volume, voxels in index order (the oracle's fixed order)
+template <class S>
+S reloc_energy(const Ctx& X, const Params<S>& P, const OrcConfig& c, const double* F, const double* W,
+               const std::vector<S>& D, const M4<S>& T, int64_t* cnt) {
+  int64_t n = int64_t(c.dim[0]) * c.dim[1] * c.dim[2];
+  S E(0.0);
+  int64_t m = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    S e;
+    if (!reloc_voxel(X, P, c.dim, c.voxel, v, F[v], W[v], D, T, e)) continue;
+    E = E + e;
+    m += 1;
+  }
+  if (cnt) *cnt = m;
+  return E;
+}
+
+// ---------------------------------------------------------------------------
 // A7. raycast (Sec. 4.1 "Ray casting", eq. surface_prediction)
 // ---------------------------------------------------------------------------
 // trilinear F at a world point; valid only if all 8 corners are observed (W>0)
@@ -1198,6 +1246,52 @@ void orc_icp_energy(const OrcConfig* c, int level, const double* Vc, const doubl
   for (int a = 0; a < 6; ++a) out[1 + a] = D.g[a];
   for (int k = 0; k < 21; ++k) out[7 + k] = D.H[k];
   out[28] = double(D.cnt);
+}
+
+// Relocalisation objective at the real pose T: reference volume F, W (real,
+// x-fastest), the query's filtered level-0 depth Df (real, H x W).  E, its
+// gradient and Hessian in the left increment exp(delta) T from 6 complex-step
+// and 21 bicomplex evaluations of the whole sum (order 0 / 1: E only / and the
+// gradient; the rest returned as 0).  out[29]: E, g[6], H (21, upper triangle
+// row-major, order phi then rho), number of contributing voxels.
+void orc_reloc_energy(const OrcConfig* c, const double* F, const double* W, const double* Df, const double* T,
+                      int order, double* out) {
+  const double h = 1e-20;
+  const int n = c->width * c->height;
+  OrcSeed s0{0, -1, -1, 0.0};
+  Ctx X0{*c, s0};
+  Params<double> P0 = make_params<double>(X0);
+  std::vector<double> D(Df, Df + n);
+  M4<double> T0 = load_pose<double>(T);
+  int64_t cnt = 0;
+  for (int k = 0; k < 29; ++k) out[k] = 0.0;
+  out[0] = reloc_energy(X0, P0, *c, F, W, D, T0, &cnt);
+  out[28] = double(cnt);
+  if (order >= 1) {
+    std::vector<cd> Dc(D.begin(), D.end());
+    for (int a = 0; a < 6; ++a) {
+      Ctx Xa{*c, OrcSeed{1, a, -1, h}};
+      Params<cd> Pa = make_params<cd>(Xa);
+      cd dx[6];
+      for (int q = 0; q < 6; ++q) dx[q] = Xa.par<cd>(0.0, q);
+      cd E = reloc_energy(Xa, Pa, *c, F, W, Dc, mul(se3_exp(dx), lift_pose<cd>(T0)), nullptr);
+      out[1 + a] = E.imag() / h;
+    }
+  }
+  if (order >= 2) {
+    std::vector<Bicomplex> Db(n);
+    for (int i = 0; i < n; ++i) Db[i] = Bicomplex(D[i]);
+    int k = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b, ++k) {
+        Ctx Xb{*c, OrcSeed{2, a, b, h}};
+        Params<Bicomplex> Pb = make_params<Bicomplex>(Xb);
+        Bicomplex dx[6];
+        for (int q = 0; q < 6; ++q) dx[q] = Xb.par<Bicomplex>(0.0, q);
+        Bicomplex E = reloc_energy(Xb, Pb, *c, F, W, Db, mul(se3_exp(dx), lift_pose<Bicomplex>(T0)), nullptr);
+        out[7 + k] = E.b.imag() / (h * h);
+      }
+  }
 }
 
 // Surface measurement of one frame: filtered depth per level and V/N maps.
