@@ -49,7 +49,9 @@ class OrcConfig(C.Structure):
                 ("iters", C.c_int32 * 3), ("dgate", C.c_double), ("agate_deg", C.c_double),
                 ("level_w", C.c_double * 3), ("disc_delta", C.c_double),
                 ("bilateral_radius", C.c_int32), ("sigma_px", C.c_double), ("sigma_m", C.c_double),
-                ("near_m", C.c_double), ("init", C.c_int32), ("update", C.c_int32), ("solver", C.c_int32)]
+                ("near_m", C.c_double), ("init", C.c_int32), ("update", C.c_int32), ("solver", C.c_int32),
+                ("pf_d_depth", C.c_double), ("pf_d_norm_deg", C.c_double), ("pf_d_dist", C.c_double),
+                ("pf_sigma", C.c_double), ("pf_c_stable", C.c_double), ("pf_capacity", C.c_int32)]
 
 
 class OrcSeed(C.Structure):
@@ -87,6 +89,10 @@ def lib():
         L.orc_icp_energy.argtypes = [cp, C.c_int, dp, dp, u8, dp, dp, dp, u8, dp, dp, C.c_int, C.c_int, dp]
         L.orc_reloc_energy.argtypes = [cp, dp, dp, dp, dp, C.c_int, dp]
         L.orc_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, dp, u8, dp, dp, i32, dp, u8]
+        L.orc_pf_frame_step.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, dp, i32, i64, dp, dp, dp, u8, dp, dp,
+                                        i32, dp, i64]
+        L.orc_pf_run_sequence.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, i64, dp, dp, dp, dp, i32, i64]
+        L.orc_pf_index_map.argtypes = [cp, dp, dp, C.c_int64, dp, C.c_int32, C.c_double, i64]
         L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
         L.orc_raycast_footprint.restype = C.c_int64
         L.orc_fuse_margin.argtypes = [cp, sp, dp, dp, i64, C.c_int64, dp]
@@ -104,7 +110,8 @@ def config(p: dict | None = None, **kw) -> OrcConfig:
     d = dict(width=160, height=120, fx=130.0, fy=130.0, cx=79.5, cy=59.5, dim=(128, 128, 128),
              voxel=0.02, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
              level_w=(1.0, 1.0, 1.0), disc_delta=0.1, bilateral_radius=3, sigma_px=4.5,
-             sigma_m=0.03, near_m=0.1, init=0, update=0, solver=0)
+             sigma_m=0.03, near_m=0.1, init=0, update=0, solver=0, pf_d_depth=0.03, pf_d_norm_deg=30.0,
+             pf_d_dist=0.03, pf_sigma=0.015, pf_c_stable=0.0, pf_capacity=0)
     if p is not None:
         cam = p["camera"]
         d.update(width=cam["width"], height=cam["height"], fx=cam["fx"], fy=cam["fy"],
@@ -112,6 +119,8 @@ def config(p: dict | None = None, **kw) -> OrcConfig:
                  trunc=p["trunc"], wcap=p["wcap"], iters=tuple(p["icp"]["iters"]),
                  dgate=p["icp"]["dgate"], agate_deg=p["icp"]["agate_deg"])
     d.update(kw)
+    if not d["pf_capacity"]:
+        d["pf_capacity"] = 8 * d["width"] * d["height"]
     c = OrcConfig()
     for k, v in d.items():
         if k in ("dim", "iters", "level_w"):
@@ -370,6 +379,83 @@ def frame_step(c: OrcConfig, s: OrcSeed, st: State, depth, depth_dot=None, touch
                          _p(st.T1), _p(st.T2), _p(st.lost, C.c_int32), _p(stats), _p(touch, C.c_uint8))
     st.frame += 1
     return stats
+
+
+def _surfel_arrays(cap: int, nc: int) -> dict:
+    return dict(v=np.zeros((cap, 3, nc)), n=np.zeros((cap, 3, nc)), r=np.zeros((cap, nc)), c=np.zeros((cap, nc)),
+                t=np.zeros(cap, np.int32))
+
+
+def pf_run_sequence(c: OrcConfig, s: OrcSeed, depths, T0, depth_dots=None) -> dict:
+    """Surfel pipeline (X-PointFusion front end, Sec. 4.2) over a sequence:
+    frame 0 at exp(seed) T0.  -> dict(poses (n,4,4,nc), stats (n,6) as
+    run_sequence's with surfel updates in column 3, pf (n,3) updated /
+    inserted / dropped, surfels dict(v (m,3,nc), n, r (m,nc), c, t (m,)))."""
+    _check_solver(c, s)
+    nc = ncomp(s)
+    depths = _f64(depths)
+    n = depths.shape[0]
+    poses = np.zeros((n, 4, 4, nc))
+    stats = np.zeros((n, 6))
+    pf = np.zeros((n, 3), np.int64)
+    S = _surfel_arrays(c.pf_capacity, nc)
+    cnt = np.zeros(1, np.int64)
+    lib().orc_pf_run_sequence(C.byref(c), C.byref(s), n, _p(depths), _p(_f64(depth_dots)), _p(_f64(T0)),
+                              _p(poses), _p(stats), _p(pf, C.c_int64), _p(S["v"]), _p(S["n"]), _p(S["r"]),
+                              _p(S["c"]), _p(S["t"], C.c_int32), _p(cnt, C.c_int64))
+    m = int(cnt[0])
+    return dict(poses=poses, stats=stats, pf=pf, surfels={k: v[:m] for k, v in S.items()})
+
+
+class PfState:
+    """State of one surfel frame step: surfels (capacity c.pf_capacity, the
+    first `count` in use), level-0 predicted maps, poses of the last two
+    frames T1, T2 (4, 4, nc; frame 0 is taken at T1), their lost flags, the
+    next frame's index."""
+
+    def __init__(self, c: OrcConfig, s: OrcSeed, T0):
+        nc = ncomp(s)
+        H, W = c.height, c.width
+        self.S = _surfel_arrays(c.pf_capacity, nc)
+        self.count = np.zeros(1, np.int64)
+        self.V = np.zeros((H, W, 3, nc))
+        self.N = np.zeros((H, W, 3, nc))
+        self.Z = np.zeros((H, W))
+        self.valid = np.zeros((H, W), np.uint8)
+        self.T1 = np.array(_f64(T0), copy=True)
+        self.T2 = self.T1.copy()
+        self.lost = np.zeros(2, np.int32)
+        self.frame = 0
+
+    def surfels(self) -> dict:
+        m = int(self.count[0])
+        return {k: v[:m] for k, v in self.S.items()}
+
+
+def pf_frame_step(c: OrcConfig, s: OrcSeed, st: PfState, depth, depth_dot=None):
+    """One surfel frame step from ``st`` (updated in place) -> (stats (6,),
+    pf counts (3,): updated, inserted, dropped)."""
+    _check_solver(c, s)
+    stats = np.zeros(6)
+    pf = np.zeros(3, np.int64)
+    S = st.S
+    lib().orc_pf_frame_step(C.byref(c), C.byref(s), int(st.frame), _p(_f64(depth)), _p(_f64(depth_dot)),
+                            _p(S["v"]), _p(S["n"]), _p(S["r"]), _p(S["c"]), _p(S["t"], C.c_int32),
+                            _p(st.count, C.c_int64), _p(st.V), _p(st.N), _p(st.Z), _p(st.valid, C.c_uint8),
+                            _p(st.T1), _p(st.T2), _p(st.lost, C.c_int32), _p(stats), _p(pf, C.c_int64))
+    st.frame += 1
+    return stats, pf
+
+
+def pf_index_map(c: OrcConfig, v, conf, T, sup: int = 4, c_min: float = -1e300) -> np.ndarray:
+    """Index map of surfels at real positions v (m, 3) with confidences conf
+    (m,) seen from the real pose T: (sup H, sup W) int64, -1 where empty."""
+    v = _f64(np.asarray(v).reshape(-1, 3))
+    conf = _f64(np.asarray(conf).reshape(-1))
+    out = np.zeros((sup * c.height, sup * c.width), np.int64)
+    lib().orc_pf_index_map(C.byref(c), _p(v), _p(conf), len(v), _p(_f64(T)), int(sup), float(c_min),
+                           _p(out, C.c_int64))
+    return out
 
 
 def raycast_footprint(c: OrcConfig, s: OrcSeed, F, W, T, touch=None):

@@ -264,6 +264,13 @@ struct OrcConfig {
   int32_t update;            // 0 exact exponential, 1 small-angle matrix (eq. icp_approx) + polar steps
   int32_t solver;            // 0 Gauss-Newton; Newton with the complex-step Hessian (real runs only):
                              // 1 correspondences held fixed per pass, 2 through the association
+  // surfel front end (X-PointFusion)
+  double pf_d_depth;         // candidate filter: depth difference along the viewing ray (m)
+  double pf_d_norm_deg;      // candidate filter: normal deviation (degrees)
+  double pf_d_dist;          // candidate filter: distance to the measured point (m)
+  double pf_sigma;           // Gaussian kernel of the one-to-many weights (m)
+  double pf_c_stable;        // confidence a surfel needs to enter the predicted model maps
+  int32_t pf_capacity;       // maximum number of surfels
 };
 struct OrcSeed {
   int32_t kind;  // 0 real, 1 complex (direction pa), 2 bicomplex (pa on i1, pb on i2)
@@ -1069,6 +1076,205 @@ void frame_step(const Ctx& X, const Params<S>& P, State<S>& St, const double* D,
   St.frame += 1;
 }
 
+// ---------------------------------------------------------------------------
+// F4. X-PointFusion front end (Sec. 4.2): surfel map, 4x4 super-resolution
+// index map, one-to-many Gaussian association, confidence-weighted update.
+// ---------------------------------------------------------------------------
+// Global model points: position v, normal n, radius r, confidence c (all in
+// the arithmetic S, so they carry the perturbation's parts) and time stamp t.
+template <class S> struct Surfels {
+  std::vector<V3<S>> v, n;
+  std::vector<S> r, c;
+  std::vector<int32_t> t;
+  size_t size() const { return v.size(); }
+};
+
+template <class S> struct PfState {
+  Surfels<S> map;
+  Maps<S> model[3];
+  M4<S> T, Tprev;
+  int frame = 0;
+  int lost1 = 0, lost2 = 0;
+};
+
+// Real part of a pose.
+template <class S> M4<double> re_pose(const M4<S>& T) {
+  M4<double> R;
+  for (int k = 0; k < 16; ++k) R.m[k] = re(T.m[k]);
+  return R;
+}
+template <class S> V3<double> re_vec(const V3<S>& a) { return V3<double>(re(a.x), re(a.y), re(a.z)); }
+
+// Index map at `sup` x the image resolution (sup = 4 for the association, 1
+// for the predicted model maps): every surfel with c >= c_min is projected
+// with the real pose, pixel u = pi(K x) with pixel centres at integers, and
+// lands in the sub-pixel (floor(sup (u_x + 1/2)), floor(sup (u_y + 1/2)));
+// each sub-pixel keeps the surfel nearest to the camera (camera z rounded to
+// FP32, ties to the lower index).  -1: empty.
+template <class S>
+std::vector<int64_t> pf_index_map(const Surfels<S>& M, const M4<S>& T, const Params<S>& P, int W, int H, int sup,
+                                  double c_min) {
+  const M4<double> Tr = re_pose(T);
+  const double fx = re(P.fx), fy = re(P.fy), cx = re(P.cx), cy = re(P.cy);
+  const int WS = W * sup, HS = H * sup;
+  std::vector<int64_t> idx(size_t(WS) * HS, -1);
+  std::vector<float> zb(size_t(WS) * HS, 0.0f);
+  for (size_t i = 0; i < M.size(); ++i) {
+    if (!(re(M.c[i]) >= c_min)) continue;
+    const V3<double> x = apply_inv(Tr, re_vec(M.v[i]));
+    if (!(x.z > 0.0)) continue;
+    const double ux = fx * x.x / x.z + cx, uy = fy * x.y / x.z + cy;
+    const double ax = std::floor(double(sup) * (ux + 0.5)), ay = std::floor(double(sup) * (uy + 0.5));
+    if (!(ax >= 0.0 && ay >= 0.0 && ax < double(WS) && ay < double(HS))) continue;
+    const size_t q = size_t(ay) * WS + size_t(ax);
+    const float zf = float(x.z);
+    if (idx[q] < 0 || zf < zb[q]) { idx[q] = int64_t(i); zb[q] = zf; }   // surfels in index order: ties keep the lower
+  }
+  return idx;
+}
+
+// Confidence of a measurement at pixel (x, y) (the PointFusion weight):
+// C = exp(-gamma^2 / 0.72), gamma the pixel's radial distance from the
+// principal point over the principal point's distance from the image corner
+// (0 at the centre, about 1 at the corners).
+template <class S> S pf_confidence(const Params<S>& P, int x, int y) {
+  const S dx = S(double(x)) - P.cx, dy = S(double(y)) - P.cy;
+  const S g2 = (dx * dx + dy * dy) / (P.cx * P.cx + P.cy * P.cy);
+  return exp(-g2 / S(0.72));
+}
+
+// Surfel radius of a measurement: sqrt(2) z / (f |n_z|), n_z the measured
+// normal's camera-z component, its magnitude bounded below by 0.25 (grazing
+// views), its sign taken from the real part.
+template <class S> S pf_radius(const Params<S>& P, const V3<S>& Vc, const V3<S>& Nc) {
+  S nz = re(Nc.z) < 0.0 ? -Nc.z : Nc.z;
+  if (re(nz) < 0.25) nz = S(0.25);
+  return S(std::sqrt(2.0)) * Vc.z / (P.fx * nz);
+}
+
+struct PfCounts { int64_t updated = 0, inserted = 0, dropped = 0; };
+
+// Data association and surface update of frame k at pose T: for each valid
+// measured pixel (row-major), the qualified candidates among the surfels of
+// its 4x4 block of the index map (rendered before the update) are updated
+// with weight w C(u); a pixel with no qualified candidate becomes a new
+// surfel, appended in pixel order (up to the capacity).
+template <class S>
+PfCounts pf_update(const Ctx& X, const Params<S>& P, Surfels<S>& M, const Maps<S>& meas, const M4<S>& T, int k) {
+  PfCounts cnt;
+  const int W = X.c.width, H = X.c.height, sup = 4;
+  const std::vector<int64_t> idx = pf_index_map(M, T, P, W, H, sup, -1e300);
+  const M4<double> Tr = re_pose(T);
+  const double cos_n = std::cos(X.c.pf_d_norm_deg * M_PI / 180.0);
+  const double two_s2 = 2.0 * X.c.pf_sigma * X.c.pf_sigma;
+  std::vector<int> fresh;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const int u = y * W + x;
+      if (!meas.valid[u]) continue;
+      const V3<S> Vg = apply(T, meas.V[u]);
+      const V3<S> Ng = rotate(T, meas.N[u]);
+      const V3<double> vg = re_vec(Vg), ng = re_vec(Ng);
+      const double zu = re(meas.V[u].z);
+      const S Cu = pf_confidence(P, x, y);
+      bool assoc = false;
+      for (int sy = 0; sy < sup; ++sy)
+        for (int sx = 0; sx < sup; ++sx) {
+          const int64_t i = idx[size_t(y * sup + sy) * (W * sup) + size_t(x * sup + sx)];
+          if (i < 0) continue;
+          // filters, on real parts
+          const V3<double> vi = re_vec(M.v[i]), ni = re_vec(M.n[i]);
+          const double zi = apply_inv(Tr, vi).z;
+          if (!(std::fabs(zi - zu) <= X.c.pf_d_depth)) continue;
+          const double nn = std::sqrt(dot(ni, ni));
+          if (!(nn > 0.0) || !(dot(ni, ng) >= cos_n * nn)) continue;
+          const V3<double> dv = vi - vg;
+          if (!(std::sqrt(dot(dv, dv)) <= X.c.pf_d_dist)) continue;
+          // one-to-many update with the Gaussian weight of the distance
+          const V3<S> d = M.v[i] - Vg;
+          const S w = exp(-dot(d, d) / S(two_s2));
+          const S a = w * Cu;
+          const S den = M.c[i] + a;
+          M.v[i] = (S(1.0) / den) * (M.c[i] * M.v[i] + a * Vg);
+          M.n[i] = (S(1.0) / den) * (M.c[i] * M.n[i] + a * Ng);
+          M.r[i] = (M.c[i] * M.r[i] + a * pf_radius(P, meas.V[u], meas.N[u])) / den;
+          M.c[i] = den;
+          M.t[i] = k;
+          cnt.updated += 1;
+          assoc = true;
+        }
+      if (!assoc) fresh.push_back(u);
+    }
+  for (int u : fresh) {
+    if (M.size() >= size_t(std::max(X.c.pf_capacity, 0))) { cnt.dropped += 1; continue; }
+    const int x = u % W, y = u / W;
+    M.v.push_back(apply(T, meas.V[u]));
+    M.n.push_back(rotate(T, meas.N[u]));
+    M.r.push_back(pf_radius(P, meas.V[u], meas.N[u]));
+    M.c.push_back(pf_confidence(P, x, y));
+    M.t.push_back(k);
+    cnt.inserted += 1;
+  }
+  return cnt;
+}
+
+// Predicted model maps at pose T for the next frame's ICP: the nearest
+// surfel per pixel among those with c >= c_stable (index map at 1x): V = v,
+// N = n / |n|, Z = its camera z (real); levels 1-2 by subsampling.
+template <class S> Maps<S> pf_predict(const Ctx& X, const Params<S>& P, const Surfels<S>& M, const M4<S>& T) {
+  const int W = X.c.width, H = X.c.height;
+  const std::vector<int64_t> idx = pf_index_map(M, T, P, W, H, 1, X.c.pf_c_stable);
+  const M4<double> Tr = re_pose(T);
+  Maps<S> O;
+  O.W = W; O.H = H;
+  const int n = W * H;
+  O.V.assign(n, V3<S>()); O.N.assign(n, V3<S>()); O.valid.assign(n, 0); O.vvalid.assign(n, 0); O.Z.assign(n, 0.0);
+  for (int q = 0; q < n; ++q) {
+    const int64_t i = idx[q];
+    if (i < 0) continue;
+    const S nn = sqrt(dot(M.n[i], M.n[i]));
+    if (!(re(nn) > 0.0)) continue;
+    O.V[q] = M.v[i];
+    O.N[q] = (S(1.0) / nn) * M.n[i];
+    O.Z[q] = apply_inv(Tr, re_vec(M.v[i])).z;
+    O.valid[q] = 1;
+    O.vvalid[q] = 1;
+  }
+  return O;
+}
+
+// One frame of the surfel pipeline: measure, track against the predicted
+// maps (as the TSDF path: Sec. 4.2 takes pose estimation from KF), update
+// the map (skipped on a lost frame), predict the maps at the new pose.
+template <class S>
+void pf_frame_step(const Ctx& X, const Params<S>& P, PfState<S>& St, const double* D, const double* Ddot,
+                   FrameStats& fs, PfCounts& pc) {
+  Measured<S> meas = measure(X, P, D, Ddot);
+  fs = FrameStats{0, 0, 0.0, 0, 0, 0};
+  pc = PfCounts{};
+  if (St.frame > 0) {
+    M4<S> Tinit = St.T;
+    if (X.c.init == 1 && St.frame > 1) Tinit = const_velocity(St.T, St.Tprev, !St.lost1 && !St.lost2);
+    Normal<S> last;
+    int32_t lost = 0;
+    M4<S> T = track(X, P, meas, St.model, St.T, Tinit, lost, &last, &fs.cnt_sum);
+    fs.lost = lost; fs.cnt_last = int32_t(last.cnt); fs.r2_last = last.r2;
+    St.Tprev = St.T;
+    St.T = T;
+  }
+  St.lost2 = St.lost1;
+  St.lost1 = fs.lost;
+  if (!fs.lost) {
+    pc = pf_update(X, P, St.map, meas.M[0], St.T, St.frame);
+    fs.n_fused = pc.updated;
+  }
+  St.model[0] = pf_predict(X, P, St.map, St.T);
+  for (uint8_t v : St.model[0].valid) fs.n_hits += v;
+  St.model[1] = subsample(St.model[0], 1);
+  St.model[2] = subsample(St.model[0], 2);
+  St.frame += 1;
+}
+
 template <class S> M4<S> load_pose(const double* p) {
   M4<S> T;
   for (int i = 0; i < 16; ++i) T.m[i] = get<S>(p + i * NC<S>::n);
@@ -1515,6 +1721,130 @@ void orc_frame_step(const OrcConfig* c, const OrcSeed* seed, int32_t frame, cons
       stats_out[3] = double(fs.n_fused); stats_out[4] = double(fs.n_hits); stats_out[5] = double(fs.cnt_sum);
     }
   });
+}
+
+// One frame of the surfel pipeline (X-PointFusion front end) from a loaded
+// state, written back.  Surfels (capacity c->pf_capacity, *count in use):
+// sv, sn [cap][3][nc], sr, sc [cap][nc], st [cap]; model maps of level 0 as
+// in orc_frame_step; T1, T2 the poses of the last two frames; lost12 their
+// lost flags.  stats_out (6, optional) as orc_frame_step's, with the number
+// of surfel updates in place of fused voxels; pf_out (3, optional): updated,
+// inserted, dropped (capacity).
+void orc_pf_frame_step(const OrcConfig* c, const OrcSeed* seed, int32_t frame, const double* depth,
+                       const double* depth_dot, double* sv, double* sn, double* sr, double* sc, int32_t* st,
+                       int64_t* count, double* Vm, double* Nm, double* Zm, uint8_t* validm, double* T1, double* T2,
+                       int32_t* lost12, double* stats_out, int64_t* pf_out) {
+  Ctx X{*c, *seed};
+  ORC_DISPATCH(seed, {
+    const int nc = NC<S>::n;
+    Params<S> P = make_params<S>(X);
+    PfState<S> St;
+    const int64_t n = *count;
+    St.map.v.resize(n); St.map.n.resize(n); St.map.r.resize(n); St.map.c.resize(n); St.map.t.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      St.map.v[i] = V3<S>(get<S>(sv + (i * 3 + 0) * nc), get<S>(sv + (i * 3 + 1) * nc), get<S>(sv + (i * 3 + 2) * nc));
+      St.map.n[i] = V3<S>(get<S>(sn + (i * 3 + 0) * nc), get<S>(sn + (i * 3 + 1) * nc), get<S>(sn + (i * 3 + 2) * nc));
+      St.map.r[i] = get<S>(sr + i * nc);
+      St.map.c[i] = get<S>(sc + i * nc);
+      St.map.t[i] = st[i];
+    }
+    St.model[0] = maps_in<S>(c->width, c->height, Vm, Nm, Zm, validm);
+    St.model[1] = subsample(St.model[0], 1);
+    St.model[2] = subsample(St.model[0], 2);
+    St.T = load_pose<S>(T1);
+    St.Tprev = load_pose<S>(T2);
+    St.frame = frame;
+    St.lost1 = lost12[0];
+    St.lost2 = lost12[1];
+    FrameStats fs;
+    PfCounts pc;
+    pf_frame_step(X, P, St, depth, depth_dot, fs, pc);
+    const int64_t m = int64_t(St.map.size());
+    for (int64_t i = 0; i < m; ++i) {
+      put(sv + (i * 3 + 0) * nc, St.map.v[i].x); put(sv + (i * 3 + 1) * nc, St.map.v[i].y);
+      put(sv + (i * 3 + 2) * nc, St.map.v[i].z);
+      put(sn + (i * 3 + 0) * nc, St.map.n[i].x); put(sn + (i * 3 + 1) * nc, St.map.n[i].y);
+      put(sn + (i * 3 + 2) * nc, St.map.n[i].z);
+      put(sr + i * nc, St.map.r[i]);
+      put(sc + i * nc, St.map.c[i]);
+      st[i] = St.map.t[i];
+    }
+    *count = m;
+    maps_out(St.model[0], Vm, Nm, Zm, validm);
+    store_pose(T1, St.T);
+    store_pose(T2, St.Tprev);
+    lost12[0] = St.lost1;
+    lost12[1] = St.lost2;
+    if (stats_out) {
+      stats_out[0] = fs.lost; stats_out[1] = fs.cnt_last; stats_out[2] = fs.r2_last;
+      stats_out[3] = double(fs.n_fused); stats_out[4] = double(fs.n_hits); stats_out[5] = double(fs.cnt_sum);
+    }
+    if (pf_out) { pf_out[0] = pc.updated; pf_out[1] = pc.inserted; pf_out[2] = pc.dropped; }
+  });
+}
+
+// Whole surfel sequence: frame 0 at exp(seed) T0 (real 4x4), then
+// track / update / predict per frame.  depths (and depth_dots or NULL):
+// n_frames x H x W.  poses_out: n_frames x 16 x nc; stats_out (optional):
+// n_frames x 6 as orc_pf_frame_step's; pf_out (optional): n_frames x 3.
+// The final surfels are written to sv, sn, sr, sc, st (capacity
+// c->pf_capacity) with their number in *count.
+void orc_pf_run_sequence(const OrcConfig* c, const OrcSeed* seed, int32_t n_frames, const double* depths,
+                         const double* depth_dots, const double* T0, double* poses_out, double* stats_out,
+                         int64_t* pf_out, double* sv, double* sn, double* sr, double* sc, int32_t* st, int64_t* count) {
+  Ctx X{*c, *seed};
+  ORC_DISPATCH(seed, {
+    const int nc = NC<S>::n;
+    Params<S> P = make_params<S>(X);
+    PfState<S> St;
+    St.T = seeded_initial_pose<S>(X, T0);
+    St.Tprev = St.T;
+    const size_t npx = size_t(c->width) * c->height;
+    for (int f = 0; f < n_frames; ++f) {
+      FrameStats fs;
+      PfCounts pc;
+      pf_frame_step(X, P, St, depths + f * npx, depth_dots ? depth_dots + f * npx : nullptr, fs, pc);
+      store_pose(poses_out + size_t(f) * 16 * nc, St.T);
+      if (stats_out) {
+        double* o = stats_out + size_t(f) * 6;
+        o[0] = fs.lost; o[1] = fs.cnt_last; o[2] = fs.r2_last; o[3] = double(fs.n_fused);
+        o[4] = double(fs.n_hits); o[5] = double(fs.cnt_sum);
+      }
+      if (pf_out) {
+        int64_t* o = pf_out + size_t(f) * 3;
+        o[0] = pc.updated; o[1] = pc.inserted; o[2] = pc.dropped;
+      }
+    }
+    const int64_t m = int64_t(St.map.size());
+    for (int64_t i = 0; i < m; ++i) {
+      put(sv + (i * 3 + 0) * nc, St.map.v[i].x); put(sv + (i * 3 + 1) * nc, St.map.v[i].y);
+      put(sv + (i * 3 + 2) * nc, St.map.v[i].z);
+      put(sn + (i * 3 + 0) * nc, St.map.n[i].x); put(sn + (i * 3 + 1) * nc, St.map.n[i].y);
+      put(sn + (i * 3 + 2) * nc, St.map.n[i].z);
+      put(sr + i * nc, St.map.r[i]);
+      put(sc + i * nc, St.map.c[i]);
+      st[i] = St.map.t[i];
+    }
+    *count = m;
+  });
+}
+
+// The index map of the surfels (real positions sv [count][3][nc], confidences
+// sc [count][nc]) at the real pose T, `sup` x the image resolution, over the
+// surfels with c >= c_min: idx_out [sup H][sup W], -1 where empty.
+void orc_pf_index_map(const OrcConfig* c, const double* sv, const double* sc, int64_t count, const double* T,
+                      int32_t sup, double c_min, int64_t* idx_out) {
+  OrcSeed s0{0, -1, -1, 0.0};
+  Ctx X{*c, s0};
+  Params<double> P = make_params<double>(X);
+  Surfels<double> M;
+  M.v.resize(count); M.c.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    M.v[i] = V3<double>(sv[i * 3 + 0], sv[i * 3 + 1], sv[i * 3 + 2]);
+    M.c[i] = sc[i];
+  }
+  std::vector<int64_t> idx = pf_index_map(M, load_pose<double>(T), P, c->width, c->height, sup, c_min);
+  std::memcpy(idx_out, idx.data(), idx.size() * sizeof(int64_t));
 }
 
 // Footprint of the raycast of (F, W) at pose T (one byte per voxel, OR-ed):
