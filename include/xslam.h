@@ -124,6 +124,26 @@ typedef struct {
                             counts those passes).  Newton needs a perturbation
                             of no directions (XSLAM_ERR_ARG otherwise)         */
 } xslam_icp;
+/* The global model (Sec. 4): the TSDF volume of KinectFusion (Sec. 4.1), or
+ * the surfel map of the PointFusion front end (Sec. 4.2: surfels with
+ * position, normal, radius, confidence and time stamp; data association
+ * through an index map rendered at 4 x 4 the image resolution, every surfel
+ * of a pixel's block within the three gates updated with a Gaussian weight
+ * of its distance times the measurement confidence exp(-gamma^2 / 0.72),
+ * gamma the pixel's radial distance from the principal point over that of
+ * the image corner; unassociated pixels appended as new surfels in pixel
+ * order).  Tracking is the same ICP against the model maps, which the surfel
+ * map renders as the nearest stable surfel per pixel. */
+enum xslam_map { XSLAM_MAP_TSDF = 0, XSLAM_MAP_SURFEL = 1 };
+typedef struct {
+  double d_depth;        /* gate: |camera z of the surfel - measured z| (m)       */
+  double d_norm_deg;     /* gate: angle between surfel and measured normal        */
+  double d_dist;         /* gate: distance to the measured point (m)              */
+  double sigma;          /* Gaussian weight exp(-d^2 / (2 sigma^2)) (m)           */
+  double c_stable;       /* confidence a surfel needs to enter the model maps     */
+  int32_t capacity;      /* maximum number of surfels (> 0); insertions past it
+                            are dropped and counted (counter slot 36)             */
+} xslam_surfel;
 typedef struct {
   int32_t prec;          /* enum xslam_prec                                       */
   xslam_camera cam;      /* width, height multiples of 4                           */
@@ -133,6 +153,8 @@ typedef struct {
   double bilateral_sigma_px, bilateral_sigma_m;
   double near_m;                   /* raycast near plane                           */
   int32_t max_frames;              /* capacity of the pose history                 */
+  int32_t map;                     /* enum xslam_map: the global model              */
+  xslam_surfel surfel;             /* surfel front end (map = XSLAM_MAP_SURFEL)     */
 } xslam_config;
 
 /* get/set fields */
@@ -156,9 +178,20 @@ enum xslam_field {
                             update norm |xi| fell below 1e-6 (0: none),
                             33 initialiser used (1 network, 0 constant velocity),
                             34 Newton passes that took the Gauss-Newton step,
-                            35..39 reserved (0); set writes rows 0..n-1 (resume)            */
+                            surfel map: 1 surfel updates, 2 valid model pixels,
+                            35 surfels inserted, 36 insertions dropped at the
+                            capacity, 37 surfels in use;
+                            38..39 reserved (0); set writes rows 0..n-1 (resume)            */
   XSLAM_F_PREV_POSE = 13,/* pose of the previous frame (ICP projection reference): [NC][16]  */
-  XSLAM_F_FRAME = 14     /* frame counter: int32                                             */
+  XSLAM_F_FRAME = 14,    /* frame counter: int32                                             */
+  /* surfel map (map = XSLAM_MAP_SURFEL; XSLAM_ERR_ARG otherwise), capacity C entries;
+   * get copies all C, set writes the leading entries the buffer holds */
+  XSLAM_F_SURF_V = 15,   /* positions (world): [3][NC][C] in the context precision          */
+  XSLAM_F_SURF_N = 16,   /* normals: [3][NC][C]                                              */
+  XSLAM_F_SURF_R = 17,   /* radii: [NC][C]                                                   */
+  XSLAM_F_SURF_C = 18,   /* confidences: [NC][C]                                             */
+  XSLAM_F_SURF_T = 19,   /* time stamps (frame index of the last update): int32 [C]          */
+  XSLAM_F_SURF_COUNT = 20/* surfels in use: int32                                            */
 };
 
 /* number of components NC = 1 + D + P of a perturbation */
@@ -225,6 +258,24 @@ int xslam_icp_pass(xslam_ctx ctx, int32_t level, double* sums_out);
  * directions (XSLAM_ERR_UNSUPPORTED otherwise). */
 int xslam_icp_energy(xslam_ctx ctx, int32_t level, int32_t through, double* out);
 
+/* Camera relocalisation objective (Sec. 5.2): E(T_q) = sum over voxels of
+ * (F_r - F_q)^2, where F_r is the context's TSDF (the reference volume M_r,
+ * built by earlier frames or set with xslam_set) and F_q the same volume
+ * after the last measured frame (the query depth, xslam_measure) is fused
+ * into it at the candidate pose `pose` (host, FP64 row-major 4x4,
+ * camera-to-world).  Only voxels the reference has observed (W_r > 0) and
+ * that fusion would update contribute, each ((F_r - F_D) / (W_r + 1))^2 with
+ * fusion's decisions and F_D; the volume, the current pose and the frame
+ * state are left unchanged.  out (host, 29 doubles): E, its gradient g[6] and
+ * Hessian H (21, upper triangle row-major) in the left increment
+ * exp(delta) T_q, order phi_x phi_y phi_z rho_x rho_y rho_z (six hyper-dual
+ * directions and their 21 pairs: the six complex-step and 21 bicomplex
+ * evaluations of the surface update in one pass), then the number of
+ * contributing voxels.  Synchronises.  Only for contexts with no directions
+ * (XSLAM_ERR_UNSUPPORTED otherwise); XSLAM_ERR_STATE before any measured
+ * frame; XSLAM_ERR_ARG for NULL or non-finite arguments. */
+int xslam_reloc_energy(xslam_ctx ctx, const double pose[16], double* out);
+
 /* Translational RMSE of the pose history against gt_poses (host, n x 16
  * FP64), no alignment; out (host): NC doubles (value and its parts).  FP64. */
 int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out);
@@ -234,7 +285,8 @@ int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out
  * reads: TSDF, WEIGHT, VMAP, NMAP, ZMAP, MVALID, POSE, PREV_POSE, POSES,
  * COUNTERS and FRAME, written back into a context created with the same
  * configuration and perturbation (brick flags and the level 1-2 model maps
- * are rebuilt from them). */
+ * are rebuilt from them); with the surfel map, the SURF_* fields and
+ * SURF_COUNT take the place of TSDF and WEIGHT. */
 int xslam_get(xslam_ctx ctx, int32_t field, void* dst, size_t bytes);
 int xslam_set(xslam_ctx ctx, int32_t field, const void* src, size_t bytes);
 

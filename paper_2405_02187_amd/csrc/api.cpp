@@ -61,6 +61,14 @@ static int validate(const xslam_config* c, const xslam_perturbation* p, int* D, 
   if (c->bilateral_radius > 0 && !(c->bilateral_sigma_px > 0 && c->bilateral_sigma_m > 0)) return bad("bilateral sigmas");
   if (!(c->bilateral_sigma_m > 0)) return bad("bilateral_sigma_m gates the pyramid and must be > 0");
   if (c->max_frames < 1) return bad("max_frames");
+  if (c->map != XSLAM_MAP_TSDF && c->map != XSLAM_MAP_SURFEL) return bad("map must be 0 (TSDF) or 1 (surfels)");
+  if (c->map == XSLAM_MAP_SURFEL) {
+    const xslam_surfel& sf = c->surfel;
+    if (sf.capacity < 1 || sf.capacity > (1 << 28)) return bad("surfel capacity must be 1..2^28");
+    if (!(sf.d_depth > 0 && sf.d_dist > 0 && sf.sigma > 0) || !(sf.d_norm_deg >= 0 && sf.d_norm_deg <= 180) ||
+        !std::isfinite(sf.c_stable))
+      return bad("surfel gates and sigma");
+  }
   int nd = p ? p->n_dirs : 0, np = p ? p->n_pairs : 0;
   if (nd < 0 || nd > kMaxDirsApi) return bad("n_dirs must be 0..16");
   if (nd > 0 && !p->dirs) return bad("dirs is NULL");
@@ -211,6 +219,14 @@ int xslam_icp_energy(xslam_ctx ctx, int32_t level, int32_t through, double* out)
   XS_CTX_CHECK(ctx);
   if (!out || through < 0 || through > 1) return XSLAM_ERR_ARG;
   return ctx->eng->icp_energy(level, through, out);
+}
+
+int xslam_reloc_energy(xslam_ctx ctx, const double pose[16], double* out) {
+  XS_CTX_CHECK(ctx);
+  if (!pose || !out) return XSLAM_ERR_ARG;
+  for (int k = 0; k < 16; ++k)
+    if (!std::isfinite(pose[k])) return XSLAM_ERR_ARG;
+  return ctx->eng->reloc_energy(pose, out);
 }
 
 int xslam_traj_err(xslam_ctx ctx, const double* gt_poses, int32_t n, double* out) {

@@ -31,6 +31,7 @@ struct EngineBase {
   virtual int step(const void* depth, const void* ddot) = 0;
   virtual int icp_pass(int level, double* out) = 0;
   virtual int icp_energy(int level, int through, double* out) = 0;
+  virtual int reloc_energy(const double* pose, double* out) = 0;
   virtual int traj_err(const double* gt, int n, double* out) = 0;
   virtual int get(int field, void* dst, size_t bytes) = 0;
   virtual int set(int field, const void* src, size_t bytes) = 0;

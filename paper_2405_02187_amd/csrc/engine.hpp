@@ -10,6 +10,8 @@
 #include "ctx.hpp"
 #include "kernels.hpp"
 #include "newton.hpp"
+#include "reloc.hpp"
+#include "surfel.hpp"
 
 namespace xs {
 
@@ -56,7 +58,7 @@ struct Engine : EngineBase {
   T* Vm[3]; T* Nm[3]; T* Zm[3]; uint8_t* mvalid[3];
   double* partials = nullptr; int* lost = nullptr;
   MPose<D, Q>* Pcur; MPose<D, Q>* Pprev; MPose<D, Q>* Pprev2; MPose<D, Q>* Pinit; MPose<D, Q>* hist;
-  KPose<T, D, Q>* Kcur; KPose<T, D, Q>* Kprev;
+  KPose<T, D, Q>* Kcur; KPose<T, D, Q>* Kprev; KPose<T, D, Q>* Kq;
   int32_t* counters = nullptr;
   double* sums = nullptr; double* traj = nullptr; double* gt = nullptr;
   T* stage = nullptr;
@@ -67,6 +69,12 @@ struct Engine : EngineBase {
   double* sums_net = nullptr; double* sums_cv = nullptr;
   xslam_cnn cnn = nullptr;
   T* tzmax = nullptr; T* czmax = nullptr; int* dframe = nullptr;
+  // surfel map (map = XSLAM_MAP_SURFEL)
+  bool surf = false;
+  SurfMap<T> sm{};
+  SurfCfg scfg{};
+  unsigned long long* smap4 = nullptr; unsigned long long* smap1 = nullptr;
+  uint8_t* sfresh = nullptr; int* sbcnt = nullptr; int* sboff = nullptr; int* supd = nullptr;
   int ntiles = 0;
   hipGraph_t graph = nullptr; hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
@@ -110,7 +118,7 @@ struct Engine : EngineBase {
     int* lost = cv.take<int>(1);
     MPose<D, Q>* P = cv.take<MPose<D, Q>>(4);
     MPose<D, Q>* hist = cv.take<MPose<D, Q>>(c.max_frames);
-    KPose<T, D, Q>* K = cv.take<KPose<T, D, Q>>(2);
+    KPose<T, D, Q>* K = cv.take<KPose<T, D, Q>>(3);
     int32_t* counters = cv.take<int32_t>(size_t(kCounters) * c.max_frames);
     double* sums = cv.take<double>(NS);
     double* traj = cv.take<double>(NC);
@@ -136,6 +144,28 @@ struct Engine : EngineBase {
     double* sums_net = cv.take<double>(NS);
     double* sums_cv = cv.take<double>(NS);
     int* dframe = cv.take<int>(1);
+    // surfel map
+    const bool sf = c.map == XSLAM_MAP_SURFEL;
+    const size_t cap = sf ? size_t(c.surfel.capacity) : 0;
+    const int nsb = sf ? int((n0 + kSurfScanBlock - 1) / kSurfScanBlock) : 0;
+    const int nub = sf ? int(((c.cam.width + 15) / 16) * ((c.cam.height + 15) / 16)) : 0;
+    T* sv = cv.take<T>(3 * NC * cap);
+    T* sn = cv.take<T>(3 * NC * cap);
+    T* sr = cv.take<T>(NC * cap);
+    T* sc = cv.take<T>(NC * cap);
+    int32_t* st = cv.take<int32_t>(cap);
+    int* scount = cv.take<int>(sf ? 2 : 0);
+    unsigned long long* m4 = cv.take<unsigned long long>(sf ? 16 * n0 : 0);
+    unsigned long long* m1 = cv.take<unsigned long long>(sf ? n0 : 0);
+    uint8_t* fr = cv.take<uint8_t>(sf ? n0 : 0);
+    int* bcn = cv.take<int>(nsb);
+    int* bof = cv.take<int>(nsb);
+    int* bup = cv.take<int>(nub);
+    if (e) {
+      e->surf = sf;
+      e->sm = SurfMap<T>{sv, sn, sr, sc, st, scount, sf ? scount + 1 : nullptr};
+      e->smap4 = m4; e->smap1 = m1; e->sfresh = fr; e->sbcnt = bcn; e->sboff = bof; e->supd = bup;
+    }
     if (e) {
       e->blist = blist; e->bcount = bcount; e->bflags = bflags; e->tzmax = tzmax; e->czmax = czmax;
       e->dframe = dframe;
@@ -150,7 +180,7 @@ struct Engine : EngineBase {
       e->partials = partials; e->lost = lost;
       for (int l = 0; l < 3; ++l) e->Dhi[l] = dhi[l];
       e->Pcur = P; e->Pprev = P + 1; e->Pprev2 = P + 2; e->Pinit = P + 3; e->hist = hist;
-      e->Kcur = K; e->Kprev = K + 1;
+      e->Kcur = K; e->Kprev = K + 1; e->Kq = K + 2;
       e->counters = counters; e->sums = sums; e->traj = traj; e->gt = gt; e->stage = stage;
     }
     return cv.off;
@@ -259,6 +289,15 @@ struct Engine : EngineBase {
     if ((rc = fill<int>(bcount, 0, 1))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
     if ((rc = fill<int32_t>(counters, 0, int64_t(kCounters) * c.max_frames))) return rc;
+    if (surf) {
+      scfg.d_depth = c.surfel.d_depth;
+      scfg.cos_norm = std::cos(c.surfel.d_norm_deg * M_PI / 180.0);
+      scfg.d_dist = c.surfel.d_dist;
+      scfg.two_s2 = 2.0 * c.surfel.sigma * c.surfel.sigma;
+      scfg.c_stable = c.surfel.c_stable;
+      scfg.cap = c.surfel.capacity;
+      if ((rc = fill<int>(sm.count, 0, 2))) return rc;
+    }
     // initial pose exp(xi_seed) T0, xi_seed = h on the pose directions
     JD xi[6];
     for (int a = 0; a < 6; ++a) xi[a] = pj(0.0, XSLAM_P_PHI_X + a);
@@ -534,9 +573,10 @@ struct Engine : EngineBase {
     // raycast tile
     static const int tiles[][2] = {{16, 16}, {32, 8}, {8, 32}, {64, 4}, {16, 8}, {32, 4}, {64, 2},
                                    {8, 8},   {16, 4}, {32, 2}, {64, 1}};
-    double best_ray = 1e30;
+    double best_ray = surf ? 0.0 : 1e30;
     int bbx = ray_bx, bby = ray_by;
     for (auto& t : tiles) {
+      if (surf) break;                 // the surfel map renders no raycast
       ray_bx = t[0];
       ray_by = t[1];
       double ms = 0;
@@ -545,7 +585,7 @@ struct Engine : EngineBase {
     }
     ray_bx = bbx;
     ray_by = bby;
-    if (!rc) rc = run_raycast();       // the model maps again with the chosen tile (same values)
+    if (!rc && !surf) rc = run_raycast();   // the model maps again with the chosen tile (same values)
     // ICP grid per level (sums only): the candidates are close, so each is
     // timed in 3 interleaved rounds and its best round counts, and a smaller
     // grid (more pixels per thread) replaces a larger one only when it is 5%
@@ -637,6 +677,67 @@ struct Engine : EngineBase {
     });
   }
 
+  // surfel map: index map at 4x, association and update, insertion in pixel
+  // order (predicated on the device lost flag)
+  int run_surf_update() {
+    int rc;
+    const int cap = scfg.cap;
+    const int64_t n0 = int64_t(npx[0]);
+    if ((rc = fill<unsigned long long>(smap4, kSurfEmpty, 16 * n0))) return rc;
+    if ((rc = launch(4, "surf_project4", [&] {
+           XS_LAUNCH((k_surf_project<T, D, Q>), dim3((cap + 255) / 256), dim3(256), 0, C->stream, kp, Kcur, sm, cap,
+                     4, -1e300, smap4);
+         })))
+      return rc;
+    const dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
+    if ((rc = launch(2, "surf_assoc", [&] {
+           XS_LAUNCH((k_surf_assoc<T, D, Q>), g, b, 0, C->stream, kp, Kcur, Vl[0], Nl[0], valid[0], sm, scfg, smap4,
+                     sfresh, lost, dframe, supd);
+         })))
+      return rc;
+    const int nsb = int((n0 + kSurfScanBlock - 1) / kSurfScanBlock);
+    if ((rc = launch(4, "surf_count", [&] {
+           XS_LAUNCH(k_surf_count<T>, dim3(nsb), dim3(kSurfScanBlock), 0, C->stream, sfresh, int(n0), sbcnt);
+         })))
+      return rc;
+    if ((rc = launch(4, "surf_scan", [&] {
+           XS_LAUNCH(k_surf_scan<T>, dim3(1), dim3(1024), 0, C->stream, sbcnt, nsb, sboff, supd, int(g.x * g.y),
+                     sm.count, sm.base, cap, counters, dframe, C->cfg.max_frames);
+         })))
+      return rc;
+    return launch(4, "surf_insert", [&] {
+      XS_LAUNCH((k_surf_insert<T, D, Q>), dim3(nsb), dim3(kSurfScanBlock), 0, C->stream, kp, Kcur, Vl[0], Nl[0],
+                sfresh, sboff, sm, cap, dframe);
+    });
+  }
+
+  // surfel map: the model maps (levels 0-2) from the nearest stable surfel
+  // per pixel at the current pose; end_frame as in run_raycast
+  int run_surf_predict(bool end_frame = false) {
+    int rc;
+    const int cap = scfg.cap;
+    if ((rc = fill<unsigned long long>(smap1, kSurfEmpty, int64_t(npx[0])))) return rc;
+    if ((rc = launch(3, "surf_project1", [&] {
+           XS_LAUNCH((k_surf_project<T, D, Q>), dim3((cap + 255) / 256), dim3(256), 0, C->stream, kp, Kcur, sm, cap,
+                     1, scfg.c_stable, smap1);
+         })))
+      return rc;
+    MapsOut<T, D, Q> o;
+    for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
+    const dim3 b(16, 16), g((W[0] + 15) / 16, (H[0] + 15) / 16);
+    if ((rc = launch(6, "surf_maps", [&] {
+           XS_LAUNCH((k_surf_maps<T, D, Q>), g, b, 0, C->stream, kp, Kcur, sm, cap, smap1, o, rhits);
+         })))
+      return rc;
+    const int nrb = int(g.x * g.y);
+    rc = launch(4, "sum_counts", [&] {
+      XS_LAUNCH(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, nullptr, 0, counters, dframe,
+                C->cfg.max_frames, 2, 31, nullptr, 0, end_frame ? dframe : nullptr);
+    });
+    if (!rc) have_model = true;
+    return rc;
+  }
+
   int all_brick_flags() {
     const int g = std::min(nbrick, 4096);
     int rc = launch(4, "brick_flags_all", [&] {
@@ -681,6 +782,11 @@ struct Engine : EngineBase {
     int rc;
     if ((rc = run_measure(true))) return rc;
     if ((rc = run_track(true))) return rc;
+    if (surf) {
+      if ((rc = post_track(true, true))) return rc;
+      if ((rc = run_surf_update())) return rc;
+      return run_surf_predict(true);
+    }
     if ((rc = run_fuse(true, true))) return rc;
     return run_raycast(true);
   }
@@ -696,13 +802,13 @@ struct Engine : EngineBase {
     if (!measured) return fail(XSLAM_ERR_STATE, "integrate: no measured frame");
     if (pose && (rc = set_real_pose(pose))) return rc;
     if ((rc = fill<int>(lost, 0, 1))) return rc;
-    return run_fuse(false, false);
+    return surf ? run_surf_update() : run_fuse(false, false);
   }
 
   int raycast(const double* pose, void* vmap, void* nmap) override {
     int rc;
     if (pose && (rc = set_real_pose(pose))) return rc;
-    if ((rc = run_raycast())) return rc;
+    if ((rc = surf ? run_surf_predict() : run_raycast())) return rc;
     size_t bytes = size_t(3) * NC * npx[0] * sizeof(T);
     if (vmap && hipMemcpyAsync(vmap, Vm[0], bytes, hipMemcpyDeviceToDevice, C->stream) != hipSuccess)
       return check("vmap copy");
@@ -724,8 +830,14 @@ struct Engine : EngineBase {
     if (frame == 0) {
       if ((rc = reset_frame_flags())) return rc;
       if ((rc = run_measure())) return rc;
-      if ((rc = run_fuse(false, true))) return rc;
-      if ((rc = run_raycast(true))) return rc;
+      if (surf) {
+        if ((rc = post_track(false, true))) return rc;
+        if ((rc = run_surf_update())) return rc;
+        if ((rc = run_surf_predict(true))) return rc;
+      } else {
+        if ((rc = run_fuse(false, true))) return rc;
+        if ((rc = run_raycast(true))) return rc;
+      }
     } else {
       if (!have_model) return fail(XSLAM_ERR_STATE, "step: no model maps");
       measured = true;
@@ -807,6 +919,42 @@ struct Engine : EngineBase {
     } else {
       (void)out;
       return fail(XSLAM_ERR_UNSUPPORTED, "icp_energy: real runs only (a perturbation with no directions)");
+    }
+  }
+
+  // relocalisation objective at the host pose T16 against the volume, with
+  // the last measured frame as the query; real runs only
+  int reloc_energy(const double* T16, double* out) override {
+    if constexpr (D == 0 && Q == 0) {
+      if (surf) return fail(XSLAM_ERR_UNSUPPORTED, "reloc_energy: needs the TSDF map");
+      if (!measured) return fail(XSLAM_ERR_STATE, "reloc_energy: no measured frame");
+      int rc = XSLAM_OK;
+      const KPose<T, D, Q> Kh = to_kpose<T, double>(pose_from_host(T16));
+      if (hipMemcpyAsync(Kq, &Kh, sizeof(Kh), hipMemcpyHostToDevice, C->stream) != hipSuccess)
+        return check("pose upload");
+      const int ntx = (W[0] + kTile - 1) / kTile, nty = (H[0] + kTile - 1) / kTile;
+      const int ncx = (ntx + kCell - 1) / kCell, ncy = (nty + kCell - 1) / kCell;
+      const PostTrack<T, D, Q> none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+      if ((rc = launch(4, "tile_zmax", [&] {
+             XS_LAUNCH((k_tile_zmax<T, D, Q>), dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0], tzmax,
+                       czmax, none);
+           })))
+        return rc;
+      if ((rc = launch(4, "reloc", [&] {
+             XS_LAUNCH((k_reloc<T>), dim3(kRelocBlocks), dim3(kBrickVox), 0, C->stream, kp, Kq, Dl[0], tzmax, czmax,
+                       bflags, rec, nbrick, partials);
+           })))
+        return rc;
+      if ((rc = launch(4, "reloc_finish", [&] {
+             XS_LAUNCH(k_reloc_finish<T>, dim3(1), dim3(1024), 0, C->stream, partials, sums);
+           })))
+        return rc;
+      if (hipMemcpyAsync(out, sums, kRelocNS * sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+        return check("sums copy");
+      return sync();   // (Kh is a stack temporary)
+    } else {
+      (void)T16; (void)out;
+      return fail(XSLAM_ERR_UNSUPPORTED, "reloc_energy: real runs only (a perturbation with no directions)");
     }
   }
 
@@ -1004,6 +1152,38 @@ struct Engine : EngineBase {
         // whether constant velocity extrapolates)
         if (bytes % row || bytes / row > size_t(C->cfg.max_frames)) return fail(XSLAM_ERR_ARG, "counters: size");
         return bytes ? copy(false, buf, counters, bytes) : XSLAM_OK;
+      }
+      case XSLAM_F_SURF_V: case XSLAM_F_SURF_N: case XSLAM_F_SURF_R: case XSLAM_F_SURF_C: case XSLAM_F_SURF_T: {
+        if (!surf) return fail(XSLAM_ERR_ARG, "surfel fields need the surfel map");
+        const size_t cap = size_t(scfg.cap);
+        const bool vec = field == XSLAM_F_SURF_V || field == XSLAM_F_SURF_N;
+        const size_t per = field == XSLAM_F_SURF_T ? sizeof(int32_t) : (vec ? 3 : 1) * NC * sizeof(T);
+        void* dev = field == XSLAM_F_SURF_V ? (void*)sm.v : field == XSLAM_F_SURF_N ? (void*)sm.n
+                  : field == XSLAM_F_SURF_R ? (void*)sm.r : field == XSLAM_F_SURF_C ? (void*)sm.c : (void*)sm.t;
+        if (get) {
+          if (!need(cap * per)) return fail(XSLAM_ERR_ARG, "surfels: size");
+          return copy(true, buf, dev, cap * per);
+        }
+        // set: the leading m entries of each plane ([planes][m] on the host)
+        const size_t planes = field == XSLAM_F_SURF_T ? 1 : (vec ? 3 : 1) * NC;
+        const size_t esz = field == XSLAM_F_SURF_T ? sizeof(int32_t) : sizeof(T);
+        if (bytes % (planes * esz) || bytes / (planes * esz) > cap) return fail(XSLAM_ERR_ARG, "surfels: size");
+        const size_t m = bytes / (planes * esz);
+        for (size_t q = 0; q < planes; ++q) {
+          if (hipMemcpyAsync(static_cast<char*>(dev) + q * cap * esz, static_cast<const char*>(buf) + q * m * esz,
+                             m * esz, hipMemcpyHostToDevice, C->stream) != hipSuccess)
+            return check("surfels upload");
+        }
+        return sync();
+      }
+      case XSLAM_F_SURF_COUNT: {
+        if (!surf) return fail(XSLAM_ERR_ARG, "surfel fields need the surfel map");
+        if (!need(sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "surfel count: size");
+        if (get) return copy(true, buf, sm.count, sizeof(int32_t));
+        const int m = *static_cast<const int32_t*>(buf);
+        if (m < 0 || m > scfg.cap) return fail(XSLAM_ERR_ARG, "surfel count: range");
+        int rc = fill<int>(sm.count, m, 1);
+        return rc ? rc : sync();
       }
       case XSLAM_F_FRAME: {
         if (!need(sizeof(int32_t))) return fail(XSLAM_ERR_ARG, "frame: size");

@@ -1175,62 +1175,67 @@ __global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int
   }
 }
 
-// Bricks that may hold an updated voxel (a conservative sphere test): in
-// front of the camera, intersecting the four frustum planes of the pixel range
-// that admits a bilinear depth lookup, and not farther than mu behind the
-// largest depth over the tiles its projection (plus one pixel) covers.
+// Whether brick b may hold a voxel that fusion at the pose P (real parts)
+// updates (a conservative sphere test): in front of the camera, intersecting
+// the four frustum planes of the pixel range that admits a bilinear depth
+// lookup, and not farther than mu behind the largest depth over the tiles its
+// projection (plus one pixel) covers.
+template <typename T, int D, int Q>
+__device__ __forceinline__ bool brick_may_update(const KParams<T, D, Q>& kp, const KPose<T, D, Q>& P,
+                                                 const T* __restrict__ tmax, const T* __restrict__ cmax, int b) {
+  const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
+  const double s = double(kp.voxel);
+  const double c[3] = {(bx * 8 + 4) * s - 0.5 * kp.dim[0] * s, (by * 8 + 4) * s - 0.5 * kp.dim[1] * s,
+                       (bz * 8 + 4) * s - 0.5 * kp.dim[2] * s};
+  const double r = 4.0 * 1.7320508075688772 * s * 1.01;
+  double d[3], x[3];
+  for (int a = 0; a < 3; ++a) d[a] = c[a] - double(P.t[a].re());
+  for (int a = 0; a < 3; ++a)
+    x[a] = double(P.R[0 + a].re()) * d[0] + double(P.R[3 + a].re()) * d[1] + double(P.R[6 + a].re()) * d[2];
+  const double fx = kp.fx.re(), fy = kp.fy.re(), cx = kp.cx.re(), cy = kp.cy.re();
+  const double n[4][3] = {{fx, 0, cx}, {-fx, 0, double(kp.W - 1) - cx}, {0, fy, cy}, {0, -fy, double(kp.H - 1) - cy}};
+  bool keep = x[2] + r > 0.0;
+  for (int q = 0; q < 4 && keep; ++q) {
+    const double dn = n[q][0] * x[0] + n[q][1] * x[1] + n[q][2] * x[2];
+    const double nn = sqrt(n[q][0] * n[q][0] + n[q][1] * n[q][1] + n[q][2] * n[q][2]);
+    keep = dn >= -r * nn;
+  }
+  // a brick reaching to the camera plane (z0 <= 1 mm) has no bounded
+  // footprint: it is kept without the depth test (a conservative cull)
+  if (keep && x[2] - r > 1e-3) {
+    const int ntx = (kp.W + kTile - 1) / kTile;
+    int tx0, tx1, ty0, ty1;
+    const double z0 = x[2] - r, z1 = x[2] + r;
+    {
+      const double ul = cx + fx * fmin((x[0] - r) / z0, (x[0] - r) / z1), uh = cx + fx * fmax((x[0] + r) / z0, (x[0] + r) / z1);
+      const double vl = cy + fy * fmin((x[1] - r) / z0, (x[1] - r) / z1), vh = cy + fy * fmax((x[1] + r) / z0, (x[1] + r) / z1);
+      const int pxl = int(fmax(floor(ul) - 1.0, 0.0)), pxh = int(fmin(floor(uh) + 2.0, double(kp.W - 1)));
+      const int pyl = int(fmax(floor(vl) - 1.0, 0.0)), pyh = int(fmin(floor(vh) + 2.0, double(kp.H - 1)));
+      tx0 = pxl / kTile; tx1 = pxh / kTile; ty0 = pyl / kTile; ty1 = pyh / kTile;
+    }
+    double zm = 0.0;
+    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= kCell * kCell) {
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) zm = fmax(zm, double(tmax[ty * ntx + tx]));
+    } else {
+      // a large footprint: the 64x64 cells covering it (a bound at least as large)
+      const int ncx = (ntx + kCell - 1) / kCell;
+      for (int cy = ty0 / kCell; cy <= ty1 / kCell; ++cy)
+        for (int cx = tx0 / kCell; cx <= tx1 / kCell; ++cx) zm = fmax(zm, double(cmax[cy * ncx + cx]));
+    }
+    keep = zm > 0.0 && z0 <= zm + double(kp.mu.re()) * 1.01 + 1e-6;
+  }
+  return keep;
+}
+
+// The bricks fusion at the current pose may update, appended to a list.
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
                                                     const T* __restrict__ tmax, const T* __restrict__ cmax,
                                                     int nbrick, int* __restrict__ list,
                                                     int* __restrict__ count, const int* __restrict__ lost) {
   const int b = blockIdx.x * 256 + threadIdx.x;
-  bool keep = false;
-  if (b < nbrick && !*lost) {
-    const int bx = b % kp.nbr[0], by = (b / kp.nbr[0]) % kp.nbr[1], bz = b / (kp.nbr[0] * kp.nbr[1]);
-    const double s = double(kp.voxel);
-    const double c[3] = {(bx * 8 + 4) * s - 0.5 * kp.dim[0] * s, (by * 8 + 4) * s - 0.5 * kp.dim[1] * s,
-                         (bz * 8 + 4) * s - 0.5 * kp.dim[2] * s};
-    const double r = 4.0 * 1.7320508075688772 * s * 1.01;
-    const KPose<T, D, Q>& P = *Kk;
-    double d[3], x[3];
-    for (int a = 0; a < 3; ++a) d[a] = c[a] - double(P.t[a].re());
-    for (int a = 0; a < 3; ++a)
-      x[a] = double(P.R[0 + a].re()) * d[0] + double(P.R[3 + a].re()) * d[1] + double(P.R[6 + a].re()) * d[2];
-    const double fx = kp.fx.re(), fy = kp.fy.re(), cx = kp.cx.re(), cy = kp.cy.re();
-    const double n[4][3] = {{fx, 0, cx}, {-fx, 0, double(kp.W - 1) - cx}, {0, fy, cy}, {0, -fy, double(kp.H - 1) - cy}};
-    keep = x[2] + r > 0.0;
-    for (int q = 0; q < 4 && keep; ++q) {
-      const double dn = n[q][0] * x[0] + n[q][1] * x[1] + n[q][2] * x[2];
-      const double nn = sqrt(n[q][0] * n[q][0] + n[q][1] * n[q][1] + n[q][2] * n[q][2]);
-      keep = dn >= -r * nn;
-    }
-    // a brick reaching to the camera plane (z0 <= 1 mm) has no bounded
-    // footprint: it is kept without the depth test (a conservative cull)
-    if (keep && x[2] - r > 1e-3) {
-      const int ntx = (kp.W + kTile - 1) / kTile;
-      int tx0, tx1, ty0, ty1;
-      const double z0 = x[2] - r, z1 = x[2] + r;
-      {
-        const double ul = cx + fx * fmin((x[0] - r) / z0, (x[0] - r) / z1), uh = cx + fx * fmax((x[0] + r) / z0, (x[0] + r) / z1);
-        const double vl = cy + fy * fmin((x[1] - r) / z0, (x[1] - r) / z1), vh = cy + fy * fmax((x[1] + r) / z0, (x[1] + r) / z1);
-        const int pxl = int(fmax(floor(ul) - 1.0, 0.0)), pxh = int(fmin(floor(uh) + 2.0, double(kp.W - 1)));
-        const int pyl = int(fmax(floor(vl) - 1.0, 0.0)), pyh = int(fmin(floor(vh) + 2.0, double(kp.H - 1)));
-        tx0 = pxl / kTile; tx1 = pxh / kTile; ty0 = pyl / kTile; ty1 = pyh / kTile;
-      }
-      double zm = 0.0;
-      if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= kCell * kCell) {
-        for (int ty = ty0; ty <= ty1; ++ty)
-          for (int tx = tx0; tx <= tx1; ++tx) zm = fmax(zm, double(tmax[ty * ntx + tx]));
-      } else {
-        // a large footprint: the 64x64 cells covering it (a bound at least as large)
-        const int ncx = (ntx + kCell - 1) / kCell;
-        for (int cy = ty0 / kCell; cy <= ty1 / kCell; ++cy)
-          for (int cx = tx0 / kCell; cx <= tx1 / kCell; ++cx) zm = fmax(zm, double(cmax[cy * ncx + cx]));
-      }
-      keep = zm > 0.0 && z0 <= zm + double(kp.mu.re()) * 1.01 + 1e-6;
-    }
-  }
+  const bool keep = b < nbrick && !*lost && brick_may_update(kp, *Kk, tmax, cmax, b);
   // one list append per workgroup (ballots, then a prefix over the 4 waves)
   const unsigned long long bal = __ballot(keep);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

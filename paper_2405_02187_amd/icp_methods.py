@@ -17,7 +17,13 @@ search can walk off the surface:
 * ``ncg``: Polak-Ribiere+ conjugate directions, the same line search,
   restarted every 6 iterations or when d is not a descent direction;
 * ``newton``: d = -H^-1 g (the complex-step Hessian), full step, halved
-  while E does not decrease; -g when H is not positive definite.
+  while E does not decrease; the gradient step when H is not positive
+  definite or no halving decreases E.  With a
+  threshold ``eta`` (Sec. 5.2: Newton's method depends on its start), the
+  gradient step is taken instead while E exceeds eta;
+* ``gd_fd``: gradient descent on central finite differences of E (step
+  ``fd_step``) instead of the complex-step gradient, the comparison the
+  paper draws for relocalisation.
 
 The paper runs this on a depth image of ICL-NUIM lr kt1 (not available
 here); a seeded synthetic scene stands in for it.
@@ -78,10 +84,24 @@ def _clip(d, radius):
     return d if n <= radius else d * (radius / n)
 
 
-def optimise(f, T_start, T_true, method: str, iters: int = 30, radius: float = 0.05):
-    """-> list of per-iteration dict(it, E, t_err_m, r_err_deg, count)."""
+def _fd_gradient(f, T, h):
+    g = np.zeros(6)
+    for a in range(6):
+        e = np.zeros(6)
+        e[a] = h
+        g[a] = (f(se3_exp(e) @ T)[0] - f(se3_exp(-e) @ T)[0]) / (2.0 * h)
+    return g
+
+
+def optimise(f, T_start, T_true, method: str, iters: int = 30, radius: float = 0.05, eta=None,
+             fd_step: float = 1e-3):
+    """-> list of per-iteration dict(it, E, t_err_m, r_err_deg, count, step)
+    (step: the direction taken to reach the next iterate, "newton" or
+    "gradient")."""
     T = np.array(T_start, dtype=np.float64)
     E, g, H, cnt = f(T)
+    if method == "gd_fd":
+        g = _fd_gradient(f, T, fd_step)
     trace = []
     d_prev, g_prev, alpha = None, None, 1.0
     for it in range(iters + 1):
@@ -89,22 +109,29 @@ def optimise(f, T_start, T_true, method: str, iters: int = 30, radius: float = 0
         trace.append(dict(it=it, E=float(E), t_err_m=dt, r_err_deg=dr, count=int(cnt)))
         if it == iters or not np.isfinite(E) or np.linalg.norm(g) == 0.0:
             break
-        if method == "newton":
+        newton = method == "newton" and (eta is None or E <= eta)
+        Tn = None
+        if newton:
             try:
                 np.linalg.cholesky(H)
                 d = -np.linalg.solve(H, g)
             except np.linalg.LinAlgError:
-                d = -g
-            d = _clip(d, radius)
-            a = 1.0
-            for _ in range(40):
-                Tn = se3_exp(a * d) @ T
-                if f(Tn)[0] <= E:
-                    break
-                a *= 0.5
-            else:
-                Tn = T
+                d = None
+            if d is not None:
+                d = _clip(d, radius)
+                a = 1.0
+                for _ in range(20):
+                    Tc = se3_exp(a * d) @ T
+                    if f(Tc)[0] <= E:
+                        Tn = Tc
+                        break
+                    a *= 0.5
+            trace[-1]["step"] = "newton" if Tn is not None else "gradient"
         else:
+            trace[-1]["step"] = "gradient"
+        if Tn is None:
+            # gradient descent / nonlinear CG, and the fall-back of a Newton
+            # step that is not a descent step
             d = -g
             if method == "ncg" and d_prev is not None and it % 6 != 0:
                 beta = max(0.0, float(g @ (g - g_prev)) / float(g_prev @ g_prev))
@@ -115,9 +142,13 @@ def optimise(f, T_start, T_true, method: str, iters: int = 30, radius: float = 0
             a0 = alpha * 2.0 if d_prev is not None else 1.0 / max(np.linalg.norm(g), 1e-300)
             a0 = min(a0, radius / max(float(np.linalg.norm(d)), 1e-300))
             alpha, Tn = _line_search(f, T, E, g, d, a0)
+            if alpha == 0.0:
+                break            # no sufficient decrease along d: stationary
             d_prev, g_prev = d, g
         T = Tn
         E, g, H, cnt = f(T)
+        if method == "gd_fd":
+            g = _fd_gradient(f, T, fd_step)
     return trace
 
 

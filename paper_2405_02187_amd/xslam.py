@@ -24,7 +24,9 @@ N_TIMER_CLASSES = len(TIMER_CLASSES)
 (P_PHI_X, P_PHI_Y, P_PHI_Z, P_RHO_X, P_RHO_Y, P_RHO_Z, P_TRUNC, P_WCAP, P_DGATE, P_AGATE,
  P_ICPW0, P_ICPW1, P_ICPW2, P_FX, P_FY, P_CX, P_CY, P_DEPTH) = range(18)
 (F_POSE, F_POSES, F_TSDF, F_WEIGHT, F_VMAP, F_NMAP, F_ZMAP, F_MVALID, F_MEAS_DEPTH, F_MEAS_V,
- F_MEAS_N, F_MEAS_VALID, F_COUNTERS, F_PREV_POSE, F_FRAME) = range(15)
+ F_MEAS_N, F_MEAS_VALID, F_COUNTERS, F_PREV_POSE, F_FRAME, F_SURF_V, F_SURF_N, F_SURF_R, F_SURF_C, F_SURF_T,
+ F_SURF_COUNT) = range(21)
+MAP_TSDF, MAP_SURFEL = 0, 1
 N_COUNTERS = 40
 
 
@@ -61,10 +63,16 @@ class xslam_launch(C.Structure):
                 ("reserved", C.c_int32 * 2)]
 
 
+class xslam_surfel(C.Structure):
+    _fields_ = [("d_depth", C.c_double), ("d_norm_deg", C.c_double), ("d_dist", C.c_double), ("sigma", C.c_double),
+                ("c_stable", C.c_double), ("capacity", C.c_int32)]
+
+
 class xslam_config(C.Structure):
     _fields_ = [("prec", C.c_int32), ("cam", xslam_camera), ("vol", xslam_volume), ("icp", xslam_icp),
                 ("bilateral_radius", C.c_int32), ("bilateral_sigma_px", C.c_double),
-                ("bilateral_sigma_m", C.c_double), ("near_m", C.c_double), ("max_frames", C.c_int32)]
+                ("bilateral_sigma_m", C.c_double), ("near_m", C.c_double), ("max_frames", C.c_int32),
+                ("map", C.c_int32), ("surfel", xslam_surfel)]
 
 
 _lib = None
@@ -91,6 +99,7 @@ def lib():
             "xslam_icp_pass": (C.c_int, [vp, C.c_int32, dp]),
             "xslam_traj_err": (C.c_int, [vp, dp, C.c_int32, dp]),
             "xslam_icp_energy": (C.c_int, [vp, C.c_int32, C.c_int32, dp]),
+            "xslam_reloc_energy": (C.c_int, [vp, dp, dp]),
             "xslam_get": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
             "xslam_set": (C.c_int, [vp, C.c_int32, vp, C.c_size_t]),
             "xslam_set_timing": (C.c_int, [vp, C.c_int32]),
@@ -118,7 +127,7 @@ def lib():
 
 
 EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xslam_measure", "xslam_integrate",
-           "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_icp_energy", "xslam_traj_err", "xslam_get",
+           "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_icp_energy", "xslam_reloc_energy", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
            "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
            "xslam_autotune", "xslam_frame_graph", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
@@ -133,7 +142,10 @@ class XslamError(RuntimeError):
 def make_config(prec=C64, width=640, height=480, fx=525.0, fy=525.0, cx=319.5, cy=239.5, dim=(512, 512, 512),
                 voxel=0.01, trunc=0.06, wcap=64.0, iters=(10, 5, 4), dgate=0.1, agate_deg=20.0,
                 level_w=(1.0, 1.0, 1.0), disc_delta=0.1, init=0, update=0, solver=0, bilateral_radius=3, sigma_px=4.5,
-                sigma_m=0.03, near_m=0.1, max_frames=512) -> xslam_config:
+                sigma_m=0.03, near_m=0.1, max_frames=512, map=MAP_TSDF, surf_d_depth=0.03, surf_d_norm_deg=30.0,
+                surf_d_dist=0.03, surf_sigma=0.015, surf_c_stable=0.0, surf_capacity=0) -> xslam_config:
+    """surf_*: the surfel front end (map=MAP_SURFEL); capacity 0: 8 x the
+    pixels of a frame."""
     c = xslam_config()
     c.prec = prec
     c.cam = xslam_camera(width, height, fx, fy, cx, cy)
@@ -145,6 +157,9 @@ def make_config(prec=C64, width=640, height=480, fx=525.0, fy=525.0, cx=319.5, c
     c.icp.disc_delta, c.icp.init, c.icp.update, c.icp.solver = disc_delta, init, update, solver
     c.bilateral_radius, c.bilateral_sigma_px, c.bilateral_sigma_m = bilateral_radius, sigma_px, sigma_m
     c.near_m, c.max_frames = near_m, max_frames
+    c.map = map
+    c.surfel = xslam_surfel(surf_d_depth, surf_d_norm_deg, surf_d_dist, surf_sigma, surf_c_stable,
+                            surf_capacity or 8 * width * height)
     return c
 
 
@@ -275,6 +290,20 @@ class Slam:
         H = H + np.triu(H, 1).T
         return out[0], out[1:7].copy(), H, int(out[28])
 
+    def reloc_energy(self, T):
+        """Relocalisation objective at the camera-to-world pose T (4x4) against
+        the context's volume, the last measured frame as the query: -> (E,
+        gradient (6,), Hessian (6, 6), contributing voxels)."""
+        T = np.ascontiguousarray(T, np.float64).reshape(16)
+        out = np.zeros(29)
+        self._check(lib().xslam_reloc_energy(self.h, T.ctypes.data_as(C.POINTER(C.c_double)),
+                                             out.ctypes.data_as(C.POINTER(C.c_double))))
+        H = np.zeros((6, 6))
+        iu = np.triu_indices(6)
+        H[iu] = out[7:28]
+        H = H + np.triu(H, 1).T
+        return out[0], out[1:7].copy(), H, int(out[28])
+
     def traj_err(self, gt):
         gt = np.ascontiguousarray(gt, np.float64).reshape(-1, 16)
         out = np.zeros(self.nc)
@@ -359,6 +388,15 @@ class Slam:
             return (tot,), np.uint8
         if field == F_COUNTERS:
             return (min(self.frame(), self.cfg.max_frames), N_COUNTERS), np.int32
+        cap = self.cfg.surfel.capacity
+        if field in (F_SURF_V, F_SURF_N):
+            return (3, nc, cap), fl
+        if field in (F_SURF_R, F_SURF_C):
+            return (nc, cap), fl
+        if field == F_SURF_T:
+            return (cap,), np.int32
+        if field == F_SURF_COUNT:
+            return (1,), np.int32
         raise ValueError(field)
 
     def frame(self):
@@ -385,6 +423,8 @@ class Slam:
         """Host copy of everything later frame steps read (checkpoint)."""
         st = {f: self.get(f) for f in self.STATE_FIELDS}
         st[F_FRAME] = self.frame()
+        if self.cfg.map == MAP_SURFEL:
+            st["surfels"] = self.surfels()
         return st
 
     def load_state(self, st: dict) -> None:
@@ -392,11 +432,36 @@ class Slam:
         same configuration and perturbation."""
         for f in self.STATE_FIELDS:
             self.set(f, st[f])
+        if "surfels" in st:
+            self.set_surfels(st["surfels"])
         self.set_frame(st[F_FRAME])
 
     def set_frame(self, k):
         v = np.array([k], np.int32)
         self._check(lib().xslam_set(self.h, F_FRAME, v.ctypes.data_as(C.c_void_p), 4))
+
+    def surfels(self) -> dict:
+        """The surfel map (map = MAP_SURFEL): dict(v (m, 3, nc), n, r (m, nc),
+        c, t (m,)) over the m surfels in use."""
+        m = int(self.get(F_SURF_COUNT)[0])
+        V, N = self.get(F_SURF_V), self.get(F_SURF_N)
+        return dict(v=np.transpose(V[:, :, :m], (2, 0, 1)), n=np.transpose(N[:, :, :m], (2, 0, 1)),
+                    r=self.get(F_SURF_R)[:, :m].T, c=self.get(F_SURF_C)[:, :m].T, t=self.get(F_SURF_T)[:m])
+
+    def set_surfels(self, S: dict) -> None:
+        """Load a surfel map (as returned by ``surfels``)."""
+        m = len(S["t"])
+        self.set_raw(F_SURF_V, np.ascontiguousarray(np.transpose(S["v"], (1, 2, 0)), dtype=self.np_dtype))
+        self.set_raw(F_SURF_N, np.ascontiguousarray(np.transpose(S["n"], (1, 2, 0)), dtype=self.np_dtype))
+        self.set_raw(F_SURF_R, np.ascontiguousarray(np.asarray(S["r"]).T, dtype=self.np_dtype))
+        self.set_raw(F_SURF_C, np.ascontiguousarray(np.asarray(S["c"]).T, dtype=self.np_dtype))
+        self.set_raw(F_SURF_T, np.ascontiguousarray(S["t"], dtype=np.int32))
+        self.set(F_SURF_COUNT, np.array([m], np.int32))
+
+    def set_raw(self, field, value: np.ndarray) -> None:
+        """xslam_set with the buffer as given (its size decides what is written)."""
+        v = np.ascontiguousarray(value)
+        self._check(lib().xslam_set(self.h, field, v.ctypes.data_as(C.c_void_p), v.nbytes))
 
     def measured(self):
         """-> per level dict(D (nc,H,W), V (3,nc,H,W), N, valid (H,W))."""

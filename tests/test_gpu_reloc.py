@@ -1,0 +1,96 @@
+"""GPU camera relocalisation (Sec. 5.2) against the oracle, and the optimiser
+on synthetic queries.
+
+* ``xslam_reloc_energy``: E(T_q) = sum (F_r - F_q)^2 with its gradient and
+  Hessian in the pose increment (the library: one pass with six hyper-dual
+  directions and their 21 pairs per voxel; the oracle: 6 complex-step and 21
+  bicomplex evaluations of the whole sum).  The reference volume is the
+  oracle's (3 frames of the 128^3 sequence), the query's filtered depth the
+  oracle's; at the query's true pose and at two poses off it: count equal,
+  E, g and H within 1e-10 (FP64).  A second call returns the same bits (the
+  sums' order is fixed), and the context's volume is untouched.
+* Relocalisation of synthetic queries (reference frames around the query
+  at their true poses, a 3 cm / 3 degree initial error): gradient descent,
+  gradient descent on finite differences, and Newton with the gradient step
+  while the loss exceeds its threshold; Newton ends closer than the start
+  and no farther than gradient descent.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as sg
+from gpu_util import created_stream, log, relerr, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_02187_amd import icp_methods as IM  # noqa: E402
+from paper_2405_02187_amd import relocalize as RL  # noqa: E402
+from paper_2405_02187_amd import xslam as X  # noqa: E402
+
+
+def test_reloc_energy_matches_oracle():
+    p = sg.preset("c0")
+    seq = sg.make_sequence(p, n_frames=6)
+    d = seq.depths().astype(np.float64)
+    c = O.config(p)
+    ref = O.run_sequence(c, O.seed(0), d[:3], seq.poses_gt[0], want_volume=True)
+    meas = O.measure(c, O.seed(0), d[4])
+    Dcat = np.concatenate([m["D"][..., 0].reshape(-1) for m in meas])
+    T_true = seq.poses_gt[4]
+    poses = [T_true, IM.se3_exp([0.01, -0.02, 0.015, 0.02, 0.01, -0.015]) @ T_true,
+             IM.se3_exp([-0.03, 0.01, 0.0, -0.01, 0.03, 0.02]) @ T_true]
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=4)
+        slam = X.Slam(cfg, X.Perturbation([]), seq.poses_gt[0])
+        slam.set(X.F_TSDF, ref["F"].T)
+        slam.set(X.F_WEIGHT, ref["W"].T)
+        slam.measure(torch_dev(d[4], np.float64))
+        slam.set(X.F_MEAS_DEPTH, Dcat)
+        for k, T in enumerate(poses):
+            E, g, H, cnt = slam.reloc_energy(T)
+            Er, gr, Hr, cr = O.reloc_energy(c, ref["F"], ref["W"], meas[0]["D"], T, order=2)
+            log("reloc pose", k, "count", cnt, cr, "E", E, Er, "g err", relerr(g, gr), "H err", relerr(H, Hr))
+            assert cnt == cr > 10000
+            assert relerr(E, Er) <= 1e-10
+            assert relerr(g, gr) <= 1e-10
+            assert relerr(H, Hr) <= 1e-10
+            E2, g2, H2, cnt2 = slam.reloc_energy(T)
+            assert E2 == E and np.array_equal(g2, g) and np.array_equal(H2, H) and cnt2 == cnt
+        F = slam.get(X.F_TSDF)
+        Wt = slam.get(X.F_WEIGHT)
+        assert np.array_equal(F[0], ref["F"][:, 0]) and np.array_equal(Wt[0], ref["W"][:, 0])
+        slam.close()
+
+
+def test_reloc_refuses_runs_with_directions():
+    p = sg.preset("c0")
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=4)
+        slam = X.Slam(cfg, X.Perturbation([(X.P_FX, 1e-20)]), np.eye(4))
+        with pytest.raises(RuntimeError):
+            slam.reloc_energy(np.eye(4))
+        slam.close()
+
+
+@pytest.mark.parametrize("prec", [X.C128, X.C64])
+def test_relocalisation_study_newton_improves(prec):
+    p = sg.preset("c0")
+    seq = sg.make_sequence(p, n_frames=40)
+    d = seq.depths()
+    with created_stream():
+        rows = RL.study(p, d, seq.poses_gt, queries=(10, 22, 34), prec=prec, iters=15)
+    for r in rows:
+        log("reloc", r)
+    s = RL.summarise(rows)
+    log("reloc summary", s)
+    for q in (10, 22, 34):
+        rq = {r["method"]: r for r in rows if r["query"] == q}
+        nt = rq["newton"]
+        assert nt["t_m"] < nt["t0_m"]
+        assert nt["E"] <= rq["gd"]["E"] * (1 + 1e-6)
+        assert np.isfinite(rq["gd_fd"]["E"])
