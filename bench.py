@@ -222,6 +222,39 @@ def forms(X, torch, sg, p1, dev1, T0, n_warm=5, n_timed=30, multi_cap=None, shap
     slam.close()
     out["fp32_16dir_10pair"]["same_workload_1dir_value"] = n_timed / dt1
     del dev2, tan2
+    # the surfel front end (X-PointFusion) on the same frames: FP32-complex, one direction
+    cfg = X.config_from_preset(p1, prec=X.C64, max_frames=nf, map=X.MAP_SURFEL)
+    slam, dt = _timed_run(X, torch, cfg, X.Perturbation([(X.P_PHI_X, h32)]), T0, dev1, n_warm, n_timed,
+                          shapes=shapes)
+    cnt = slam.get(X.F_COUNTERS)
+    Ps = slam.get(X.F_POSES)
+    slam.close()
+    gt = sg.make_sequence(p1, n_frames=nf).poses_gt
+    out["surfel_fp32_1dir"] = dict(value=n_timed / dt, unit="frames·directions/s", frames=n_timed,
+                                   workload="seq640x480_surfels_fp32complex_1dir",
+                                   surfels_at_end=int(cnt[nf - 1, 37]), lost_frames=int(cnt[:nf, 0].sum()),
+                                   ate_m=float(np.sqrt(np.mean(np.sum((Ps[:nf, 0, :3, 3] - gt[:nf, :3, 3]) ** 2, -1)))))
+    # the relocalisation objective with its gradient and Hessian (one pass),
+    # reference volume from 4 frames around a query, FP32
+    from paper_2405_02187_amd import relocalize as RL
+    q = min(nf - 7, 20)
+    refs = [q - 6, q - 3, q + 3, q + 6]
+    cfg = X.config_from_preset(p1, prec=X.C64, max_frames=4)
+    slam = X.Slam(cfg, X.Perturbation([]), T0)
+    RL.build_reference(slam, dev1[refs], gt[refs])
+    slam.measure(dev1[q])
+    for _ in range(3):
+        slam.reloc_energy(gt[q])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_ev = 20
+    for _ in range(n_ev):
+        E, g, H, c = slam.reloc_energy(gt[q])
+    dt = time.perf_counter() - t0
+    slam.close()
+    out["reloc_objective_fp32"] = dict(value=n_ev / dt, unit="evaluations/s (E, gradient, Hessian)",
+                                       contributing_voxels=int(c), workload="tsdf512_1cm_640x480_query_4refs",
+                                       note="synchronous calls: includes the host round trip")
     # one FP32 frame step from the FP64 state at later frames of the sequence
     from paper_2405_02187_amd import precision as PR
     kmax = 499

@@ -108,21 +108,28 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16* __restrict__ x, co
   }
 }
 
-// input gradient of conv L masked by relu'(its input): rows = input positions
-// (n, iy, ix), cols = input channels, k = co*9 + ky*3 + kx gathering dz at
-// oy = (iy + 1 - ky)/2, ox = (ix + 1 - kx)/2 when integral and in range.
-template <int L>
+// input gradient of conv L masked by relu'(its input).  Of the 9 taps of the
+// stride-2 3x3 convolution only those of one parity class reach an input
+// position: an even input row takes ky = 1 (output row iy/2), an odd one
+// ky = 0 and 2 (output rows (iy+1)/2 and (iy-1)/2); columns likewise.  So the
+// input positions are split into the four classes (iy mod 2, ix mod 2), and
+// class (PY, PX) is an implicit GEMM of rows = its positions (n, iy, ix),
+// cols = input channels, k = co * NT + t over its NT = (1 + PY)(1 + PX) taps:
+// every MFMA operand is a tap that exists.
+template <int L, int PY, int PX>
 __global__ __launch_bounds__(256) void k_conv_bwd_x(const bf16* __restrict__ dz, const bf16* __restrict__ w,
                                                      const bf16* __restrict__ xin, bf16* __restrict__ dzin, int N) {
   constexpr int Ci = kCh[L], Co = kCh[L + 1], H = kH[L], W = kW[L], Ho = kH[L + 1], Wo = kW[L + 1];
-  constexpr int K = Co * 9, KP = (K + 15) / 16 * 16, KPW = kpad(L);
+  constexpr int NY = 1 + PY, NX = 1 + PX, NT = NY * NX;
+  constexpr int Hc = (H - PY + 1) / 2, Wc = (W - PX + 1) / 2;   // positions of the class per image
+  constexpr int K = Co * NT, KP = (K + 15) / 16 * 16, KPW = kpad(L);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int M = N * H * W;
+  const int M = N * Hc * Wc;
   const int m0 = (blockIdx.x * 4 + wv) * 16, n0 = blockIdx.y * 16;
   const int row = m0 + (lane & 15), kq = 4 * (lane >> 4);
   const bool rok = row < M;
-  const int n = rok ? row / (H * W) : 0, pr = rok ? row % (H * W) : 0;
-  const int iy = pr / W, ix = pr % W;
+  const int n = rok ? row / (Hc * Wc) : 0, pr = rok ? row % (Hc * Wc) : 0;
+  const int iy = 2 * (pr / Wc) + PY, ix = 2 * (pr % Wc) + PX;
   const int ci = n0 + (lane & 15);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < KP; k0 += 16) {
@@ -132,11 +139,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const bf16* __restrict__ dz,
       const int k = k0 + kq + j;
       bf16 av = 0, bv = 0;
       if (k < K) {
-        const int co = k / 9, r = k % 9, ky = r / 3, kx = r % 3;
-        const int ty = iy + 1 - ky, tx = ix + 1 - kx;
-        if (rok && ty >= 0 && tx >= 0 && !(ty & 1) && !(tx & 1) && (ty >> 1) < Ho && (tx >> 1) < Wo)
-          av = dz[((size_t(n) * Co + co) * Ho + (ty >> 1)) * Wo + (tx >> 1)];
-        if (ci < Ci) bv = w[size_t(co) * KPW + ci * 9 + r];
+        const int co = k / NT, t = k % NT;
+        const int ky = PY ? ((t / NX) ? 2 : 0) : 1, kx = PX ? ((t % NX) ? 2 : 0) : 1;
+        const int oy = (iy + 1 - ky) >> 1, ox = (ix + 1 - kx) >> 1;
+        if (rok && iy + 1 - ky >= 0 && ix + 1 - kx >= 0 && oy < Ho && ox < Wo)
+          av = dz[((size_t(n) * Co + co) * Ho + oy) * Wo + ox];
+        if (ci < Ci) bv = w[size_t(co) * KPW + ci * 9 + ky * 3 + kx];
       }
       a[j] = short(av);
       b[j] = short(bv);
@@ -147,8 +155,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const bf16* __restrict__ dz,
   for (int j = 0; j < 4; ++j) {
     const int r2 = m0 + kq + j;
     if (r2 < M && ci < Ci) {
-      const int nn = r2 / (H * W), p2 = r2 % (H * W);
-      const size_t o = (size_t(nn) * Ci + ci) * (H * W) + p2;
+      const int nn = r2 / (Hc * Wc), p2 = r2 % (Hc * Wc);
+      const int y2 = 2 * (p2 / Wc) + PY, x2 = 2 * (p2 % Wc) + PX;
+      const size_t o = (size_t(nn) * Ci + ci) * (H * W) + size_t(y2) * W + x2;
       dzin[o] = f2bf(bf2f(xin[o]) > 0.f ? acc[j] : 0.f);
     }
   }
@@ -494,6 +503,12 @@ struct Cnn {
     return check("cnn forward");
   }
 
+  template <int L, int PY, int PX>
+  void bwd_x_class(int N) {
+    const int M = N * ((kH[L] - PY + 1) / 2) * ((kW[L] - PX + 1) / 2);
+    hipLaunchKernelGGL((k_conv_bwd_x<L, PY, PX>), dim3((M + 63) / 64, (kCh[L] + 15) / 16), dim3(256), 0, stream,
+                       dz[L + 1], wl(L), act[L], dz[L], N);
+  }
   template <int L> void conv_bwd(int N) {
     // weight gradient over position chunks
     const int P = N * kH[L + 1] * kW[L + 1];
@@ -505,10 +520,11 @@ struct Cnn {
                        chunk);
     const int nt = kCh[L + 1] * (kdim(L) + 1);
     hipLaunchKernelGGL(k_conv_grad_reduce<L>, dim3((nt + 255) / 256), dim3(256), 0, stream, part, nch, grad, o);
-    if (L > 0) {
-      const int M = N * kH[L] * kW[L];
-      hipLaunchKernelGGL(k_conv_bwd_x<L>, dim3((M + 63) / 64, (kCh[L] + 15) / 16), dim3(256), 0, stream, dz[L + 1],
-                         wl(L), act[L], dz[L], N);
+    if constexpr (L > 0) {
+      bwd_x_class<L, 0, 0>(N);
+      bwd_x_class<L, 0, 1>(N);
+      bwd_x_class<L, 1, 0>(N);
+      bwd_x_class<L, 1, 1>(N);
     }
   }
   int train(const float* x, const float* label, int N, float lr, float* loss_host) {

@@ -172,7 +172,7 @@ XJ MPose<D, Q> se3_exp(const Jet<double, D, Q> xi[6]) {
 // exp(xi); the rows of [phi]x it needs are picked with selects, not indexing).
 template <int D, int Q>
 __device__ __forceinline__ Jet<double, D, Q> se3_exp_mul_entry(const Jet<double, D, Q> xi[6],
-                                                               const MPose<D, Q>* __restrict__ P, int r, int c) {
+                                                               const Jet<double, D, Q> col[3], int r, int c) {
   using J = Jet<double, D, Q>;
   const J& px = xi[0];
   const J& py = xi[1];
@@ -193,16 +193,39 @@ __device__ __forceinline__ Jet<double, D, Q> se3_exp_mul_entry(const Jet<double,
   }
   const J tr = Vr[0] * xi[3] + Vr[1] * xi[4] + Vr[2] * xi[5];
   // column c of P: rotation column c, or the translation
+  const J prod = Er[0] * col[0] + Er[1] * col[1] + Er[2] * col[2];
+  return c < 3 ? prod : prod + tr;
+}
+
+// The same entries with the column read from P where it is used.
+template <int D, int Q>
+__device__ __forceinline__ Jet<double, D, Q> se3_exp_mul_entry(const Jet<double, D, Q> xi[6],
+                                                               const MPose<D, Q>* __restrict__ P, int r, int c) {
+  using J = Jet<double, D, Q>;
+  const J& px = xi[0];
+  const J& py = xi[1];
+  const J& pz = xi[2];
+  J A, B, C;
+  se3_abc<D, Q>(xi, A, B, C);
+  const J z = jzero<J>();
+  const J K[9] = {z, -pz, py, pz, z, -px, -py, px, z};
+  auto pick = [r](const J& a, const J& b, const J& d) { return r == 0 ? a : (r == 1 ? b : d); };
+  const J Kr[3] = {pick(K[0], K[3], K[6]), pick(K[1], K[4], K[7]), pick(K[2], K[5], K[8])};
+  J Er[3], Vr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const J K2 = Kr[0] * K[0 * 3 + k] + Kr[1] * K[1 * 3 + k] + Kr[2] * K[2 * 3 + k];
+    const J I = jconst<J>(r == k ? 1.0 : 0.0);
+    Er[k] = I + A * Kr[k] + B * K2;
+    Vr[k] = I + B * Kr[k] + C * K2;
+  }
+  const J tr = Vr[0] * xi[3] + Vr[1] * xi[4] + Vr[2] * xi[5];
   const J p0 = c < 3 ? P->m[0 * 3 + c] : P->m[9 + 0];
   const J p1 = c < 3 ? P->m[1 * 3 + c] : P->m[9 + 1];
   const J p2 = c < 3 ? P->m[2 * 3 + c] : P->m[9 + 2];
   const J prod = Er[0] * p0 + Er[1] * p1 + Er[2] * p2;
   return c < 3 ? prod : prod + tr;
 }
-
-// Entry (r, c) of T_sa(xi) * P with T_sa the small-angle transform of eq.
-// icp_approx: rotation I + [phi]x (cos taken as 1, sin as the angle),
-// translation rho.
 template <int D, int Q>
 __device__ __forceinline__ Jet<double, D, Q> smallangle_mul_entry(const Jet<double, D, Q> xi[6],
                                                                   const MPose<D, Q>* __restrict__ P, int r, int c) {
@@ -216,6 +239,30 @@ __device__ __forceinline__ Jet<double, D, Q> smallangle_mul_entry(const Jet<doub
   const J p1 = c < 3 ? P->m[1 * 3 + c] : P->m[9 + 1];
   const J p2 = c < 3 ? P->m[2 * 3 + c] : P->m[9 + 2];
   const J prod = Er[0] * p0 + Er[1] * p1 + Er[2] * p2;
+  return c < 3 ? prod : prod + xi[3 + r];
+}
+
+// Column c of the pose P (rotation column c < 3, else the translation), the
+// operand of the *_mul_entry functions.
+template <int D, int Q>
+__device__ __forceinline__ void pose_column(const MPose<D, Q>* __restrict__ P, int c, Jet<double, D, Q> col[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) col[k] = c < 3 ? P->m[k * 3 + c] : P->m[9 + k];
+}
+
+// Entry (r, c) of T_sa(xi) * P with T_sa the small-angle transform of eq.
+// icp_approx: rotation I + [phi]x (cos taken as 1, sin as the angle),
+// translation rho.
+template <int D, int Q>
+__device__ __forceinline__ Jet<double, D, Q> smallangle_mul_entry(const Jet<double, D, Q> xi[6],
+                                                                  const Jet<double, D, Q> col[3], int r, int c) {
+  using J = Jet<double, D, Q>;
+  const J z = jzero<J>();
+  const J K[9] = {z, -xi[2], xi[1], xi[2], z, -xi[0], -xi[1], xi[0], z};
+  J Er[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Er[k] = jconst<J>(r == k ? 1.0 : 0.0) + K[r * 3 + k];
+  const J prod = Er[0] * col[0] + Er[1] * col[1] + Er[2] * col[2];
   return c < 3 ? prod : prod + xi[3 + r];
 }
 

@@ -751,18 +751,52 @@ struct IcpChunks {
 // The solve after the sums (one wave): FP64 solve, relaxation, SE(3) update
 // (one entry of the new pose per lane), counters; or only the sums when they
 // are all that is wanted.
+//
+// What the finish needs from memory besides the sums, loaded by the solving
+// wave when the kernel starts, so that these round trips overlap the sums'
+// instead of following the solve one after another: the frame's counter row
+// (and the two counters it reads back), and lane (r, c)'s column of the pose.
+// (Jets of up to 8 parts, the 1024-thread finish; the many-part finish keeps
+// these loads where they are used: holding them from the start there added
+// spills to a kernel that already keeps most of its state in scratch, and
+// the 16 + 10 shape then lost its tangents.)
 template <typename T, int D, int Q>
-__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, int lane, double (*Xs)[6]) {
+constexpr bool kFinishPreload = Jet<T, D, Q>::N <= 8;
+template <int D, int Q>
+struct FinishPre {
+  int32_t* crow;
+  int32_t crow3, crow32;
+  Jet<double, D, Q> col[3];
+};
+template <typename T, int D, int Q>
+__device__ __forceinline__ FinishPre<D, Q> finish_preload(const IcpArgs<T, D, Q>& g, int lane) {
+  FinishPre<D, Q> pre;
+  const int c = lane & 3;
+  if (lane < 12) pose_column<D, Q>(g.Pcur, c, pre.col);
+  pre.crow = counter_row(g.counters, g.frame, g.max_frames);
+  pre.crow3 = 0;
+  pre.crow32 = 0;
+  if (g.do_solve && lane == 0) {
+    pre.crow3 = pre.crow[3];
+    pre.crow32 = pre.crow[32];
+  }
+  return pre;
+}
+
+template <typename T, int D, int Q>
+__device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, int lane, double (*Xs)[6],
+                                 const FinishPre<D, Q>& pre) {
   constexpr int NC = Jet<T, D, Q>::N;
   constexpr int NS = IcpSize<D, Q>::NS;
+  constexpr bool kPre = kFinishPreload<T, D, Q>;
   const int cnt = int(fin[27 * NC]);
-  int32_t* crow = counter_row(g.counters, g.frame, g.max_frames);
+  int32_t* crow = kPre ? pre.crow : counter_row(g.counters, g.frame, g.max_frames);
   if (!g.do_solve) {
     for (int k = lane; k < NS; k += 64) g.sums_out[k] = fin[k];
     return;
   }
   if (lane == 0) {
-    crow[3] += cnt;
+    crow[3] = (kPre ? pre.crow3 : crow[3]) + cnt;
     crow[4] = cnt;
     if (g.iter_slot < kMaxPasses) crow[5 + g.iter_slot] = cnt;
   }
@@ -781,13 +815,16 @@ __device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, i
   if (lane == 0) {
     double nn = 0.0;
     for (int a = 0; a < 6; ++a) nn += dx[a].re() * dx[a].re();
-    if (crow[32] == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
+    if ((kPre ? pre.crow32 : crow[32]) == 0 && sqrt(nn) < 1e-6) crow[32] = g.iter_slot + 1;
   }
   // the update exp(dx) * P, one of its 12 entries per lane
   if (lane >= 12) return;
   const int r = lane >> 2, c = lane & 3;
-  Jet<double, D, Q> e = g.update ? smallangle_mul_entry<D, Q>(dx, g.Pcur, r, c)
-                                 : se3_exp_mul_entry<D, Q>(dx, g.Pcur, r, c);
+  Jet<double, D, Q> e;
+  if constexpr (kPre)
+    e = g.update ? smallangle_mul_entry<D, Q>(dx, pre.col, r, c) : se3_exp_mul_entry<D, Q>(dx, pre.col, r, c);
+  else
+    e = g.update ? smallangle_mul_entry<D, Q>(dx, g.Pcur, r, c) : se3_exp_mul_entry<D, Q>(dx, g.Pcur, r, c);
   if (g.update) {
     // the composed rotation back to orthonormal: every lane gathers the nine
     // rotation entries and runs the same two polar Newton steps on them
@@ -1005,6 +1042,9 @@ __global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArg
   __shared__ double fin[NS];
   __shared__ double xs[Jet<T, D, Q>::N][6];
   const int lost = *g.lost;   // read now, tested after the sums (its load overlaps theirs)
+  FinishPre<D, Q> pre;
+  if constexpr (kFinishPreload<T, D, Q>)
+    if (threadIdx.x < 64) pre = finish_preload(g, int(threadIdx.x));
   const int grp0 = threadIdx.x / KC, kk = threadIdx.x % KC;
   const unsigned B = nblocks;
   for (int kc = 0; kc < NS; kc += KC) {
@@ -1043,7 +1083,7 @@ __global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArg
     __syncthreads();
   }
   if (threadIdx.x >= 64 || lost) return;
-  icp_finish_solve<T, D, Q>(g, fin, threadIdx.x, xs);
+  icp_finish_solve<T, D, Q>(g, fin, threadIdx.x, xs, pre);
 }
 
 

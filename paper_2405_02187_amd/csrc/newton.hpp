@@ -134,6 +134,8 @@ __global__ __launch_bounds__(256) void k_icp_newton_finish(IcpArgs<T, D, Q> g, i
   __shared__ double fnew[29], fgn[29];
   __shared__ double xs[1][6];
   const int lost = *g.lost;
+  FinishPre<D, Q> pre;
+  if (threadIdx.x < 64) pre = finish_preload(g, int(threadIdx.x));
   const int grp0 = threadIdx.x / KC, kk = threadIdx.x % KC;
   const unsigned B = nblocks;
   for (int kc = 0; kc < NS; kc += KC) {
@@ -182,8 +184,8 @@ __global__ __launch_bounds__(256) void k_icp_newton_finish(IcpArgs<T, D, Q> g, i
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   Jet<double, 0, 0> probe[6];
   const bool newton = int(fnew[27]) >= 6 && icp_solve<0, 0>(fnew, probe, lane, xs);
-  if (!newton && lane == 0) counter_row(g.counters, g.frame, g.max_frames)[34] += 1;
-  icp_finish_solve<T, D, Q>(g, newton ? fnew : fgn, lane, xs);
+  if (!newton && lane == 0) pre.crow[34] += 1;
+  icp_finish_solve<T, D, Q>(g, newton ? fnew : fgn, lane, xs, pre);
 }
 
 }  // namespace xs

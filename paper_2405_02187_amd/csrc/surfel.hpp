@@ -194,22 +194,30 @@ __global__ __launch_bounds__(1024) void k_surf_scan(const int* __restrict__ bcnt
                                                     const int* __restrict__ block_upd, int nupd, int* count, int* base,
                                                     int cap, int32_t* __restrict__ counter_base,
                                                     const int* __restrict__ frame, int max_frames) {
-  __shared__ int part[1024];
+  __shared__ int wtot[16];
   int upd = 0;
   for (int i = threadIdx.x; i < nupd; i += blockDim.x) upd += block_upd[i];
   upd = block_sum_int(upd);
-  // serial chunks of the block counts, one per thread, then a scan of the chunk sums
+  // serial chunks of the block counts, one per thread, then an exclusive scan
+  // of the chunk sums (wave scans, then the scan of the 16 wave totals)
   const int per = (nblk + 1023) / 1024;
   const int b0 = threadIdx.x * per;
   int s = 0;
   for (int b = b0; b < b0 + per && b < nblk; ++b) s += bcnt[b];
-  part[threadIdx.x] = s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wtot[wv] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
-    for (int q = 0; q < 1024; ++q) {
-      const int v = part[q];
-      part[q] = acc;
+    for (int w = 0; w < 16; ++w) {
+      const int v = wtot[w];
+      wtot[w] = acc;
       acc += v;
     }
     const int c0 = *count;
@@ -223,7 +231,7 @@ __global__ __launch_bounds__(1024) void k_surf_scan(const int* __restrict__ bcnt
     row[37] = c0 + ins;
   }
   __syncthreads();
-  int acc = part[threadIdx.x];
+  int acc = wtot[wv] + inc - s;
   for (int b = b0; b < b0 + per && b < nblk; ++b) {
     boff[b] = acc;
     acc += bcnt[b];
