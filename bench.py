@@ -197,10 +197,16 @@ def forms(X, torch, sg, p1, dev1, T0, n_warm=5, n_timed=30, multi_cap=None, shap
     slam, dt = _timed_run(X, torch, cfg, X.Perturbation([(q, h32) for q in range(6)]), T0, dev1, n_warm, n_timed,
                           shapes=shapes)
     P6 = slam.get(X.F_POSES)
+    # the trajectory error of these frames and its derivative with respect to
+    # the six initial-pose directions (the complex-step parts over h)
+    gt_nf = sg.make_sequence(p1, n_frames=nf).poses_gt
+    te = slam.traj_err(gt_nf)
     slam.close()
     out["fp32_6dir_batched"] = dict(value=6 * n_timed / dt, unit="frames·directions/s", frames=n_timed,
                                     workload="seq640x480_tsdf512_1cm_fp32complex_6dir",
-                                    grad_phi_x_rel_err_vs_1dir=_rel(P6[:, 1], poses32[:nf, 1]))
+                                    grad_phi_x_rel_err_vs_1dir=_rel(P6[:, 1], poses32[:nf, 1]),
+                                    traj_err_m=float(te[0]),
+                                    dtraj_err_dxi0=[float(x) / h32 for x in te[1:7]])
     # 16 directions + 4x4 Hessian (10 pairs) in one launch per stage, 256^3 at 2 cm
     p2 = sg.preset("c2")
     seq2 = sg.make_sequence(p2, n_frames=nf)

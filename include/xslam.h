@@ -401,8 +401,10 @@ int xslam_cnn_train_step(xslam_cnn cnn, const float* x_dev, const float* label_d
 const char* xslam_cnn_last_error(xslam_cnn cnn);
 int xslam_cnn_destroy(xslam_cnn cnn);
 
-/* Attach a network to a context (created on the same stream) for icp.init 2;
- * NULL detaches.  Each tracked frame then builds the input from its measured
+/* Attach a network to a context for icp.init 2; NULL detaches.  The network
+ * must have been created on the context's stream (XSLAM_ERR_ARG otherwise):
+ * its forward pass then runs in the context's stream order and inside the
+ * context's captured frame graph.  Each tracked frame then builds the input from its measured
  * depth and the previous model maps, proposes T_{k-1} exp(xi), and keeps the
  * candidate (network or constant velocity) with the lower mean squared
  * point-to-plane residual of one level-2 association pass; the network's only

@@ -93,6 +93,8 @@ def lib():
                                         i32, dp, i64]
         L.orc_pf_run_sequence.argtypes = [cp, sp, C.c_int32, dp, dp, dp, dp, dp, i64, dp, dp, dp, dp, i32, i64]
         L.orc_pf_index_map.argtypes = [cp, dp, dp, C.c_int64, dp, C.c_int32, C.c_double, i64]
+        fp = C.POINTER(C.c_float)
+        L.orc_cnn_parts.argtypes = [cp, dp, dp, dp, u8, dp, fp, fp]
         L.orc_raycast_footprint.argtypes = [cp, sp, dp, dp, dp, u8]
         L.orc_raycast_footprint.restype = C.c_int64
         L.orc_fuse_margin.argtypes = [cp, sp, dp, dp, i64, C.c_int64, dp]
@@ -456,6 +458,23 @@ def pf_index_map(c: OrcConfig, v, conf, T, sup: int = 4, c_min: float = -1e300) 
     lib().orc_pf_index_map(C.byref(c), _p(v), _p(conf), len(v), _p(_f64(T)), int(sup), float(c_min),
                            _p(out, C.c_int64))
     return out
+
+
+def cnn_parts(c: OrcConfig, D2, Nm, Zm, validm, T):
+    """Learned-initialiser input parts (real): level-3 depth from the level-2
+    filtered depth D2 ((H/4, W/4)), and the level-0 model maps (Nm (H, W, 3),
+    Zm (H, W), validm (H, W)) sampled at (8x, 8y) with the normal rotated into
+    the camera frame of pose T.  -> (depth (H/8, W/8), model (4, H/8, W/8))
+    float32."""
+    H3, W3 = c.height // 8, c.width // 8
+    d = np.zeros((H3, W3), np.float32)
+    m = np.zeros((4, H3, W3), np.float32)
+    Nm = np.asarray(Nm)
+    Nm = Nm[..., 0] if Nm.ndim == 4 else Nm
+    lib().orc_cnn_parts(C.byref(c), _p(_f64(D2)), _p(_f64(Nm)), _p(_f64(Zm)),
+                        _p(np.ascontiguousarray(validm, np.uint8), C.c_uint8), _p(_f64(T)),
+                        _p(d, C.c_float), _p(m, C.c_float))
+    return d, m
 
 
 def raycast_footprint(c: OrcConfig, s: OrcSeed, F, W, T, touch=None):

@@ -1829,6 +1829,41 @@ void orc_pf_run_sequence(const OrcConfig* c, const OrcSeed* seed, int32_t n_fram
   });
 }
 
+// Input parts of the learned initialiser (real): the level-2 filtered depth
+// D2 ((H/4) x (W/4)) reduced once more with the pyramid's gated binomial
+// (level 3), and the level-0 model maps sampled at (8x, 8y): hit depth Zm
+// and the world normal Nm rotated into the camera frame of the pose T
+// (R^T n); invalid model pixels give 0.  depth_out: (H/8) x (W/8);
+// model_out: 4 planes of (H/8) x (W/8) (depth, n_x, n_y, n_z), FP32 values.
+void orc_cnn_parts(const OrcConfig* c, const double* D2, const double* Nm, const double* Zm, const uint8_t* validm,
+                   const double* T, float* depth_out, float* model_out) {
+  OrcSeed s0{0, -1, -1, 0.0};
+  Ctx X{*c, s0};
+  const int W2 = c->width / 4, H2 = c->height / 4, W3 = c->width / 8, H3 = c->height / 8;
+  std::vector<double> d2(D2, D2 + size_t(W2) * H2);
+  std::vector<double> d3 = pyrdown(X, d2, W2, H2);
+  const M4<double> P = load_pose<double>(T);
+  const int n3 = W3 * H3;
+  for (int y = 0; y < H3; ++y)
+    for (int x = 0; x < W3; ++x) {
+      const int o = y * W3 + x;
+      depth_out[o] = float(d3[size_t(y) * (W2 / 2) + x]);
+      const size_t q = size_t(8 * y) * c->width + 8 * x;
+      float z = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
+      if (validm[q]) {
+        const double n0 = Nm[q * 3 + 0], n1 = Nm[q * 3 + 1], n2 = Nm[q * 3 + 2];
+        z = float(Zm[q]);
+        nx = float(P(0, 0) * n0 + P(1, 0) * n1 + P(2, 0) * n2);   // R^T n
+        ny = float(P(0, 1) * n0 + P(1, 1) * n1 + P(2, 1) * n2);
+        nz = float(P(0, 2) * n0 + P(1, 2) * n1 + P(2, 2) * n2);
+      }
+      model_out[o] = z;
+      model_out[n3 + o] = nx;
+      model_out[2 * n3 + o] = ny;
+      model_out[3 * n3 + o] = nz;
+    }
+}
+
 // The index map of the surfels (real positions sv [count][3][nc], confidences
 // sc [count][nc]) at the real pose T, `sup` x the image resolution, over the
 // surfels with c >= c_min: idx_out [sup H][sup W], -1 where empty.

@@ -9,6 +9,10 @@
 #include "ctx.hpp"
 #include "combos.hpp"
 
+namespace xsc {
+void* cnn_stream(const xslam_cnn_s* h);   // cnn.hip
+}
+
 namespace xs {
 constexpr int kMaxDirsApi = 16;
 #define XS_DECL(T, D, Q, NAME)                                                      \
@@ -280,6 +284,10 @@ int xslam_kernel_times(xslam_ctx ctx, double ms_out[8], int64_t launches_out[8])
 
 int xslam_ctx_set_cnn(xslam_ctx ctx, xslam_cnn cnn) {
   XS_CTX_CHECK(ctx);
+  if (cnn && xsc::cnn_stream(cnn) != static_cast<void*>(ctx->stream)) {
+    ctx->err = "set_cnn: the network was created on another stream than the context";
+    return XSLAM_ERR_ARG;
+  }
   return ctx->eng->set_cnn(cnn);
 }
 

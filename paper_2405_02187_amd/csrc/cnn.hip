@@ -559,6 +559,13 @@ struct xslam_cnn_s {
   xsc::Cnn c;
 };
 
+namespace xsc {
+// the stream a network handle launches on (a context may only use a network
+// created on its own stream: the forward then joins the context's order and
+// its graph capture)
+void* cnn_stream(const xslam_cnn_s* h) { return h ? static_cast<void*>(h->c.stream) : nullptr; }
+}  // namespace xsc
+
 using namespace xsc;
 
 extern "C" {

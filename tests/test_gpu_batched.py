@@ -54,6 +54,30 @@ def test_batched_directions_equal_single_runs_fp64():
         assert e <= 1e-13 and ef <= 1e-13
 
 
+def test_batched_directions_match_oracle_fp64():
+    """Six directions in one FP64 launch against the oracle's complex-step run
+    of each direction (its own seed), 4 frames of the 128^3 sequence: real
+    parts of the poses within 1e-12, every tangent within 1e-10, the volume's
+    tangent planes within 1e-10."""
+    p = sg.preset("c0")
+    n = 4
+    seq = sg.make_sequence(p, n_frames=n)
+    depths = seq.depths()
+    T0 = seq.poses_gt[0]
+    params = [X.P_PHI_X, X.P_PHI_Y, X.P_RHO_Z, X.P_TRUNC, X.P_FX, X.P_CY]
+    P6, F6 = run(p, depths, T0, X.C128, [(q, H20) for q in params])
+    c = O.config(p)
+    d64 = depths[:n].astype(np.float64)
+    for d, q in enumerate(params):
+        r = O.run_sequence(c, O.seed(1, q, h=H20), d64, T0, want_volume=True)
+        Pr = np.moveaxis(r["poses"], -1, 1)                     # (n, 2, 4, 4)
+        e_re = relerr(P6[:, 0], Pr[:, 0])
+        e_tan = relerr(P6[:, 1 + d], Pr[:, 1])
+        e_f = relerr(F6[1 + d], r["F"][:, 1])
+        log("batched direction", q, "vs oracle: pose", e_re, "tangent", e_tan, "F tangent", e_f)
+        assert e_re <= 1e-12 and e_tan <= 1e-10 and e_f <= 1e-10
+
+
 def test_batched_16_directions_fp32_equal_single_runs():
     p = sg.preset("c0")
     seq = sg.make_sequence(p, n_frames=6)

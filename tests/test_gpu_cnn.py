@@ -110,3 +110,57 @@ def test_training_reduces_loss():
     log("cnn training loss", losses[0], losses[-1])
     assert losses[-1] < 0.2 * losses[0]
     net.close()
+
+
+def test_network_on_another_stream_is_refused():
+    """A context only takes a network created on its own stream (its forward
+    then runs in the context's order and inside its frame graph)."""
+    import scenegen as sg
+    from gpu_util import created_stream
+    p = sg.preset("c0")
+    net = X.Cnn(max_batch=1)                      # on torch's current stream
+    with created_stream():
+        cfg = X.config_from_preset(p, max_frames=2)
+        slam = X.Slam(cfg, X.Perturbation([]), np.eye(4))
+        with pytest.raises(X.XslamError):
+            slam.set_cnn(net)
+        net2 = X.Cnn(max_batch=1)                 # on the context's stream
+        slam.set_cnn(net2)
+        slam.set_cnn(None)
+        net2.close()
+        slam.close()
+    net.close()
+
+
+def test_network_input_parts_match_oracle():
+    """xslam_cnn_parts (level-3 depth by the pyramid's gated binomial; model
+    depth and camera-frame normals at (8x, 8y)) against the oracle fed with the
+    context's own measured depth, model maps and pose: FP64 context, 640x480."""
+    import oracle as O
+    import scenegen as sg
+    from gpu_util import created_stream, torch_dev
+    p = sg.preset("c1")
+    seq = sg.make_sequence(p, n_frames=2)
+    d = seq.depths().astype(np.float64)
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=2, dim=(128, 128, 128), voxel=0.04)
+        slam = X.Slam(cfg, X.Perturbation([]), seq.poses_gt[0])
+        dev = torch_dev(d, np.float64)
+        for k in range(2):
+            slam.step(dev[k])
+        gd, gm = slam.cnn_parts()
+        gd, gm = gd.cpu().numpy()[0], gm.cpu().numpy()
+        W, H = cfg.cam.width, cfg.cam.height
+        Dall = slam.get(X.F_MEAS_DEPTH)
+        off = W * H + (W // 2) * (H // 2)
+        D2 = Dall[off:off + (W // 4) * (H // 4)].reshape(H // 4, W // 4)
+        Nm = slam.get(X.F_NMAP).reshape(3, 1, H, W)[:, 0].transpose(1, 2, 0)
+        Zm = slam.get(X.F_ZMAP).reshape(H, W)
+        Vm = slam.get(X.F_MVALID).reshape(H, W)
+        T = slam.get(X.F_POSE)[0]
+        slam.close()
+    od, om = O.cnn_parts(O.config(p, dim=(128, 128, 128), voxel=0.04), D2, Nm, Zm, Vm, T)
+    ed, em = np.abs(gd - od).max(), np.abs(gm - om).max()
+    log("cnn parts vs oracle: depth", ed, "model", em, "valid model pixels", int((om[0] > 0).sum()))
+    assert (om[0] > 0).sum() > 1000
+    assert ed <= 1e-6 and em <= 1e-6
