@@ -122,3 +122,38 @@ def test_surfel_checkpoint_resume_bit_exact():
     assert np.array_equal(P, ref["P"])
     for k in ("v", "n", "r", "c", "t"):
         assert np.array_equal(S2[k], ref["S"][k])
+
+
+def test_surfel_capacity_and_lost_frame_match_oracle():
+    """A capacity the sequence overflows (insertions past it dropped, in pixel
+    order) and a frame with no depth (tracking lost: no update, the model maps
+    predicted at the previous pose): counts, poses and surfels equal the
+    oracle's (FP64)."""
+    p = sg.preset("c0")
+    seq = sg.make_sequence(p, n_frames=4)
+    d = seq.depths().astype(np.float64)
+    d[2] = 0.0                                                    # frame 2: no depth
+    T0 = seq.poses_gt[0]
+    cap = 12000
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=8, map=X.MAP_SURFEL, surf_capacity=cap)
+        slam = X.Slam(cfg, X.Perturbation([]), T0)
+        dev = torch_dev(d, np.float64)
+        for k in range(4):
+            slam.step(dev[k])
+        cnt, P, S = slam.get(X.F_COUNTERS), slam.get(X.F_POSES), slam.surfels()
+        slam.close()
+    c = O.config(p, pf_capacity=cap)
+    r = O.pf_run_sequence(c, O.seed(0), d, T0)
+    log("capacity / lost: gpu", cnt[:, [0, 1, 35, 36, 37]].tolist(), "oracle", r["stats"][:, 0].tolist(),
+        r["pf"].tolist())
+    assert cnt[2, 0] == 1 and r["stats"][2, 0] == 1
+    assert np.array_equal(cnt[:, 0], r["stats"][:, 0].astype(int))
+    assert np.array_equal(cnt[:, 1], r["pf"][:, 0])
+    assert np.array_equal(cnt[:, 35], r["pf"][:, 1])
+    assert np.array_equal(cnt[:, 36], r["pf"][:, 2])
+    assert r["pf"][:, 2].sum() > 0 and cnt[-1, 37] == cap == len(S["t"])
+    assert relerr(P[:, 0], np.moveaxis(r["poses"], -1, 1)[:, 0]) <= 1e-10
+    assert np.array_equal(S["t"], r["surfels"]["t"])
+    for k in ("v", "n", "r", "c"):
+        assert relerr(S[k], r["surfels"][k]) <= 1e-10
