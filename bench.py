@@ -273,15 +273,23 @@ def forms(X, torch, sg, p1, dev1, T0, n_warm=5, n_timed=30, multi_cap=None, shap
     t0 = time.perf_counter()
     insts = M.make_instances(sg.instance_presets(24), frame_cap=multi_cap)
     log(f"multi-instance inputs in {time.perf_counter() - t0:.1f}s")
-    res = M.run_batch(insts, n_streams=8)
-    lost = int(sum(s.get(X.F_COUNTERS)[:, 0].sum() for s in res["slams"]))
-    for s_ in res["slams"]:
-        s_.close()
-    out["multi_instance_24"] = dict(value=res["value"], unit="frames·directions/s", frames=res["frames"],
-                                    frames_x_directions=res["frames_x_dirs"], wall_s=res["wall_s"],
-                                    streams=res["streams"], latency_ms=res["latency_ms"], lost_frames=lost,
-                                    workload="24 sequences: 128^3-384^3 TSDF at 1-2 cm, 320x240 or 640x480, "
-                                             "60-400 frames, 1-6 directions each, FP32-complex")
+    wl = ("24 sequences: 128^3-384^3 TSDF at 1-2 cm, 320x240 or 640x480, 60-400 frames, 1-6 directions each, "
+          "FP32-complex")
+    # streams: every context on one of 8 streams, launching its own frames;
+    # grouped: contexts of one shape stepped by grouped launches (one stream
+    # per shape), workgroups per item or a persistent grid
+    for key, kw in (("multi_instance_24", dict(n_streams=8)),
+                    ("multi_instance_24_grouped", dict(grouped=True)),
+                    ("multi_instance_24_grouped_persistent", dict(grouped=True, persist=2048))):
+        res = M.run_batch(insts, **kw)
+        lost = int(sum(s.get(X.F_COUNTERS)[:, 0].sum() for s in res["slams"]))
+        for s_ in res["slams"]:
+            s_.close()
+        out[key] = dict(value=res["value"], unit="frames·directions/s", frames=res["frames"],
+                        frames_x_directions=res["frames_x_dirs"], wall_s=res["wall_s"], mode=res["mode"],
+                        streams=res["streams"], persist=res["persist"], latency_ms=res["latency_ms"],
+                        lost_frames=lost, workload=wl)
+        log(f"{key}: {res['value']:.0f} frames·directions/s, latency {res['latency_ms']}")
     del insts
     return out
 

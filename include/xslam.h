@@ -353,6 +353,29 @@ int xslam_autotune(xslam_ctx ctx, int32_t reps, xslam_launch* best, double* ms_o
  * is in xslam_batch_last_index. */
 typedef struct xslam_batch_s* xslam_batch;
 int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out);
+/* The same batch advanced by grouped launches: contexts of one shape
+ * (precision, directions, Hessian size) created on one stream form a group
+ * (at most 32 per group, in context order) and are stepped together, one
+ * launch per stage of the tracked frame for all of them; groups on different
+ * streams overlap.  Each context contributes a descriptor (its own launch
+ * arguments) and its own grid of work items (pixel tiles, bricks, ICP
+ * workgroups); the grouped kernels' workgroups take the concatenated
+ * (context, item) list in a fixed stride and run each item as the context's
+ * own launch would, so every context's results equal its solo run bit for
+ * bit.  The work of a group is captured into a graph and replayed until the
+ * set of stepping contexts changes; a context's frame 0 runs its own step.
+ * persist: workgroups per grouped launch, a multiple of 8 (0: one per work
+ * item).  Requirements: the TSDF map, icp.solver 0, no network initialiser
+ * attached, kernel timing off.  The raycast tile of a group is that of its
+ * first context.  The library
+ * allocates the groups' descriptor tables (device memory, freed by
+ * xslam_batch_destroy).  Latency (xslam_batch_latency) is that of the
+ * context's group's step: from its first launch to its last.  Errors:
+ * XSLAM_ERR_ARG (as above, a persist that is negative or not a multiple of 8,
+ * contexts on different devices),
+ * XSLAM_ERR_UNSUPPORTED (surfel map or Newton solver; the context's error
+ * text names it), XSLAM_ERR_HIP. */
+int xslam_batch_create_grouped(const xslam_ctx* ctxs, int32_t n, int32_t persist, xslam_batch* out);
 /* depths[i] / depth_dots[i]: the frame of context i (device pointers, layout
  * as in xslam_step; depth_dots may be NULL); active (optional, n flags):
  * contexts with 0 are skipped (finished sequences). */

@@ -53,7 +53,7 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
         units.append((os.path.join(CSRC, "inst.hip"), os.path.join(BUILD, f"inst_{name}.o"),
                       [f"-DXS_T={T}", f"-DXS_D={D}", f"-DXS_Q={Q}", f"-DXS_NAME={name}"]))
     hdr = os.path.join(HERE, "..", "include", "xslam.h")
-    eng = [os.path.join(CSRC, f) for f in ("jet.hpp", "common.hpp", "kernels.hpp", "newton.hpp", "reloc.hpp", "surfel.hpp", "engine.hpp", "ctx.hpp",
+    eng = [os.path.join(CSRC, f) for f in ("jet.hpp", "common.hpp", "kernels.hpp", "newton.hpp", "reloc.hpp", "surfel.hpp", "group.hpp", "engine.hpp", "ctx.hpp",
                                            "inst.hip")] + [hdr]
     deps = {"api.cpp": eng + [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "combos.hpp")],
             "inst.hip": eng, "cnn.hip": [os.path.join(CSRC, "cnn.hip"), hdr]}

@@ -338,6 +338,9 @@ struct xslam_batch_s {
   std::vector<hipEvent_t> e0, e1;
   std::vector<char> ran;
   int32_t last_index = -1;
+  // grouped batches: the groups and, per group, its members' context indices
+  std::vector<xs::GroupBase*> groups;
+  std::vector<std::vector<int>> members;
 };
 
 int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out) {
@@ -365,10 +368,82 @@ int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out) {
   return XSLAM_OK;
 }
 
+int xslam_batch_create_grouped(const xslam_ctx* ctxs, int32_t n, int32_t persist, xslam_batch* out) {
+  if (!ctxs || n < 1 || !out || persist < 0 || persist % xs::kGroupAlign) return XSLAM_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !ctxs[i]->eng) return XSLAM_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return XSLAM_ERR_ARG;
+  }
+  for (int i = 0; i < n; ++i) {
+    const xslam_config& c = ctxs[i]->cfg;
+    if (c.map != XSLAM_MAP_TSDF || c.icp.solver != 0) {
+      ctxs[i]->err = "grouped batch: needs the TSDF map and the Gauss-Newton solver";
+      return XSLAM_ERR_UNSUPPORTED;
+    }
+    if (ctxs[i]->device != ctxs[0]->device) {
+      ctxs[i]->err = "grouped batch: contexts on different devices";
+      return XSLAM_ERR_ARG;
+    }
+  }
+  auto* b = new xslam_batch_s;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->ran.assign(n, 0);
+  // members by shape and stream, in context order, at most kGroupMax per group
+  std::vector<char> taken(n, 0);
+  int rc = XSLAM_OK;
+  for (int i = 0; i < n && !rc; ++i) {
+    if (taken[i]) continue;
+    std::vector<int> mem;
+    for (int j = i; j < n && int(mem.size()) < xs::kGroupMax; ++j)
+      if (!taken[j] && ctxs[j]->eng->shape_key() == ctxs[i]->eng->shape_key() && ctxs[j]->stream == ctxs[i]->stream) {
+        mem.push_back(j);
+        taken[j] = 1;
+      }
+    std::vector<xs::EngineBase*> es;
+    for (int j : mem) es.push_back(ctxs[j]->eng);
+    hipSetDevice(ctxs[i]->device);
+    xs::GroupBase* g = ctxs[i]->eng->new_group(es.data(), int(es.size()), ctxs[i]->stream, persist);
+    if (!g) { rc = XSLAM_ERR_HIP; break; }
+    b->groups.push_back(g);
+    b->members.push_back(mem);
+  }
+  if (rc) {
+    for (auto g : b->groups) delete g;
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return XSLAM_OK;
+}
+
+static int batch_step_grouped(xslam_batch b, const void* const* depths, const void* const* depth_dots,
+                              const int32_t* active) {
+  for (size_t k = 0; k < b->groups.size(); ++k) {
+    const std::vector<int>& mem = b->members[k];
+    std::vector<const void*> d(mem.size()), dd(mem.size());
+    std::vector<int32_t> act(mem.size());
+    for (size_t q = 0; q < mem.size(); ++q) {
+      d[q] = depths[mem[q]];
+      dd[q] = depth_dots ? depth_dots[mem[q]] : nullptr;
+      act[q] = active ? active[mem[q]] : 1;
+    }
+    const int rc = b->groups[k]->step(d.data(), dd.data(), act.data());
+    for (size_t q = 0; q < mem.size(); ++q) b->ran[mem[q]] = b->groups[k]->ran(int(q)) ? 1 : 0;
+    if (rc) {
+      const int f = b->groups[k]->failed_member();
+      b->last_index = f >= 0 ? mem[f] : mem[0];
+      return rc;
+    }
+  }
+  return XSLAM_OK;
+}
+
 int xslam_batch_step(xslam_batch b, const void* const* depths, const void* const* depth_dots,
                      const int32_t* active) {
   if (!b || !depths) return XSLAM_ERR_ARG;
   b->last_index = -1;
+  if (!b->groups.empty()) return batch_step_grouped(b, depths, depth_dots, active);
   const int n = int(b->ctx.size());
   for (int i = 0; i < n; ++i) {
     b->ran[i] = 0;
@@ -388,6 +463,13 @@ int xslam_batch_step(xslam_batch b, const void* const* depths, const void* const
 
 int xslam_batch_latency(xslam_batch b, float* ms_out) {
   if (!b || !ms_out) return XSLAM_ERR_ARG;
+  if (!b->groups.empty()) {
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      const float ms = b->groups[k]->last_ms();
+      for (int i : b->members[k]) ms_out[i] = b->ran[i] ? ms : -1.f;
+    }
+    return XSLAM_OK;
+  }
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     ms_out[i] = -1.f;
     if (!b->ran[i]) continue;
@@ -401,7 +483,8 @@ int32_t xslam_batch_last_index(xslam_batch b) { return b ? b->last_index : -1; }
 
 int xslam_batch_destroy(xslam_batch b) {
   if (!b) return XSLAM_ERR_ARG;
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
+  for (auto g : b->groups) delete g;   // (waits for the group's stream)
+  for (size_t i = 0; i < b->e0.size(); ++i) {
     if (b->ran[i]) hipEventSynchronize(b->e1[i]);
     hipEventDestroy(b->e0[i]);
     hipEventDestroy(b->e1[i]);

@@ -22,8 +22,31 @@ inline thread_local hipEvent_t tl_ev1 = nullptr;
       hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                                  \
   } while (0)
 
+// Contexts per group of a grouped batch, and the multiple a grouped launch's
+// workgroup count keeps (the XCD count: an item stays on the XCD its solo
+// launch would give it).
+constexpr int kGroupMax = 32;
+constexpr int kGroupAlign = 8;
+
+// Several contexts of one shape stepped by grouped launches (group.hpp).
+// step: one frame of each member with active[m] != 0 (member order);
+// failed_member: the member whose check failed after a non-zero return.
+struct GroupBase {
+  virtual ~GroupBase() {}
+  virtual int step(const void* const* depths, const void* const* ddots, const int32_t* active) = 0;
+  virtual int failed_member() const = 0;
+  // device time of the group's last step (ms), -1 if it did nothing
+  virtual float last_ms() = 0;
+  virtual bool ran(int member) const = 0;
+};
+
 struct EngineBase {
   virtual ~EngineBase() {}
+  // equal for engines of one (precision, directions, Hessian) shape
+  virtual int shape_key() const = 0;
+  // a group runner for n engines of this engine's shape (es[0] is this one),
+  // launching on stream; persist: workgroups of a grouped launch (0: one per item)
+  virtual GroupBase* new_group(EngineBase* const* es, int n, hipStream_t stream, int persist) = 0;
   virtual int measure(const void* depth, const void* ddot) = 0;
   virtual int integrate(const double* pose) = 0;
   virtual int raycast(const double* pose, void* vmap, void* nmap) = 0;

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <cmath>
+#include <functional>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -12,6 +13,7 @@
 #include "newton.hpp"
 #include "reloc.hpp"
 #include "surfel.hpp"
+#include "group.hpp"
 
 namespace xs {
 
@@ -349,24 +351,18 @@ struct Engine : EngineBase {
 
   // begin_track: the bilateral launch also starts the tracking of the frame
   // (k_track_begin's work, folded into the first launch of a tracked frame)
-  int run_measure(bool begin_track = false) {
-    int rc;
-    dim3 b(16, 16);
-    dim3 g0((W[0] + 15) / 16, (H[0] + 15) / 16);
-    TrackBegin<T, D, Q> tb{};
-    if (begin_track) tb = track_begin_args();
-    if ((rc = launch(0, "bilateral", [&] {
-           XS_LAUNCH((k_bilateral<T, D, Q>), g0, b, 0, C->stream, kp, raw, rawdot, Dl[0], Dhi[0], tb);
-         })))
-      return rc;
-    for (int l = 1; l < 3; ++l) {
-      dim3 g((W[l] + 15) / 16, (H[l] + 15) / 16);
-      if ((rc = launch(0, "pyrdown", [&] {
-             XS_LAUNCH((k_pyrdown<T, D, Q>), g, b, 0, C->stream, kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l],
-                                Dhi[l - 1], Dhi[l]);
-           })))
-        return rc;
-    }
+  // ---- stage descriptors: the arguments of each frame-step launch (the
+  // solo launches below and the grouped ones take the same)
+  GBilateral<T, D, Q> d_bilateral(bool begin_track) const {
+    GBilateral<T, D, Q> a{kp, raw, rawdot, Dl[0], Dhi[0], TrackBegin<T, D, Q>{}};
+    if (begin_track) a.tb = track_begin_args();
+    return a;
+  }
+  dim3 g_level(int l) const { return dim3((W[l] + 15) / 16, (H[l] + 15) / 16); }
+  GPyrdown<T, D, Q> d_pyrdown(int l) const {
+    return GPyrdown<T, D, Q>{kp, Dl[l - 1], W[l - 1], H[l - 1], Dl[l], Dhi[l - 1], Dhi[l]};
+  }
+  GVertexNormal<T, D, Q> d_vertex_normal() const {
     VNLevels<T> lv;
     lv.first[0] = 0;
     for (int l = 0; l < 3; ++l) {
@@ -375,8 +371,28 @@ struct Engine : EngineBase {
       lv.tiles_x[l] = (W[l] + 15) / 16;
       lv.first[l + 1] = lv.first[l] + lv.tiles_x[l] * ((H[l] + 15) / 16);
     }
+    return GVertexNormal<T, D, Q>{kp, lv};
+  }
+
+  int run_measure(bool begin_track = false) {
+    int rc;
+    const dim3 b(16, 16);
+    const auto a = d_bilateral(begin_track);
+    if ((rc = launch(0, "bilateral", [&] {
+           XS_LAUNCH((k_bilateral<T, D, Q>), g_level(0), b, 0, C->stream, a.kp, a.depth, a.ddot, a.Dout, a.Dhi, a.tb);
+         })))
+      return rc;
+    for (int l = 1; l < 3; ++l) {
+      const auto p = d_pyrdown(l);
+      if ((rc = launch(0, "pyrdown", [&] {
+             XS_LAUNCH((k_pyrdown<T, D, Q>), g_level(l), b, 0, C->stream, p.kp, p.Din, p.Wi, p.Hi, p.Dout, p.Dhi_in,
+                       p.Dhi_out);
+           })))
+        return rc;
+    }
+    const auto v = d_vertex_normal();
     if ((rc = launch(0, "vertex_normal", [&] {
-           XS_LAUNCH((k_vertex_normal<T, D, Q>), dim3(lv.first[3]), b, 0, C->stream, kp, lv);
+           XS_LAUNCH((k_vertex_normal<T, D, Q>), dim3(v.lv.first[3]), b, 0, C->stream, v.kp, v.lv);
          })))
       return rc;
     measured = true;
@@ -385,7 +401,7 @@ struct Engine : EngineBase {
 
   int32_t* host_counter_row() { return counters + size_t(kCounters) * std::min(frame, C->cfg.max_frames - 1); }
 
-  int run_icp_level(int l, int iter_slot, int do_solve, double* sums_out = nullptr) {
+  IcpArgs<T, D, Q> icp_args(int l, int iter_slot, int do_solve, double* sums_out = nullptr) const {
     IcpArgs<T, D, Q> a;
     a.V = Vl[l]; a.N = Nl[l]; a.valid = valid[l];
     a.Vm = Vm[l]; a.Nm = Nm[l]; a.Zm = Zm[l]; a.validm = mvalid[l];
@@ -393,8 +409,16 @@ struct Engine : EngineBase {
     a.Kcur = Kcur; a.Kprev = Kprev; a.Pcur = Pcur; a.omega = omega[l]; a.update = C->cfg.icp.update;
     a.partials = partials; a.lost = lost; a.counters = counters; a.sums_out = sums_out ? sums_out : sums;
     a.frame = dframe; a.max_frames = C->cfg.max_frames;
-    int blocks = icp_grid[l] > 0 ? icp_grid[l]
-                                 : int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+    return a;
+  }
+  int icp_blocks(int l) const {
+    return icp_grid[l] > 0 ? icp_grid[l]
+                           : int(std::min<size_t>((npx[l] + kIcpThreads - 1) / kIcpThreads, kMaxIcpBlocks));
+  }
+
+  int run_icp_level(int l, int iter_slot, int do_solve, double* sums_out = nullptr) {
+    const IcpArgs<T, D, Q> a = icp_args(l, iter_slot, do_solve, sums_out);
+    const int blocks = icp_blocks(l);
     if (C->cfg.icp.solver >= 1) {
       if constexpr (D == 0 && Q == 0) {
         int rc = launch(1, "icp_newton", [&] {
@@ -562,6 +586,9 @@ struct Engine : EngineBase {
     return rc;
   }
 
+  int shape_key() const override { return int(sizeof(T)) * 10000 + D * 100 + Q; }
+  GroupBase* new_group(EngineBase* const* es, int n, hipStream_t stream, int persist) override;
+
   int autotune(int reps, double* ms_out) override {
     if (!measured || !have_model) return fail(XSLAM_ERR_STATE, "autotune: needs a measured frame and model maps");
     if (reps < 1 || reps > 1000) return fail(XSLAM_ERR_ARG, "autotune: reps in [1, 1000]");
@@ -648,32 +675,53 @@ struct Engine : EngineBase {
   // fusion: per-tile depth bound, brick culling, list-driven update, brick
   // flags.  The brick count is reset by the end-of-tracking work, which the
   // first launch here does too (post_track(tracked, store) folded in).
-  int run_fuse(bool tracked, bool store) {
-    int rc;
+  dim3 g_tile_zmax() const {
     const int ntx = (W[0] + kTile - 1) / kTile, nty = (H[0] + kTile - 1) / kTile;
-    const int ncx = (ntx + kCell - 1) / kCell, ncy = (nty + kCell - 1) / kCell;
+    return dim3((ntx + kCell - 1) / kCell, (nty + kCell - 1) / kCell);
+  }
+  GTileZmax<T, D, Q> d_tile_zmax(bool tracked, bool store) const {
     const PostTrack<T, D, Q> post{Pcur, Pinit, Kcur, tracked ? lost : nullptr, store ? hist : nullptr,
                                   dframe, C->cfg.max_frames, bcount};
+    return GTileZmax<T, D, Q>{Dl[0], W[0], H[0], tzmax, czmax, post};
+  }
+  GBrickCull<T, D, Q> d_brick_cull() const {
+    return GBrickCull<T, D, Q>{kp, Kcur, tzmax, czmax, nbrick, blist, bcount, lost};
+  }
+  int fuse_blocks() const { return std::min(nbrick, fuse_grid); }
+  GFuse<T, D, Q> d_fuse() const {
+    return GFuse<T, D, Q>{kp, Kcur, Dl[0], rec, Ftan, Wtan, lost, nvox, blist, bcount, fcounts};
+  }
+  // (the brick flags' workgroup 0 also sums the fusion counts)
+  GBrickFlags<T> d_brick_flags() const {
+    return GBrickFlags<T>{rec, bflags, blist, bcount, nbrick, fcounts, fuse_blocks(), counters, dframe,
+                          C->cfg.max_frames};
+  }
+
+  int run_fuse(bool tracked, bool store) {
+    int rc;
+    const auto z = d_tile_zmax(tracked, store);
     if ((rc = launch(4, "tile_zmax", [&] {
-           XS_LAUNCH((k_tile_zmax<T, D, Q>), dim3(ncx, ncy), dim3(256), 0, C->stream, Dl[0], W[0], H[0],
-                              tzmax, czmax, post);
+           XS_LAUNCH((k_tile_zmax<T, D, Q>), g_tile_zmax(), dim3(256), 0, C->stream, z.D0, z.W, z.H, z.tmax, z.cmax,
+                     z.post);
          })))
       return rc;
+    const auto c = d_brick_cull();
     if ((rc = launch(7, "brick_cull", [&] {
-           XS_LAUNCH((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, kp, Kcur,
-                              tzmax, czmax, nbrick, blist, bcount, lost);
+           XS_LAUNCH((k_brick_cull<T, D, Q>), dim3((nbrick + 255) / 256), dim3(256), 0, C->stream, c.kp, c.Kk,
+                     c.tmax, c.cmax, c.nbrick, c.list, c.count, c.lost);
          })))
       return rc;
-    const int g = std::min(nbrick, fuse_grid);
+    const int g = fuse_blocks();
+    const auto f = d_fuse();
     if ((rc = launch(2, "fuse", [&] {
-           XS_LAUNCH((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, kp, Kcur, Dl[0], rec, Ftan,
-                              Wtan, lost, nvox, blist, bcount, fcounts);
+           XS_LAUNCH((k_fuse<T, D, Q>), dim3(g), dim3(kBrickVox), 0, C->stream, f.kp, f.Kk, f.Df, f.rec, f.Ftan,
+                     f.Wtan, f.lost, f.nvox, f.list, f.count, f.block_counts);
          })))
       return rc;
-    // (the brick flags' workgroup 0 also sums the fusion counts)
+    const auto bf = d_brick_flags();
     return launch(4, "brick_flags", [&] {
-      XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, blist, bcount, nbrick,
-                         fcounts, g, counters, dframe, C->cfg.max_frames);
+      XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, bf.rec, bf.flags, bf.list, bf.count,
+                bf.nbrick, bf.fcounts, bf.nf, bf.counter_base, bf.frame, bf.max_frames);
     });
   }
 
@@ -749,22 +797,37 @@ struct Engine : EngineBase {
 
   // end_frame: the counter sums also advance the frame index (the frame's
   // last launch)
-  int run_raycast(bool end_frame = false) {
+  // raycast tile grid for a tile of bx x by threads
+  dim3 g_ray(int bx, int by) const { return dim3((W[0] + bx - 1) / bx, (H[0] + by - 1) / by); }
+  GRaymarch<T, D, Q> d_raymarch() const { return GRaymarch<T, D, Q>{kp, Kcur, rec, bflags, bracket, rsamples}; }
+  GRayhit<T, D, Q> d_rayhit() const {
     MapsOut<T, D, Q> o;
     for (int l = 0; l < 3; ++l) { o.V[l] = Vm[l]; o.N[l] = Nm[l]; o.Z[l] = Zm[l]; o.valid[l] = mvalid[l]; }
-    dim3 b(ray_bx, ray_by), g((W[0] + ray_bx - 1) / ray_bx, (H[0] + ray_by - 1) / ray_by);
+    return GRayhit<T, D, Q>{kp, Kcur, rec, Ftan, nvox, bracket, o, rhits};
+  }
+  // the raycast's hit and sample counts; end_frame: also advance the frame index
+  GSumCounts<T> d_ray_sum(int nrb, bool end_frame) const {
+    return GSumCounts<T>{rhits, nrb, rsamples, nrb, counters, dframe, C->cfg.max_frames, 2, 31, nullptr, 0,
+                         end_frame ? dframe : nullptr};
+  }
+
+  int run_raycast(bool end_frame = false) {
+    const dim3 b(ray_bx, ray_by), g = g_ray(ray_bx, ray_by);
+    const auto m = d_raymarch();
     int rc = launch(3, "raymarch", [&] {
-      XS_LAUNCH((k_raymarch<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, bflags, bracket, rsamples);
+      XS_LAUNCH((k_raymarch<T, D, Q>), g, b, 0, C->stream, m.kp, m.Kk, m.rec, m.flags, m.bracket, m.block_samples);
     });
     if (rc) return rc;
+    const auto h = d_rayhit();
     rc = launch(6, "rayhit", [&] {
-      XS_LAUNCH((k_rayhit<T, D, Q>), g, b, 0, C->stream, kp, Kcur, rec, Ftan, nvox, bracket, o, rhits);
+      XS_LAUNCH((k_rayhit<T, D, Q>), g, b, 0, C->stream, h.kp, h.Kk, h.rec, h.Ftan, h.nvox, h.bracket, h.out,
+                h.block_hits);
     });
     if (rc) return rc;
-    const int nrb = int(g.x * g.y);
+    const auto s = d_ray_sum(int(g.x * g.y), end_frame);
     rc = launch(4, "sum_counts", [&] {
-      XS_LAUNCH(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, rhits, nrb, rsamples, nrb, counters,
-                         dframe, C->cfg.max_frames, 2, 31, nullptr, 0, end_frame ? dframe : nullptr);
+      XS_LAUNCH(k_sum_counts<T>, dim3(1), dim3(1024), 0, C->stream, s.a, s.n, s.b, s.nb, s.counter_base, s.frame,
+                s.max_frames, s.slot_a, s.slot_b, s.extra, s.slot_extra, s.advance);
     });
     if (!rc) have_model = true;
     return rc;
@@ -1234,6 +1297,276 @@ struct Engine : EngineBase {
     return xfer(false, field, const_cast<void*>(src), bytes);
   }
 };
+
+// ---------------------------------------------------------------------------
+// Grouped stepping of several contexts of one shape: the tracked-frame work of
+// every member in one grid per stage (group.hpp), captured into a graph that
+// is replayed until the set of stepping members changes.  A member's frame 0
+// runs its own step.  The members' ICP passes are taken level by level
+// (coarse first), pass by pass; a member with fewer iterations at a level
+// sits out the passes it does not have.
+template <typename T, int D, int Q>
+struct GroupRun : GroupBase {
+  using E = Engine<T, D, Q>;
+  std::vector<E*> e;
+  hipStream_t stream;
+  int persist;
+  int failed = -1;
+  std::vector<char> ran_;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  // the built plan: its members, descriptor tables, launches and graph
+  std::vector<int> built;
+  std::vector<char> htab;
+  char* dtab = nullptr;
+  size_t dcap = 0;
+  std::vector<std::function<void(const char*)>> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  GroupRun(EngineBase* const* es, int n, hipStream_t s, int p) : stream(s), persist(p) {
+    for (int i = 0; i < n; ++i) e.push_back(static_cast<E*>(es[i]));
+    ran_.assign(n, 0);
+  }
+  int init() {
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) return XSLAM_ERR_HIP;
+    return XSLAM_OK;
+  }
+  ~GroupRun() override {
+    hipStreamSynchronize(stream);
+    drop();
+    if (dtab) hipFree(dtab);
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+  }
+  void drop() {
+    if (gexec) { hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { hipGraphDestroy(graph); graph = nullptr; }
+    built.clear();
+  }
+  int fail_at(int m, int code, const std::string& msg) {
+    failed = m;
+    e[m]->C->err = msg;
+    return code;
+  }
+
+  // one grouped launch: the members' descriptors, their grids and the block
+  template <class A>
+  void stage(const std::vector<A>& d, const std::vector<dim3>& grids, dim3 block) {
+    const size_t off = align_up(htab.size());
+    htab.resize(off + d.size() * sizeof(A));
+    memcpy(htab.data() + off, d.data(), d.size() * sizeof(A));
+    GroupMap m{};
+    m.n = int(d.size());
+    int f = 0;
+    for (int i = 0; i < m.n; ++i) {
+      m.first[i] = f;
+      m.gx[i] = int(grids[i].x);
+      m.gy[i] = int(grids[i].y);
+      const int cnt = m.gx[i] * m.gy[i];
+      f += i + 1 < m.n ? (cnt + kGroupAlign - 1) / kGroupAlign * kGroupAlign : cnt;
+    }
+    m.first[m.n] = f;
+    m.total = f;
+    const int grid = persist > 0 ? std::min(f, persist) : f;
+    hipStream_t s = stream;
+    launches.push_back([m, grid, block, off, s](const char* base) {
+      hipLaunchKernelGGL(k_group<A>, dim3(grid), block, 0, s, reinterpret_cast<const A*>(base + off), m);
+    });
+  }
+
+  // the tracked-frame stages of the members mem (indices into e)
+  void plan(const std::vector<int>& mem) {
+    htab.clear();
+    launches.clear();
+    const size_t n = mem.size();
+    auto each = [&](auto f) {
+      using A = decltype(f(e[mem[0]]));
+      std::vector<A> v;
+      for (int m : mem) v.push_back(f(e[m]));
+      return v;
+    };
+    auto grids = [&](auto f) {
+      std::vector<dim3> v;
+      for (int m : mem) v.push_back(f(e[m]));
+      return v;
+    };
+    const dim3 b16(16, 16);
+    stage(each([](E* x) { return x->d_bilateral(true); }), grids([](E* x) { return x->g_level(0); }), b16);
+    for (int l = 1; l < 3; ++l)
+      stage(each([l](E* x) { return x->d_pyrdown(l); }), grids([l](E* x) { return x->g_level(l); }), b16);
+    stage(each([](E* x) { return x->d_vertex_normal(); }),
+          grids([](E* x) { return dim3(x->d_vertex_normal().lv.first[3]); }), b16);
+    std::vector<int> slot(n, 0);
+    for (int l = 2; l >= 0; --l) {
+      int most = 0;
+      for (int m : mem) most = std::max(most, e[m]->C->cfg.icp.iters[l]);
+      for (int it = 0; it < most; ++it) {
+        std::vector<GIcp<T, D, Q>> pi;
+        std::vector<GIcpFinish<T, D, Q>> pf;
+        std::vector<dim3> gi, gf;
+        for (size_t k = 0; k < n; ++k) {
+          E* x = e[mem[k]];
+          if (it >= x->C->cfg.icp.iters[l]) continue;
+          const IcpArgs<T, D, Q> a = x->icp_args(l, slot[k]++, 1);
+          pi.push_back(GIcp<T, D, Q>{x->kp, a});
+          pf.push_back(GIcpFinish<T, D, Q>{a, x->icp_blocks(l)});
+          gi.push_back(dim3(x->icp_blocks(l)));
+          gf.push_back(dim3(1));
+        }
+        stage(pi, gi, dim3(kIcpThreads));
+        stage(pf, gf, dim3(kFinishThreads<T, D, Q>));
+      }
+    }
+    stage(each([](E* x) { return x->d_tile_zmax(true, true); }), grids([](E* x) { return x->g_tile_zmax(); }),
+          dim3(256));
+    stage(each([](E* x) { return x->d_brick_cull(); }), grids([](E* x) { return dim3((x->nbrick + 255) / 256); }),
+          dim3(256));
+    stage(each([](E* x) { return x->d_fuse(); }), grids([](E* x) { return dim3(x->fuse_blocks()); }), dim3(kBrickVox));
+    stage(each([](E* x) { return x->d_brick_flags(); }), grids([](E* x) { return dim3(x->fuse_blocks()); }),
+          dim3(kBrickVox));
+    const int bx = e[mem[0]]->ray_bx, by = e[mem[0]]->ray_by;
+    stage(each([](E* x) { return x->d_raymarch(); }), grids([&](E* x) { return x->g_ray(bx, by); }), dim3(bx, by));
+    stage(each([](E* x) { return x->d_rayhit(); }), grids([&](E* x) { return x->g_ray(bx, by); }), dim3(bx, by));
+    stage(each([&](E* x) {
+            const dim3 g = x->g_ray(bx, by);
+            return x->d_ray_sum(int(g.x * g.y), true);
+          }),
+          grids([](E*) { return dim3(1); }), dim3(1024));
+  }
+
+  int build(const std::vector<int>& mem) {
+    drop();
+    plan(mem);
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail_at(mem[0], XSLAM_ERR_HIP, "group: stream");
+    if (htab.size() > dcap) {
+      if (dtab) hipFree(dtab);
+      dtab = nullptr;
+      dcap = 0;
+      if (hipMalloc(&dtab, htab.size()) != hipSuccess) {
+        hipGetLastError();
+        return fail_at(mem[0], XSLAM_ERR_HIP, "group: descriptor table allocation");
+      }
+      dcap = htab.size();
+    }
+    if (hipMemcpy(dtab, htab.data(), htab.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail_at(mem[0], XSLAM_ERR_HIP, "group: descriptor upload");
+    built = mem;
+    // capture; on failure the launches run eagerly
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+      for (auto& f : launches) f(dtab);
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(stream, &g) == hipSuccess && g) {
+        if (hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) == hipSuccess) {
+          graph = g;
+        } else {
+          gexec = nullptr;
+          hipGraphDestroy(g);
+        }
+      }
+    }
+    hipGetLastError();
+    return XSLAM_OK;
+  }
+
+  int failed_member() const override { return failed; }
+  bool ran(int m) const override { return ran_[m] != 0; }
+  float last_ms() override {
+    if (!timed) return -1.f;
+    float ms = -1.f;
+    if (hipEventSynchronize(ev1) != hipSuccess || hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) return -1.f;
+    return ms;
+  }
+
+  int step(const void* const* depths, const void* const* ddots, const int32_t* active) override {
+    failed = -1;
+    timed = false;
+    const int n = int(e.size());
+    std::vector<int> solo, grp;
+    for (int m = 0; m < n; ++m) {
+      ran_[m] = 0;
+      if (active && !active[m]) continue;
+      E* x = e[m];
+      if (!depths[m]) return fail_at(m, XSLAM_ERR_ARG, "depth is NULL");
+      if (x->C->timer.on) return fail_at(m, XSLAM_ERR_STATE, "group: kernel timing is on");
+      if (x->C->cfg.icp.init == 2 && x->cnn) return fail_at(m, XSLAM_ERR_UNSUPPORTED, "group: learned initialiser");
+      if (x->frame >= x->C->cfg.max_frames) return fail_at(m, XSLAM_ERR_STATE, "step: max_frames reached");
+      if (x->ndepth > 0 && !(ddots && ddots[m]))
+        return fail_at(m, XSLAM_ERR_ARG, "depth_dot required by a depth direction");
+      if (x->frame == 0) {
+        solo.push_back(m);
+      } else {
+        if (!x->have_model) return fail_at(m, XSLAM_ERR_STATE, "step: no model maps");
+        grp.push_back(m);
+      }
+    }
+    if (solo.empty() && grp.empty()) return XSLAM_OK;
+    hipEventRecord(ev0, stream);
+    for (int m : solo) {
+      const int rc = e[m]->step(depths[m], ddots ? ddots[m] : nullptr);
+      if (rc) { failed = m; return rc; }
+      ran_[m] = 1;
+    }
+    if (!grp.empty()) {
+      // the frames' inputs, one copy launch (entries that are not 16-byte
+      // aligned go through hipMemcpyAsync)
+      CopyMap cm{};
+      int64_t most = 0;
+      auto add = [&](const void* src, void* dst, int64_t bytes) -> int {
+        if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | uintptr_t(bytes)) & 15) {
+          return hipMemcpyAsync(dst, src, size_t(bytes), hipMemcpyDeviceToDevice, stream) == hipSuccess ? 0 : 1;
+        }
+        cm.src[cm.n] = src;
+        cm.dst[cm.n] = dst;
+        cm.bytes[cm.n] = bytes;
+        cm.n += 1;
+        most = std::max(most, bytes);
+        return 0;
+      };
+      for (int m : grp) {
+        E* x = e[m];
+        if (add(depths[m], x->raw, int64_t(x->npx[0] * sizeof(T))) ||
+            (x->ndepth > 0 && add(ddots[m], x->rawdot, int64_t(size_t(x->ndepth) * x->npx[0] * sizeof(T)))))
+          return fail_at(m, XSLAM_ERR_HIP, "group: input copy");
+      }
+      if (cm.n) {
+        const int gx = int(std::min<int64_t>(256, (most / 16 + 255) / 256));
+        hipLaunchKernelGGL(k_group_copy<T>, dim3(gx, cm.n), dim3(256), 0, stream, cm);
+      }
+      if (grp != built) {
+        const int rc = build(grp);
+        if (rc) return rc;
+      }
+      if (gexec) {
+        if (hipGraphLaunch(gexec, stream) != hipSuccess) {
+          hipGetLastError();
+          return fail_at(grp[0], XSLAM_ERR_HIP, "group: graph launch");
+        }
+      } else {
+        for (auto& f : launches) f(dtab);
+      }
+      if (hipGetLastError() != hipSuccess) return fail_at(grp[0], XSLAM_ERR_HIP, "group: launch");
+      for (int m : grp) {
+        e[m]->measured = true;
+        e[m]->frame += 1;
+        ran_[m] = 1;
+      }
+    }
+    hipEventRecord(ev1, stream);
+    timed = true;
+    return XSLAM_OK;
+  }
+};
+
+template <typename T, int D, int Q>
+GroupBase* Engine<T, D, Q>::new_group(EngineBase* const* es, int n, hipStream_t stream, int persist) {
+  auto* g = new GroupRun<T, D, Q>(es, n, stream, persist);
+  if (g->init()) {
+    delete g;
+    return nullptr;
+  }
+  return g;
+}
 
 template <typename T, int D, int Q>
 EngineBase* make_engine(xslam_ctx_s* ctx, const double T0[16], int* rc) {

@@ -27,6 +27,30 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
   return x * q + min(x, r) + k;
 }
 
+// The workgroup a kernel body works on: its position in the body's own grid
+// and that grid's size.  A plain launch passes the hardware ids; a grouped
+// launch (group.hpp) runs the bodies of several instances in one grid and
+// passes each workgroup's position in its instance's grid.
+// Pointers a body takes from a descriptor in memory: PtrSame leaves them as
+// they are (kernel arguments, known to be global); PtrGlobal states that they
+// address global memory, so that the accesses through them are global rather
+// than flat instructions.
+struct PtrSame {
+  template <class P> __device__ __forceinline__ P* operator()(P* p) const { return p; }
+};
+struct PtrGlobal {
+  template <class P> __device__ __forceinline__ P* operator()(P* p) const {
+    return (P*)(P __attribute__((address_space(1)))*)(uintptr_t)p;
+  }
+};
+
+struct VB {
+  int bx, by, gx, gy;
+  static __device__ __forceinline__ VB hw() {
+    return VB{int(blockIdx.x), int(blockIdx.y), int(gridDim.x), int(gridDim.y)};
+  }
+};
+
 // ---------------------------------------------------------------------------
 // A1. depth promotion (eq. "csfd_depth") and bilateral filter
 // ---------------------------------------------------------------------------
@@ -42,10 +66,10 @@ template <typename T, int D, int Q> __device__ void track_begin_work(const Track
 // (tb.lost != nullptr: workgroup 0 also starts the tracking of the frame,
 // which only the kernels after this one read; see k_track_begin)
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T* __restrict__ depth,
-                                                   const T* __restrict__ ddot, T* __restrict__ Dout,
-                                                   double* __restrict__ Dhi, TrackBegin<T, D, Q> tb) {
-  if (tb.lost && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) track_begin_work(tb);
+__device__ __forceinline__ void bilateral_body(const VB& vb, const KParams<T, D, Q>& kp, const T* __restrict__ depth,
+                                                             const T* __restrict__ ddot, T* __restrict__ Dout,
+                                                             double* __restrict__ Dhi, const TrackBegin<T, D, Q>& tb) {
+  if (tb.lost && vb.bx == 0 && vb.by == 0 && threadIdx.x == 0 && threadIdx.y == 0) track_begin_work(tb);
   // FP32 runs evaluate the real part in FP64 as well (Dhi) and store it rounded:
   // normals are differences of neighbouring vertices a few mm apart at metres of
   // depth, which FP32 accumulation would leave with ~1e-4 rad errors
@@ -55,7 +79,7 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
   __shared__ J tile[S * S];
   const int W = kp.W, H = kp.H, r = kp.bil_radius;
   const size_t n = size_t(W) * H;
-  const int x0 = blockIdx.x * kBilTile - kBilMaxR, y0 = blockIdx.y * kBilTile - kBilMaxR;
+  const int x0 = vb.bx * kBilTile - kBilMaxR, y0 = vb.by * kBilTile - kBilMaxR;
   const int tid = threadIdx.y * kBilTile + threadIdx.x;
   // the tile's raw depths and depth tangents, every load in flight together
   // (coordinates clamped to the image; entries outside it are zero), then
@@ -94,7 +118,7 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
     tile[q] = v;
   }
   __syncthreads();
-  const int x = blockIdx.x * kBilTile + threadIdx.x, y = blockIdx.y * kBilTile + threadIdx.y;
+  const int x = vb.bx * kBilTile + threadIdx.x, y = vb.by * kBilTile + threadIdx.y;
   if (x >= W || y >= H) return;
   const size_t i = size_t(y) * W + x;
   const J c = tile[(threadIdx.y + kBilMaxR) * S + threadIdx.x + kBilMaxR];
@@ -137,18 +161,24 @@ __global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T*
   }
   jstore(Dout, n, i, out);
 }
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_bilateral(KParams<T, D, Q> kp, const T* __restrict__ depth,
+                                                   const T* __restrict__ ddot, T* __restrict__ Dout,
+                                                   double* __restrict__ Dhi, TrackBegin<T, D, Q> tb) {
+  bilateral_body<T, D, Q>(VB::hw(), kp, depth, ddot, Dout, Dhi, tb);
+}
 
 // Coarser level (Sec. 4.1: "Gaussian smoothing", the perturbation smoothed
 // alike): 5x5 binomial (1,4,6,4,1)^2 centred on (2x,2y) over valid taps within
 // 3 s_m of the centre, renormalised; real weights.
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* __restrict__ Din, int Wi, int Hi,
-                                                 T* __restrict__ Dout, const double* __restrict__ Dhi_in,
-                                                 double* __restrict__ Dhi_out) {
+__device__ __forceinline__ void pyrdown_body(const VB& vb, const KParams<T, D, Q>& kp, const T* __restrict__ Din, int Wi, int Hi,
+                                                           T* __restrict__ Dout, const double* __restrict__ Dhi_in,
+                                                           double* __restrict__ Dhi_out) {
   using J = Jet<T, D, Q>;
   constexpr bool kHi = std::is_same<T, float>::value;   // FP32 runs: real part in FP64 as well
   const int Wo = Wi / 2, Ho = Hi / 2;
-  const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+  const int x = vb.bx * 16 + threadIdx.x, y = vb.by * 16 + threadIdx.y;
   if (x >= Wo || y >= Ho) return;
   const size_t ni = size_t(Wi) * Hi, no = size_t(Wo) * Ho, o = size_t(y) * Wo + x;
   // the real parts of the 25 taps, all in flight together (indexes clamped
@@ -210,6 +240,12 @@ __global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* _
   }
   jstore(Dout, no, o, out);
 }
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_pyrdown(KParams<T, D, Q> kp, const T* __restrict__ Din, int Wi, int Hi,
+                                                 T* __restrict__ Dout, const double* __restrict__ Dhi_in,
+                                                 double* __restrict__ Dhi_out) {
+  pyrdown_body<T, D, Q>(VB::hw(), kp, Din, Wi, Hi, Dout, Dhi_in, Dhi_out);
+}
 
 // ---------------------------------------------------------------------------
 // A2. vertex and normal maps (eqs. "vertex", "normal"), level l with K / 2^l.
@@ -232,13 +268,19 @@ __device__ __forceinline__ void vertex_normal_px(const KParams<T, D, Q>& kp, int
                                                  int Wl, int Hl, T* __restrict__ Vout, T* __restrict__ Nout,
                                                  uint8_t* __restrict__ valid, const double* __restrict__ Dhi,
                                                  int x, int y);
-template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, VNLevels<T> lv) {
-  const int b = blockIdx.x;
+template <typename T, int D, int Q, class PtrAs = PtrSame>
+__device__ __forceinline__ void vertex_normal_body(const VB& vb, const KParams<T, D, Q>& kp, const VNLevels<T>& lv,
+                                                   const PtrAs& as = PtrAs()) {
+  const int b = vb.bx;
   const int l = b < lv.first[1] ? 0 : (b < lv.first[2] ? 1 : 2);
   const int t = b - lv.first[l];
   const int x = (t % lv.tiles_x[l]) * 16 + threadIdx.x, y = (t / lv.tiles_x[l]) * 16 + threadIdx.y;
-  vertex_normal_px(kp, l, lv.D[l], lv.W[l], lv.H[l], lv.V[l], lv.N[l], lv.valid[l], lv.Dhi[l], x, y);
+  vertex_normal_px(kp, l, as(lv.D[l]), lv.W[l], lv.H[l], as(lv.V[l]), as(lv.N[l]), as(lv.valid[l]), as(lv.Dhi[l]), x,
+                   y);
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_vertex_normal(KParams<T, D, Q> kp, VNLevels<T> lv) {
+  vertex_normal_body<T, D, Q>(VB::hw(), kp, lv);
 }
 template <typename T, int D, int Q>
 __device__ __forceinline__ void vertex_normal_px(const KParams<T, D, Q>& kp, int level, const T* __restrict__ Dl,
@@ -851,7 +893,7 @@ __device__ void icp_finish_solve(const IcpArgs<T, D, Q>& g, const double* fin, i
 
 
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
+__device__ __forceinline__ void icp_body(const VB& vb, const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g) {
   using J = Jet<T, D, Q>;
   constexpr int NC = J::N;
   constexpr int NS = IcpSize<D, Q>::NS;
@@ -868,8 +910,8 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // each logical workgroup takes a contiguous run of pixels (a multiple of the
   // workgroup size); with the XCD remap every L2 sees one band of the image
-  const size_t chunk = (n + size_t(gridDim.x) * kIcpThreads - 1) / (size_t(gridDim.x) * kIcpThreads) * kIcpThreads;
-  const size_t p0 = size_t(xcd_remap(blockIdx.x, gridDim.x)) * chunk;
+  const size_t chunk = (n + size_t(vb.gx) * kIcpThreads - 1) / (size_t(vb.gx) * kIcpThreads) * kIcpThreads;
+  const size_t p0 = size_t(xcd_remap(vb.bx, vb.gx)) * chunk;
   const size_t p1 = p0 + chunk < n ? p0 + chunk : n;
 
   if constexpr (kRegAcc) {
@@ -1013,13 +1055,17 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
     if (lane == 0) { red[wv][27 * NC] = sc1; red[wv][27 * NC + 1] = sr2; }
   }
   __syncthreads();
-  double* part = g.partials + size_t(blockIdx.x) * NS;
+  double* part = g.partials + size_t(vb.bx) * NS;
   for (int k = threadIdx.x; k < NS; k += kIcpThreads) {
     double s = red[0][k];
 #pragma unroll
     for (int w = 1; w < kIcpThreads / 64; ++w) s += red[w][k];
     part[k] = s;
   }
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArgs<T, D, Q> g) {
+  icp_body<T, D, Q>(VB::hw(), kp, g);
 }
 
 // One workgroup after k_icp (a kernel boundary makes every partial visible to
@@ -1034,7 +1080,7 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 template <typename T, int D, int Q>
 constexpr int kFinishThreads = Jet<T, D, Q>::N > 8 ? 256 : 1024;
 template <typename T, int D, int Q>
-__global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
+__device__ __forceinline__ void icp_finish_body(const VB& vb, const IcpArgs<T, D, Q>& g, int nblocks) {
   constexpr int NS = IcpSize<D, Q>::NS;
   constexpr int NT = kFinishThreads<T, D, Q>;
   constexpr int G = 16, KC = 64, GPT = G * KC / NT;
@@ -1084,6 +1130,10 @@ __global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArg
   }
   if (threadIdx.x >= 64 || lost) return;
   icp_finish_solve<T, D, Q>(g, fin, threadIdx.x, xs, pre);
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__((kFinishThreads<T, D, Q>)) void k_icp_finish(IcpArgs<T, D, Q> g, int nblocks) {
+  icp_finish_body<T, D, Q>(VB::hw(), g, nblocks);
 }
 
 
@@ -1182,12 +1232,12 @@ __device__ void post_track_work(const PostTrack<T, D, Q>& a) {
 // (post.count != nullptr: workgroup 0 also does the end-of-tracking work, which
 // the kernels after this one read)
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax,
-                                                   T* __restrict__ cmax, PostTrack<T, D, Q> post) {
-  if (post.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) post_track_work(post);
+__device__ __forceinline__ void tile_zmax_body(const VB& vb, const T* __restrict__ D0, int W, int H, T* __restrict__ tmax,
+                                                             T* __restrict__ cmax, const PostTrack<T, D, Q>& post) {
+  if (post.count && vb.bx == 0 && vb.by == 0 && threadIdx.x == 0) post_track_work(post);
   const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
   const int tile = threadIdx.x >> 4, row = threadIdx.x & 15;
-  const int tx = blockIdx.x * kCell + (tile & 3), ty = blockIdx.y * kCell + (tile >> 2);
+  const int tx = vb.bx * kCell + (tile & 3), ty = vb.by * kCell + (tile >> 2);
   T m = 0;
   const int y = ty * kTile + row;
   if (tx < ntx && ty < nty && y < H) {
@@ -1211,8 +1261,13 @@ __global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int
   __syncthreads();
   if (threadIdx.x == 0) {
     const T a = wm[0] > wm[1] ? wm[0] : wm[1], b = wm[2] > wm[3] ? wm[2] : wm[3];
-    cmax[blockIdx.y * gridDim.x + blockIdx.x] = a > b ? a : b;
+    cmax[vb.by * vb.gx + vb.bx] = a > b ? a : b;
   }
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_tile_zmax(const T* __restrict__ D0, int W, int H, T* __restrict__ tmax,
+                                                   T* __restrict__ cmax, PostTrack<T, D, Q> post) {
+  tile_zmax_body<T, D, Q>(VB::hw(), D0, W, H, tmax, cmax, post);
 }
 
 // Whether brick b may hold a voxel that fusion at the pose P (real parts)
@@ -1270,11 +1325,11 @@ __device__ __forceinline__ bool brick_may_update(const KParams<T, D, Q>& kp, con
 
 // The bricks fusion at the current pose may update, appended to a list.
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                    const T* __restrict__ tmax, const T* __restrict__ cmax,
-                                                    int nbrick, int* __restrict__ list,
-                                                    int* __restrict__ count, const int* __restrict__ lost) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void brick_cull_body(const VB& vb, const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                              const T* __restrict__ tmax, const T* __restrict__ cmax,
+                                                              int nbrick, int* __restrict__ list,
+                                                              int* __restrict__ count, const int* __restrict__ lost) {
+  const int b = vb.bx * 256 + threadIdx.x;
   const bool keep = b < nbrick && !*lost && brick_may_update(kp, *Kk, tmax, cmax, b);
   // one list append per workgroup (ballots, then a prefix over the 4 waves)
   const unsigned long long bal = __ballot(keep);
@@ -1292,6 +1347,13 @@ __global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const K
   }
   __syncthreads();
   if (keep) list[bbase + wbase[wv] + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_brick_cull(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                    const T* __restrict__ tmax, const T* __restrict__ cmax,
+                                                    int nbrick, int* __restrict__ list,
+                                                    int* __restrict__ count, const int* __restrict__ lost) {
+  brick_cull_body<T, D, Q>(VB::hw(), kp, Kk, tmax, cmax, nbrick, list, count, lost);
 }
 
 template <typename T, int D, int Q>
@@ -1401,19 +1463,28 @@ __device__ __forceinline__ int fuse_brick(const KParams<T, D, Q>& kp, const KPos
 }
 
 template <typename T, int D, int Q>
+__device__ __forceinline__ void fuse_body(const VB& vb, const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                        const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
+                                                        T* __restrict__ Ftan, T* __restrict__ Wtan,
+                                                        const int* __restrict__ lost, int64_t nvox,
+                                                        const int* __restrict__ list, const int* __restrict__ count,
+                                                        int* __restrict__ block_counts) {
+  int total = 0;
+  if (!*lost) {
+    const int nact = *count;
+    for (int q = vb.bx; q < nact; q += vb.gx)
+      total += fuse_brick(kp, Kk, Df, rec, Ftan, Wtan, nvox, list[q]);
+  }
+  if (threadIdx.x == 0) block_counts[vb.bx] = total;   // summed by k_sum_counts, no atomics
+}
+template <typename T, int D, int Q>
 __global__ __launch_bounds__(kBrickVox) void k_fuse(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
                                                     const T* __restrict__ Df, typename Vec2<T>::type* __restrict__ rec,
                                                     T* __restrict__ Ftan, T* __restrict__ Wtan,
                                                     const int* __restrict__ lost, int64_t nvox,
                                                     const int* __restrict__ list, const int* __restrict__ count,
                                                     int* __restrict__ block_counts) {
-  int total = 0;
-  if (!*lost) {
-    const int nact = *count;
-    for (int q = blockIdx.x; q < nact; q += gridDim.x)
-      total += fuse_brick(kp, Kk, Df, rec, Ftan, Wtan, nvox, list[q]);
-  }
-  if (threadIdx.x == 0) block_counts[blockIdx.x] = total;   // summed by k_sum_counts, no atomics
+  fuse_body<T, D, Q>(VB::hw(), kp, Kk, Df, rec, Ftan, Wtan, lost, nvox, list, count, block_counts);
 }
 
 // counters[slot] = sum of n per-block counts (one block, fixed order)
@@ -1434,10 +1505,10 @@ __device__ __forceinline__ int block_sum_int(int v) {
 // order is exact); advance != nullptr also ends the frame (frame index + 1,
 // after every thread has read it).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, int n, const int* __restrict__ b, int nb,
-                                                     int32_t* __restrict__ counter_base, const int* frame,
-                                                     int max_frames, int slot_a, int slot_b, const int* __restrict__ extra,
-                                                     int slot_extra, int* advance) {
+__device__ __forceinline__ void sum_counts_body(const VB& vb, const int* __restrict__ a, int n, const int* __restrict__ b, int nb,
+                                                              int32_t* __restrict__ counter_base, const int* frame,
+                                                              int max_frames, int slot_a, int slot_b, const int* __restrict__ extra,
+                                                              int slot_extra, int* advance) {
   int32_t* counters = counter_row(counter_base, frame, max_frames);
   int sa = 0, sb = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sa += a[i];
@@ -1453,6 +1524,13 @@ __global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, 
     if (advance) *advance += 1;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, int n, const int* __restrict__ b, int nb,
+                                                     int32_t* __restrict__ counter_base, const int* frame,
+                                                     int max_frames, int slot_a, int slot_b, const int* __restrict__ extra,
+                                                     int slot_extra, int* advance) {
+  sum_counts_body<T>(VB::hw(), a, n, b, nb, counter_base, frame, max_frames, slot_a, slot_b, extra, slot_extra, advance);
+}
 
 // Per-brick summary for the raycast: bit 0 = some voxel observed (W > 0),
 // bit 1 = every voxel observed with F exactly 1 (free space).  Recomputed for
@@ -1460,13 +1538,13 @@ __global__ __launch_bounds__(1024) void k_sum_counts(const int* __restrict__ a, 
 // Workgroup 0 also sums the fusion's per-workgroup counts into the frame's
 // counter row (fcounts != nullptr): fused voxels and active bricks.
 template <typename T>
-__global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T>::type* __restrict__ rec,
-                                                           uint8_t* __restrict__ flags, const int* __restrict__ list,
-                                                           const int* __restrict__ count, int nbrick,
-                                                           const int* __restrict__ fcounts, int nf,
-                                                           int32_t* __restrict__ counter_base,
-                                                           const int* __restrict__ frame, int max_frames) {
-  if (fcounts && blockIdx.x == 0) {
+__device__ __forceinline__ void brick_flags_body(const VB& vb, const typename Vec2<T>::type* __restrict__ rec,
+                                                               uint8_t* __restrict__ flags, const int* __restrict__ list,
+                                                               const int* __restrict__ count, int nbrick,
+                                                               const int* __restrict__ fcounts, int nf,
+                                                               int32_t* __restrict__ counter_base,
+                                                               const int* __restrict__ frame, int max_frames) {
+  if (fcounts && vb.bx == 0) {
     int sf = 0;
     for (int i = threadIdx.x; i < nf; i += blockDim.x) sf += fcounts[i];
     sf = block_sum_int(sf);
@@ -1477,13 +1555,22 @@ __global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T
     }
   }
   const int nact = list ? *count : nbrick;
-  for (int q = blockIdx.x; q < nact; q += gridDim.x) {
+  for (int q = vb.bx; q < nact; q += vb.gx) {
     const int b = list ? list[q] : q;
     const auto r = rec[int64_t(b) * kBrickVox + threadIdx.x];
     const int obs = __syncthreads_or(r.y > T(0));
     const int fre = __syncthreads_and(r.y > T(0) && r.x == T(1));
     if (threadIdx.x == 0) flags[b] = uint8_t((obs ? 1 : 0) | (fre ? 2 : 0));
   }
+}
+template <typename T>
+__global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T>::type* __restrict__ rec,
+                                                           uint8_t* __restrict__ flags, const int* __restrict__ list,
+                                                           const int* __restrict__ count, int nbrick,
+                                                           const int* __restrict__ fcounts, int nf,
+                                                           int32_t* __restrict__ counter_base,
+                                                           const int* __restrict__ frame, int max_frames) {
+  brick_flags_body<T>(VB::hw(), rec, flags, list, count, nbrick, fcounts, nf, counter_base, frame, max_frames);
 }
 
 template <typename T, int D, int Q>
@@ -1643,13 +1730,13 @@ __device__ __forceinline__ bool tri_eval(const TriCell<T, D, Q>& t, Jet<T, D, Q>
 // arithmetic.  Real parts here are computed with the same operations as the
 // real parts of k_rayhit's jets.
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                  const typename Vec2<T>::type* __restrict__ rec,
-                                                  const uint8_t* __restrict__ flags,
-                                                  typename Vec2<T>::type* __restrict__ bracket,
-                                                  int* __restrict__ block_samples) {
-  const int tile = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int x = (tile % gridDim.x) * blockDim.x + threadIdx.x, y = (tile / gridDim.x) * blockDim.y + threadIdx.y;
+__device__ __forceinline__ void raymarch_body(const VB& vb, const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                            const typename Vec2<T>::type* __restrict__ rec,
+                                                            const uint8_t* __restrict__ flags,
+                                                            typename Vec2<T>::type* __restrict__ bracket,
+                                                            int* __restrict__ block_samples) {
+  const int tile = xcd_remap(vb.by * vb.gx + vb.bx, vb.gx * vb.gy);
+  const int x = (tile % vb.gx) * blockDim.x + threadIdx.x, y = (tile / vb.gx) * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   int nsamp = 0;
   if (x < W && y < H) {
@@ -1736,7 +1823,15 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
     bracket[size_t(y) * W + x] = b;
   }
   const int ns = block_sum_int(nsamp);
-  if (threadIdx.x == 0 && threadIdx.y == 0) block_samples[blockIdx.y * gridDim.x + blockIdx.x] = ns;
+  if (threadIdx.x == 0 && threadIdx.y == 0) block_samples[vb.by * vb.gx + vb.bx] = ns;
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                  const typename Vec2<T>::type* __restrict__ rec,
+                                                  const uint8_t* __restrict__ flags,
+                                                  typename Vec2<T>::type* __restrict__ bracket,
+                                                  int* __restrict__ block_samples) {
+  raymarch_body<T, D, Q>(VB::hw(), kp, Kk, rec, flags, bracket, block_samples);
 }
 
 // Complex-step evaluation of a bracketed crossing: alpha0 = alpha_m -
@@ -1744,14 +1839,14 @@ __global__ __launch_bounds__(256) void k_raymarch(KParams<T, D, Q> kp, const KPo
 // N = normalised central difference of F at +-1 voxel; writes the model maps
 // of levels 0-2.
 template <typename T, int D, int Q>
-__global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
-                                                const typename Vec2<T>::type* __restrict__ rec,
-                                                const T* __restrict__ Ftan, int64_t nvox,
-                                                const typename Vec2<T>::type* __restrict__ bracket,
-                                                MapsOut<T, D, Q> out, int* __restrict__ block_hits) {
+__device__ __forceinline__ void rayhit_body(const VB& vb, const KParams<T, D, Q>& kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                          const typename Vec2<T>::type* __restrict__ rec,
+                                                          const T* __restrict__ Ftan, int64_t nvox,
+                                                          const typename Vec2<T>::type* __restrict__ bracket,
+                                                          const MapsOut<T, D, Q>& out, int* __restrict__ block_hits) {
   using J = Jet<T, D, Q>;
-  const int tile = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int x = (tile % gridDim.x) * blockDim.x + threadIdx.x, y = (tile / gridDim.x) * blockDim.y + threadIdx.y;
+  const int tile = xcd_remap(vb.by * vb.gx + vb.bx, vb.gx * vb.gy);
+  const int x = (tile % vb.gx) * blockDim.x + threadIdx.x, y = (tile / vb.gx) * blockDim.y + threadIdx.y;
   const int W = kp.W, H = kp.H;
   const bool inside = x < W && y < H;
   bool ok = false;
@@ -1818,7 +1913,7 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
     }
   }
   const int nh = block_sum_int(ok ? 1 : 0);
-  if (threadIdx.x == 0 && threadIdx.y == 0) block_hits[blockIdx.y * gridDim.x + blockIdx.x] = nh;
+  if (threadIdx.x == 0 && threadIdx.y == 0) block_hits[vb.by * vb.gx + vb.bx] = nh;
   if (!inside) return;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
@@ -1830,6 +1925,14 @@ __global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose
     out.Z[l][il] = zhit;
     out.valid[l][il] = ok ? 1 : 0;
   }
+}
+template <typename T, int D, int Q>
+__global__ __launch_bounds__(256) void k_rayhit(KParams<T, D, Q> kp, const KPose<T, D, Q>* __restrict__ Kk,
+                                                const typename Vec2<T>::type* __restrict__ rec,
+                                                const T* __restrict__ Ftan, int64_t nvox,
+                                                const typename Vec2<T>::type* __restrict__ bracket,
+                                                MapsOut<T, D, Q> out, int* __restrict__ block_hits) {
+  rayhit_body<T, D, Q>(VB::hw(), kp, Kk, rec, Ftan, nvox, bracket, out, block_hits);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,11 +1,20 @@
 """Several independent CSFD sequences of uneven size advanced together.
 
-Each instance is its own context (volume, image size, directions) on its own
-HIP stream; a ``Batch`` enqueues one frame step of every unfinished instance
-per round, so the latency-bound ICP passes and small volumes of one instance
-overlap with the work of the others.  Throughput is the aggregate
-frames x directions over the wall time of the whole batch; latency is the
-device time of each frame step under that load (HIP events on its stream).
+Each instance is its own context (volume, image size, directions).  Two ways
+to step them, one frame of every unfinished instance per round:
+
+* streams: each context on its own HIP stream, its frame step launched by
+  itself, so the latency-bound ICP passes and small volumes of one instance
+  overlap with the work of the others;
+* grouped: contexts of one shape (number of directions) on one stream are
+  stepped by grouped launches, one grid per stage for all of them, each
+  context bringing its descriptor and its own grid of work items; a shape's
+  contexts are dealt to groups of at most group_size, each group on its own
+  stream, and the groups overlap.
+
+Throughput is the aggregate frames x directions over the wall time of the
+whole batch; latency is the device time of each frame step under that load
+(HIP events on its stream; grouped: the group's step).
 """
 from __future__ import annotations
 
@@ -46,16 +55,42 @@ def make_context(inst, stream=None):
         return X.Slam(cfg, pert, inst["T0"])
 
 
-def run_batch(instances, n_streams: int | None = None):
+def shape_of(inst):
+    return len(inst["preset"]["dirs"])
+
+
+def group_streams(instances, group_size: int):
+    """Stream index of every instance in grouped mode: each shape's instances
+    (in order) dealt round-robin to ceil(count / group_size) groups."""
+    out, nxt = [None] * len(instances), 0
+    for q in sorted({shape_of(inst) for inst in instances}):
+        idx = [i for i, inst in enumerate(instances) if shape_of(inst) == q]
+        ng = -(-len(idx) // group_size)
+        for k, i in enumerate(idx):
+            out[i] = nxt + k % ng
+        nxt += ng
+    return out
+
+
+def run_batch(instances, n_streams: int | None = None, grouped: bool = False, persist: int = 0,
+              group_size: int = 32):
     """All instances to the end of their sequences, together.  -> dict with
     aggregate frames*directions/s, per-frame latency percentiles and the
-    contexts (caller closes them)."""
+    contexts (caller closes them).  grouped: grouped launches, groups of at
+    most group_size instances of one shape, one stream per group (n_streams
+    is ignored)."""
     import torch
     n = len(instances)
-    n_streams = n if n_streams is None else n_streams
-    streams = [torch.cuda.Stream() for _ in range(n_streams)]
-    slams = [make_context(inst, streams[i % n_streams]) for i, inst in enumerate(instances)]
-    batch = X.Batch(slams)
+    if grouped:
+        gs = group_streams(instances, group_size)
+        streams = [torch.cuda.Stream() for _ in range(max(gs) + 1)]
+        slams = [make_context(inst, streams[g]) for inst, g in zip(instances, gs)]
+        n_streams = len(streams)
+    else:
+        n_streams = n if n_streams is None else n_streams
+        streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        slams = [make_context(inst, streams[i % n_streams]) for i, inst in enumerate(instances)]
+    batch = X.Batch(slams, grouped=grouped, persist=persist)
     lat = []
     n_max = max(inst["n"] for inst in instances)
     torch.cuda.synchronize()
@@ -76,6 +111,8 @@ def run_batch(instances, n_streams: int | None = None):
     batch.close()
     lat = np.array(lat)
     return dict(value=work / wall, frames=frames, frames_x_dirs=work, wall_s=wall, streams=n_streams,
+                mode="grouped" if grouped else "streams", persist=persist,
+                group_size=group_size if grouped else None,
                 latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
                                 sampled_rounds=int(len(lat))),
                 slams=slams)

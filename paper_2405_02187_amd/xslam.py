@@ -114,6 +114,7 @@ def lib():
             "xslam_frame_graph": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "xslam_autotune": (C.c_int, [vp, C.c_int32, C.POINTER(xslam_launch), dp]),
             "xslam_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, C.POINTER(vp)]),
+            "xslam_batch_create_grouped": (C.c_int, [C.POINTER(vp), C.c_int32, C.c_int32, C.POINTER(vp)]),
             "xslam_batch_step": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int32)]),
             "xslam_batch_latency": (C.c_int, [vp, C.POINTER(C.c_float)]),
             "xslam_batch_last_index": (C.c_int32, [vp]),
@@ -130,7 +131,7 @@ EXPORTS_CORE = ["xslam_components", "xslam_workspace_bytes", "xslam_create", "xs
            "xslam_raycast", "xslam_track", "xslam_step", "xslam_icp_pass", "xslam_icp_energy", "xslam_reloc_energy", "xslam_traj_err", "xslam_get",
            "xslam_set", "xslam_set_timing", "xslam_kernel_times", "xslam_sync", "xslam_last_error",
            "xslam_destroy", "xslam_ctx_set_cnn", "xslam_cnn_parts", "xslam_set_launch", "xslam_get_launch",
-           "xslam_autotune", "xslam_frame_graph", "xslam_batch_create", "xslam_batch_step", "xslam_batch_latency",
+           "xslam_autotune", "xslam_frame_graph", "xslam_batch_create", "xslam_batch_create_grouped", "xslam_batch_step", "xslam_batch_latency",
            "xslam_batch_last_index", "xslam_batch_destroy"]
 
 
@@ -517,16 +518,22 @@ def _cnn_lib():
 
 class Batch:
     """Independent contexts advanced together, one frame each per step (each on
-    the stream it was created with)."""
+    the stream it was created with).  grouped=True: contexts of one shape are
+    stepped by grouped launches (they must share a stream); persist is the
+    number of workgroups per grouped launch (0: one per work item)."""
 
-    def __init__(self, slams):
+    def __init__(self, slams, grouped: bool = False, persist: int = 0):
         self.slams = list(slams)
         n = len(self.slams)
         arr = (C.c_void_p * n)(*[s.h for s in self.slams])
         h = C.c_void_p()
-        rc = lib().xslam_batch_create(arr, n, C.byref(h))
+        if grouped:
+            rc = lib().xslam_batch_create_grouped(arr, n, persist, C.byref(h))
+        else:
+            rc = lib().xslam_batch_create(arr, n, C.byref(h))
         if rc != 0:
-            raise XslamError(f"xslam_batch_create: error {rc}")
+            msgs = "; ".join(lib().xslam_last_error(s.h).decode() for s in self.slams if lib().xslam_last_error(s.h))
+            raise XslamError(f"xslam_batch_create{'_grouped' if grouped else ''}: error {rc}: {msgs}")
         self.h = h
         self.n = n
 
