@@ -279,15 +279,16 @@ def forms(X, torch, sg, p1, dev1, T0, n_warm=5, n_timed=30, multi_cap=None, shap
     # grouped: contexts of one shape stepped by grouped launches (one stream
     # per shape), workgroups per item or a persistent grid
     for key, kw in (("multi_instance_24", dict(n_streams=8)),
-                    ("multi_instance_24_grouped", dict(grouped=True)),
-                    ("multi_instance_24_grouped_persistent", dict(grouped=True, persist=2048))):
+                    ("multi_instance_24_grouped", dict(grouped=True, group_size=4)),
+                    ("multi_instance_24_grouped_persistent", dict(grouped=True, group_size=4, persist=2048))):
         res = M.run_batch(insts, **kw)
         lost = int(sum(s.get(X.F_COUNTERS)[:, 0].sum() for s in res["slams"]))
         for s_ in res["slams"]:
             s_.close()
         out[key] = dict(value=res["value"], unit="frames·directions/s", frames=res["frames"],
                         frames_x_directions=res["frames_x_dirs"], wall_s=res["wall_s"], mode=res["mode"],
-                        streams=res["streams"], persist=res["persist"], latency_ms=res["latency_ms"],
+                        streams=res["streams"], persist=res["persist"], group_size=res["group_size"],
+                        latency_ms=res["latency_ms"],
                         lost_frames=lost, workload=wl)
         log(f"{key}: {res['value']:.0f} frames·directions/s, latency {res['latency_ms']}")
     del insts
