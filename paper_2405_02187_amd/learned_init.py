@@ -170,6 +170,7 @@ def main(argv=None):
     import torch
     import scenegen as sg
     ap = argparse.ArgumentParser()
+    ap.add_argument("--train-preset", default="c2", help="scene / volume preset of the training sequences")
     ap.add_argument("--train-seeds", type=int, default=16)
     ap.add_argument("--test-seeds", type=int, default=4)
     ap.add_argument("--frames", type=int, default=300)
@@ -184,7 +185,7 @@ def main(argv=None):
     ps = PairSet()
     lost_train = 0
     for i in range(a.train_seeds):
-        p, s, d = _sequence(sg, torch, "c2", 1000 + i, a.frames)
+        p, s, d = _sequence(sg, torch, a.train_preset, 1000 + i, a.frames)
         cfg = X.config_from_preset(p, prec=X.C64, max_frames=a.frames)
         poses, dp, mp, cnt = run_sequence_parts(cfg, d, s.poses_gt[0])
         # pairs only between frames that tracked (label quality): not lost and
@@ -193,6 +194,7 @@ def main(argv=None):
         ps.add(poses, dp, mp, a.max_step, ok)
         lost_train += int(cnt[:, 0].sum())
         print(f"train seed {1000 + i}: {int(ok.sum())}/{a.frames} frames usable, {len(ps)} pairs", flush=True)
+        del d
     ps.finalize()
     t_data = time.perf_counter() - t0
     net = X.Cnn(max_batch=a.batch)
@@ -211,7 +213,8 @@ def main(argv=None):
     t_train = time.perf_counter() - t1
     print(f"trained {a.steps} steps in {t_train:.1f}s: loss {np.mean(losses[:20]):.1f} -> {np.mean(losses[-20:]):.2f}",
           flush=True)
-    report = dict(pairs=len(ps), train_seeds=a.train_seeds, frames=a.frames, steps=a.steps, batch=a.batch,
+    report = dict(pairs=len(ps), train_preset=a.train_preset, train_seeds=a.train_seeds, frames=a.frames,
+                  lost_train_frames=lost_train, steps=a.steps, batch=a.batch,
                   loss_first=float(np.mean(losses[:20])), loss_last=float(np.mean(losses[-20:])),
                   train_s=t_train, data_s=t_data, samples_per_s=a.steps * a.batch / t_train, tests=[])
     for j in range(a.test_seeds):
@@ -230,6 +233,14 @@ def main(argv=None):
             print(f"test seed {2000 + j} step {fs}: cv {cv}  net {nn}", flush=True)
         del d
     net.close()
+    # per frame step: means over the held-out seeds
+    summary = {}
+    for fs in sorted({str(t["frame_step"]) for t in report["tests"]}):
+        ts = [t for t in report["tests"] if str(t["frame_step"]) == fs]
+        summary[fs] = {k: {m: float(np.mean([t[k][m] for t in ts])) for m in ts[0][k]}
+                       for k in ("constant_velocity", "network")}
+    report["summary"] = summary
+    print("summary over held-out seeds:", json.dumps(summary), flush=True)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(report, f, indent=1)
