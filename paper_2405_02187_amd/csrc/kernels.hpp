@@ -642,16 +642,11 @@ __device__ bool icp_solve(const double* sums, Jet<double, D, Q> dx[6], int lane,
 // parts, so the looked-up model point and normal do not move with the jet's
 // directions (the correspondences of a pass held fixed).
 template <bool kHold = false, typename J, typename KP, typename LD, typename T, int D, int Q>
-__device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g, const KP& Tc,
+__device__ __forceinline__ bool icp_pixel_from(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g, const KP& Tc,
                                                const KP& Tp, const J& fx, const J& fy, const J& cx, const J& cy,
-                                               size_t n, size_t i, J jac[6], J& r, LD&& ld) {
+                                               size_t n, uint32_t vi, const V3<J>& v, const V3<J>& nv, J jac[6], J& r,
+                                               LD&& ld) {
   const int W = g.W, H = g.H;
-  // the pixel's maps are loaded together with its flag (one memory round trip)
-  uint32_t vi = g.valid[i];
-  V3<J> v = ld(g.V, i), nv = ld(g.N, i);
-  pin(vi);
-  pin(v);
-  pin(nv);
   if (!vi) return false;
   const V3<J> p = pose_apply(Tc, v);
   const V3<J> nr = pose_rotate(Tc, nv);
@@ -741,6 +736,20 @@ __device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const
   const V3<J> pm = vcross(p, m);
   jac[0] = pm.x; jac[1] = pm.y; jac[2] = pm.z; jac[3] = m.x; jac[4] = m.y; jac[5] = m.z;
   return true;
+}
+
+// the pixel's maps are loaded together with its flag (one memory round trip),
+// then the rest of the pixel
+template <bool kHold = false, typename J, typename KP, typename LD, typename T, int D, int Q>
+__device__ __forceinline__ bool icp_pixel_with(const KParams<T, D, Q>& kp, const IcpArgs<T, D, Q>& g, const KP& Tc,
+                                               const KP& Tp, const J& fx, const J& fy, const J& cx, const J& cy,
+                                               size_t n, size_t i, J jac[6], J& r, LD&& ld) {
+  uint32_t vi = g.valid[i];
+  V3<J> v = ld(g.V, i), nv = ld(g.N, i);
+  pin(vi);
+  pin(v);
+  pin(nv);
+  return icp_pixel_from<kHold>(kp, g, Tc, Tp, fx, fy, cx, cy, n, vi, v, nv, jac, r, ld);
 }
 
 template <typename T, int D, int Q>
@@ -898,6 +907,7 @@ __device__ __forceinline__ void icp_body(const VB& vb, const KParams<T, D, Q>& k
   constexpr int NC = J::N;
   constexpr int NS = IcpSize<D, Q>::NS;
   constexpr bool kRegAcc = NS <= 192;
+  constexpr bool kPrefetch = NC <= 2;   // registers for the next pixel's maps
   __shared__ double red[kIcpThreads / 64][NS];
   // (no test of the lost flag here: after a lost pass the pose is left as it
   // was, these sums are computed from it and k_icp_finish drops them; a test
@@ -918,9 +928,7 @@ __device__ __forceinline__ void icp_body(const VB& vb, const KParams<T, D, Q>& k
     T acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0;
-    for (size_t i = p0 + threadIdx.x; i < p1; i += kIcpThreads) {
-      J jac[6], r;
-      if (!icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r)) continue;
+    auto accumulate = [&](const J (&jac)[6], const J& r) {
       int k = 0;
 #pragma unroll
       for (int a = 0; a < 6; ++a)
@@ -938,6 +946,44 @@ __device__ __forceinline__ void icp_body(const VB& vb, const KParams<T, D, Q>& k
       }
       acc[27 * NC] += T(1);
       acc[27 * NC + 1] += r.re() * r.re();
+    };
+    if constexpr (kPrefetch) {
+      // Each thread's pixels are taken one after the other; the maps of its
+      // next pixel are loaded before the current one's model taps, so that the
+      // two memory round trips of consecutive pixels overlap (the sums and
+      // their order are those of one pixel at a time).
+      auto ld = [&](const T* base, size_t idx) { return vload<J>(base, n, idx); };
+      size_t i = p0 + threadIdx.x;
+      uint32_t vi = 0;
+      V3<J> v{}, nv{};
+      if (i < p1) {
+        vi = g.valid[i];
+        v = ld(g.V, i);
+        nv = ld(g.N, i);
+      }
+      for (; i < p1; i += kIcpThreads) {
+        uint32_t vi2 = 0;
+        V3<J> v2 = v, nv2 = nv;
+        if (i + kIcpThreads < p1) {
+          vi2 = g.valid[i + kIcpThreads];
+          v2 = ld(g.V, i + kIcpThreads);
+          nv2 = ld(g.N, i + kIcpThreads);
+        }
+        pin(vi);
+        pin(v);
+        pin(nv);
+        J jac[6], r;
+        const bool ok = icp_pixel_from(kp, g, Tc, Tp, fx, fy, cx, cy, n, vi, v, nv, jac, r, ld);
+        vi = vi2;
+        v = v2;
+        nv = nv2;
+        if (ok) accumulate(jac, r);
+      }
+    } else {
+      for (size_t i = p0 + threadIdx.x; i < p1; i += kIcpThreads) {
+        J jac[6], r;
+        if (icp_pixel(kp, g, Tc, Tp, fx, fy, cx, cy, n, i, jac, r)) accumulate(jac, r);
+      }
     }
     // block reduction in FP64: wave butterflies, then the 4 waves in fixed
     // order.  The tangent sums cancel strongly (the derivative of a converged
