@@ -1,10 +1,14 @@
 """Benchmark of the CSFD dense-SLAM frame step on one MI355X.
 
 Workload: 640x480 depth (fx=fy=525), 512^3 TSDF at 1 cm (5.12 m cube),
-FP32-complex, one complex-step direction (initial-pose rotation phi_x),
-3-level ICP with 10/5/4 passes, on a seeded synthetic scene and a smooth
-trajectory at 30 Hz (inputs resident in HBM before timing).  A step is one
-whole frame step: measurement, tracking, fusion and raycast.
+FP32-complex, 3-level ICP with 10/5/4 passes, on a seeded synthetic scene and
+a smooth trajectory at 30 Hz (inputs resident in HBM before timing).  The
+job is the derivative of the trajectory with respect to the 6-DoF initial
+pose as six runs of one complex-step direction each (phi_x .. rho_z); the
+runs are independent and run side by side, each on its own stream (--runs 1:
+the phi_x run alone).  A step is one whole frame step (measurement,
+tracking, fusion and raycast) of every run.  The per-kernel timing and the
+rooflines come from the phi_x run stepping alone afterwards.
 
 Prints one JSON line: frames*directions/s, per-kernel timing from HIP events
 on the library's stream, the roofline of the dominant kernel, the CPU oracle
@@ -306,6 +310,11 @@ def main():
     ap.add_argument("--no-footprint", dest="footprint", action="store_false",
                     help="skip the oracle's count of the voxels the raycast touches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--runs", type=int, default=6, choices=range(1, 7),
+                    help="single-direction runs side by side (the first `runs` of phi_x, phi_y, phi_z, rho_x, "
+                         "rho_y, rho_z)")
+    ap.add_argument("--single-steps", type=int, default=60,
+                    help="frames of the phi_x run alone after the timed steps (its own rate)")
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
     ap.add_argument("--no-forms", action="store_true", help="only the headline workload")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes")
@@ -339,7 +348,8 @@ def main():
         del src, dst
 
     p = sg.preset("c1")
-    n_frames = args.warmup + args.steps + args.fill_steps + args.timing_steps
+    single_steps = args.single_steps if args.runs > 1 else 0
+    n_frames = args.warmup + args.steps + single_steps + args.fill_steps + args.timing_steps
     assert n_frames <= p["n_frames"], "the sequence has 500 frames"
     t0 = time.perf_counter()
     seq = sg.make_sequence(p, n_frames=n_frames)
@@ -350,8 +360,16 @@ def main():
     dev = torch.from_numpy(depths.astype(np.float32 if prec == X.C64 else np.float64)).to("cuda:0")
     h = 2.0 ** -20 if prec == X.C64 else 1e-20
     cfg = X.config_from_preset(p, prec=prec, max_frames=n_frames)
+    run_dirs = [X.P_PHI_X, X.P_PHI_Y, X.P_PHI_Z, X.P_RHO_X, X.P_RHO_Y, X.P_RHO_Z][:args.runs]
     pert = X.Perturbation([(X.P_PHI_X, h)])
     slam = X.Slam(cfg, pert, seq.poses_gt[0])
+    # the other runs, each on a stream of its own (the phi_x run keeps the
+    # current stream)
+    others = []
+    for d in run_dirs[1:]:
+        st = torch.cuda.Stream() if not args.null_stream else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            others.append(X.Slam(cfg, X.Perturbation([(d, h)]), seq.poses_gt[0]))
 
     from paper_2405_02187_amd import autotune as AT
     shapes = None
@@ -363,27 +381,46 @@ def main():
         shapes = {k: tuned[k] for k in ("ray_tile", "icp_blocks", "fuse_blocks")}
         log(f"autotuned in {time.perf_counter() - t0:.1f}s: {tuned}")
         k_start = 1 + tuned["frames"]
+        for o in others:
+            AT.apply(o, shapes)
     elif not args.no_autotune:
         # warm-up too short to tune: the shapes the tuner chose for this
         # workload on an MI355X, committed with the package
         cached = AT.load(AT.SHAPES_FILE).get(AT.key(slam))
         if cached:
             shapes = {k: cached[k] for k in ("ray_tile", "icp_blocks", "fuse_blocks")}
-            AT.apply(slam, shapes)
+            for s_ in [slam] + others:
+                AT.apply(s_, shapes)
             log(f"launch shapes from {os.path.basename(AT.SHAPES_FILE)}: {shapes}")
-    for k in range(k_start, args.warmup):
-        slam.step(dev[k])
-    slam.sync()
+    for k in range(0, args.warmup):
+        for j, s_ in enumerate([slam] + others):
+            if j > 0 or k >= k_start:
+                s_.step(dev[k])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
-        slam.step(dev[k])
-    slam.sync()
+        for s_ in [slam] + others:
+            s_.step(dev[k])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    value = args.steps * 1 / dt
-    graph_used = slam.frame_graph()
-    log(f"{args.steps} frame steps in {dt:.3f}s (frame graph: {graph_used})")
+    value = args.steps * len(run_dirs) / dt
+    graph_used = all(s_.frame_graph() for s_ in [slam] + others)
+    log(f"{args.steps} frame steps of {len(run_dirs)} runs in {dt:.3f}s (frame graphs: {graph_used})")
+    run_lost = [int(s_.get(X.F_COUNTERS)[:args.warmup + args.steps, 0].sum()) for s_ in [slam] + others]
+    for o in others:
+        o.close()
+    single = None
+    if single_steps:
+        # the phi_x run alone
+        k0 = args.warmup + args.steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(k0, k0 + single_steps):
+            slam.step(dev[k])
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0
+        single = dict(value=single_steps / dts, ms_per_frame=1e3 * dts / single_steps, frames=single_steps)
+        log(f"phi_x run alone: {single['value']:.0f} frames/s")
 
     # per-kernel durations with HIP events on the library's stream.  The
     # host first queues `fill` graph-replayed frames, then the timed frames
@@ -391,7 +428,7 @@ def main():
     # behind the fill frames, so the GPU runs them back to back and each
     # event pair brackets its kernel (not the host's launch latency).
     ms0, launches0 = slam.kernel_times()
-    k0 = args.warmup + args.steps
+    k0 = args.warmup + args.steps + single_steps
     for k in range(k0, k0 + args.fill_steps):
         slam.step(dev[k])
     slam.set_timing(True)
@@ -466,10 +503,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if prec == X.C64 else "f64", "data": "synthetic",
-        "config": {"workload": "seq640x480_tsdf512_1cm_fp32complex_1dir" if prec == X.C64
-                   else "seq640x480_tsdf512_1cm_fp64complex_1dir",
-                   "width": 640, "height": 480, "tsdf": 512, "voxel_m": 0.01, "directions": 1,
-                   "icp_iters": [10, 5, 4], "frames_timed": args.steps},
+        "config": {"workload": ("seq640x480_tsdf512_1cm_%s_%druns_x_1dir" %
+                                ("fp32complex" if prec == X.C64 else "fp64complex", len(run_dirs))),
+                   "width": 640, "height": 480, "tsdf": 512, "voxel_m": 0.01, "runs": len(run_dirs),
+                   "directions_per_run": 1,
+                   "run_directions": ["phi_x", "phi_y", "phi_z", "rho_x", "rho_y", "rho_z"][:len(run_dirs)],
+                   "streams": len(run_dirs), "icp_iters": [10, 5, 4], "frames_timed": args.steps},
+        "single_run": single, "runs_lost_frames": run_lost,
         "roofline": roofline,
         "kernel_classes": per, "kernel_rooflines": kern, "per_frame": extra,
         "lost_frames": int(cnt[:, 0].sum()),
