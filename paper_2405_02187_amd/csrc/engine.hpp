@@ -697,6 +697,15 @@ struct Engine : EngineBase {
                           C->cfg.max_frames};
   }
 
+  GBrickApron<T> d_brick_apron() const { return GBrickApron<T>{bflags, kp.nbr[0], kp.nbr[1], kp.nbr[2]}; }
+  dim3 g_brick_apron() const { return dim3((nbrick + 255) / 256); }
+  int run_brick_apron() {
+    const auto a = d_brick_apron();
+    return launch(4, "brick_apron", [&] {
+      XS_LAUNCH(k_brick_apron<T>, g_brick_apron(), dim3(256), 0, C->stream, a.flags, a.nbx, a.nby, a.nbz);
+    });
+  }
+
   int run_fuse(bool tracked, bool store) {
     int rc;
     const auto z = d_tile_zmax(tracked, store);
@@ -719,10 +728,12 @@ struct Engine : EngineBase {
          })))
       return rc;
     const auto bf = d_brick_flags();
-    return launch(4, "brick_flags", [&] {
-      XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, bf.rec, bf.flags, bf.list, bf.count,
-                bf.nbrick, bf.fcounts, bf.nf, bf.counter_base, bf.frame, bf.max_frames);
-    });
+    if ((rc = launch(4, "brick_flags", [&] {
+           XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, bf.rec, bf.flags, bf.list, bf.count,
+                     bf.nbrick, bf.fcounts, bf.nf, bf.counter_base, bf.frame, bf.max_frames);
+         })))
+      return rc;
+    return run_brick_apron();
   }
 
   // surfel map: index map at 4x, association and update, insertion in pixel
@@ -792,6 +803,7 @@ struct Engine : EngineBase {
       XS_LAUNCH(k_brick_flags<T>, dim3(g), dim3(kBrickVox), 0, C->stream, rec, bflags, nullptr, nullptr,
                          nbrick, nullptr, 0, nullptr, nullptr, 0);
     });
+    if (!rc) rc = run_brick_apron();
     return rc ? rc : sync();
   }
 
@@ -1425,6 +1437,7 @@ struct GroupRun : GroupBase {
     stage(each([](E* x) { return x->d_fuse(); }), grids([](E* x) { return dim3(x->fuse_blocks()); }), dim3(kBrickVox));
     stage(each([](E* x) { return x->d_brick_flags(); }), grids([](E* x) { return dim3(x->fuse_blocks()); }),
           dim3(kBrickVox));
+    stage(each([](E* x) { return x->d_brick_apron(); }), grids([](E* x) { return x->g_brick_apron(); }), dim3(256));
     const int bx = e[mem[0]]->ray_bx, by = e[mem[0]]->ray_by;
     stage(each([](E* x) { return x->d_raymarch(); }), grids([&](E* x) { return x->g_ray(bx, by); }), dim3(bx, by));
     stage(each([](E* x) { return x->d_rayhit(); }), grids([&](E* x) { return x->g_ray(bx, by); }), dim3(bx, by));

@@ -174,6 +174,13 @@ struct GBrickFlags {
   }
 };
 
+template <typename T>
+struct GBrickApron {
+  static constexpr int kThreads = 256;
+  uint8_t* flags; int nbx, nby, nbz;
+  __device__ __forceinline__ void run(const VB& vb) const { brick_apron_body<T>(vb, kG(flags), nbx, nby, nbz); }
+};
+
 template <typename T, int D, int Q>
 struct GRaymarch {
   static constexpr int kThreads = 256;

@@ -1619,6 +1619,32 @@ __global__ __launch_bounds__(kBrickVox) void k_brick_flags(const typename Vec2<T
   brick_flags_body<T>(VB::hw(), rec, flags, list, count, nbrick, fcounts, nf, counter_base, frame, max_frames);
 }
 
+// Bit 2 of a brick's flag: the brick and its seven neighbours in +x, +y, +z
+// (the bricks a cell whose lower corner lies in this brick can reach) are all
+// free, so every cell with its lower corner here interpolates eight ones.
+// Recomputed for every brick after the flags change (a neighbour's update
+// changes it); bits 0 and 1, which other threads read here, are not written.
+template <typename T>
+__device__ __forceinline__ void brick_apron_body(const VB& vb, uint8_t* __restrict__ flags, int nbx, int nby, int nbz) {
+  const int b = vb.bx * 256 + threadIdx.x;
+  if (b >= nbx * nby * nbz) return;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const uint32_t f = flags[b];
+  bool all = (f & 2) && bx + 1 < nbx && by + 1 < nby && bz + 1 < nbz;
+  if (all) {
+    uint32_t n[7];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) n[c - 1] = flags[b + (c & 1) + ((c >> 1) & 1) * nbx + (c >> 2) * nbx * nby];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) all = all && (n[c] & 2);
+  }
+  flags[b] = uint8_t((f & 3) | (all ? 4 : 0));
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_brick_apron(uint8_t* __restrict__ flags, int nbx, int nby, int nbz) {
+  brick_apron_body<T>(VB::hw(), flags, nbx, nby, nbz);
+}
+
 template <typename T, int D, int Q>
 __global__ void k_post_track(MPose<D, Q>* Pcur, const MPose<D, Q>* Pinit, KPose<T, D, Q>* Kcur, const int* lost,
                              MPose<D, Q>* history, const int* frame, int max_frames, int* count) {
@@ -1640,8 +1666,9 @@ struct MapsOut {
 // - 1/2 (the caller forms g); valid iff all 8 corners observed (W > 0).
 // The brick flags only skip loads: a cell whose first corner lies in a brick
 // with no observed voxel is invalid (that corner has W = 0), and a cell inside
-// an all-free brick has eight corners equal to 1, where the value is taken as
-// 1 without loading them (the march only compares sample values with 0 and
+// an all-free brick, or with its lower corner in a brick whose +x/+y/+z
+// neighbours are all free as well (bit 2), has eight corners equal to 1,
+// where the value is taken as 1 without loading them (the march only compares sample values with 0 and
 // 0.999, which the interpolation of eight ones meets in the same way).  Brick
 // indexes are 32-bit (the brick grid holds far fewer than 2^31 bricks).
 template <typename T, int D, int Q>
@@ -1667,7 +1694,7 @@ __device__ __forceinline__ bool trilinear_re(const KParams<T, D, Q>& kp, const t
   }
   const uint32_t bf = cached_flag;
   if (!(bf & 1)) return false;
-  if ((bf & 2) && (((i0[0] & 7) != 7) & ((i0[1] & 7) != 7) & ((i0[2] & 7) != 7))) {
+  if ((bf & 4) || ((bf & 2) && (((i0[0] & 7) != 7) & ((i0[1] & 7) != 7) & ((i0[2] & 7) != 7)))) {
     out = T(1);
     return true;
   }
