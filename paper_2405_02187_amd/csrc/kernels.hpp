@@ -1429,7 +1429,7 @@ __device__ __forceinline__ int fuse_brick(const KParams<T, D, Q>& kp, const KPos
   bool upd = false;
   int i0 = 0, j0 = 0;
   bool nearest = false;
-  size_t tn = 0;
+  int sel = 0;
   T ux_r = 0, uy_r = 0;
   if (xr.z.re() > T(0)) {
     ux_r = kp.fx.re() * xr.x.re() / xr.z.re() + kp.cx.re();
@@ -1441,9 +1441,11 @@ __device__ __forceinline__ int fuse_brick(const KParams<T, D, Q>& kp, const KPos
       const size_t t0 = size_t(j0) * W + i0;
       const T d0 = Df[t0], d1 = Df[t0 + 1], d2 = Df[t0 + W], d3 = Df[t0 + W + 1];
       if (d0 > T(0) && d1 > T(0) && d2 > T(0) && d3 > T(0)) {
+        // the nearest pixel floor(u + 1/2) is one of the four taps (u lies in
+        // [floor(u), floor(u) + 1)), so its depth is already loaded
         const int in = int(floor(ux_r + T(0.5))), jn = int(floor(uy_r + T(0.5)));
-        tn = size_t(jn) * W + in;
-        const T dn = Df[tn];
+        sel = (jn - j0) * 2 + (in - i0);
+        const T dn = sel == 0 ? d0 : sel == 1 ? d1 : sel == 2 ? d2 : d3;
         const T disc = fabs(d0 - dn) + fabs(d1 - dn) + fabs(d2 - dn) + fabs(d3 - dn);
         T L;
         if (disc >= kp.disc_delta) {
@@ -1463,30 +1465,42 @@ __device__ __forceinline__ int fuse_brick(const KParams<T, D, Q>& kp, const KPos
   if (!upd) return nupd;
 
   // ---- the update in complex-step arithmetic
+  // the four depth taps with their parts (the nearest is one of them) and
+  // the voxel's record, all in flight together
+  const size_t t0 = size_t(j0) * W + i0;
+  J q0 = jload<J>(Df, n, t0), q1 = jload<J>(Df, n, t0 + 1);
+  J q2 = jload<J>(Df, n, t0 + W), q3 = jload<J>(Df, n, t0 + W + 1);
+  auto r = rec[vi];
+  J F;
+#pragma unroll
+  for (int q = 1; q < J::N; ++q) F.v[q] = Ftan[size_t(q - 1) * nvox + vi];
+  T wt = Wtan != nullptr ? Wtan[vi] : T(0);
+  pin(q0);
+  pin(q1);
+  pin(q2);
+  pin(q3);
+  pin(r.x);
+  pin(r.y);
+#pragma unroll
+  for (int q = 1; q < J::N; ++q) pin(F.v[q]);
+  pin(wt);
+  F.v[0] = r.x;
   const V3<J> c = {jconst<J>(cc[0]), jconst<J>(cc[1]), jconst<J>(cc[2])};
   const V3<J> x = pose_apply_inv(P, c);
   const J ux = kp.fx * x.x / x.z + kp.cx;
   const J uy = kp.fy * x.y / x.z + kp.cy;
   J L;
   if (nearest) {
-    L = jload<J>(Df, n, tn);
+    L = sel == 0 ? q0 : sel == 1 ? q1 : sel == 2 ? q2 : q3;
   } else {
-    const size_t t0 = size_t(j0) * W + i0;
     const J a = ux - T(i0), bb = uy - T(j0);
     const J a1 = jconst<J>(T(1)) - a, b1 = jconst<J>(T(1)) - bb;
-    L = b1 * (a1 * jload<J>(Df, n, t0) + a * jload<J>(Df, n, t0 + 1)) +
-        bb * (a1 * jload<J>(Df, n, t0 + W) + a * jload<J>(Df, n, t0 + W + 1));
+    L = b1 * (a1 * q0 + a * q1) + bb * (a1 * q2 + a * q3);
   }
   const J eta = L - x.z;
   const J Fd = (eta.re() >= kp.mu.re()) ? jconst<J>(T(1)) : eta / kp.mu;
-  auto r = rec[vi];
-  J F, Wj;
-  F.v[0] = r.x;
-#pragma unroll
-  for (int q = 1; q < J::N; ++q) F.v[q] = Ftan[size_t(q - 1) * nvox + vi];
-  Wj = jconst<J>(r.y);
+  J Wj = jconst<J>(r.y);
   if (Wtan != nullptr) {
-    const T wt = Wtan[vi];
 #pragma unroll
     for (int q = 0; q < D; ++q)
       if (q == kp.wcap_dir) Wj.v[1 + q] = wt;
