@@ -407,6 +407,13 @@ def main():
     graph_used = all(s_.frame_graph() for s_ in [slam] + others)
     log(f"{args.steps} frame steps of {len(run_dirs)} runs in {dt:.3f}s (frame graphs: {graph_used})")
     run_lost = [int(s_.get(X.F_COUNTERS)[:args.warmup + args.steps, 0].sum()) for s_ in [slam] + others]
+    # the job's output: the trajectory error over the frames so far and its
+    # derivative with respect to each run's initial-pose direction
+    nf_runs = args.warmup + args.steps
+    te_runs = [s_.traj_err(seq.poses_gt[:nf_runs]) for s_ in [slam] + others]
+    traj = dict(frames=nf_runs, traj_err_m=float(te_runs[0][0]),
+                dtraj_err_dtheta=[float(t[1]) / h for t in te_runs],
+                directions=["phi_x", "phi_y", "phi_z", "rho_x", "rho_y", "rho_z"][:len(run_dirs)])
     for o in others:
         o.close()
     single = None
@@ -509,7 +516,7 @@ def main():
                    "directions_per_run": 1,
                    "run_directions": ["phi_x", "phi_y", "phi_z", "rho_x", "rho_y", "rho_z"][:len(run_dirs)],
                    "streams": len(run_dirs), "icp_iters": [10, 5, 4], "frames_timed": args.steps},
-        "single_run": single, "runs_lost_frames": run_lost,
+        "single_run": single, "runs_lost_frames": run_lost, "trajectory_derivative": traj,
         "roofline": roofline,
         "kernel_classes": per, "kernel_rooflines": kern, "per_frame": extra,
         "lost_frames": int(cnt[:, 0].sum()),
