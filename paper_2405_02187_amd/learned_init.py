@@ -10,7 +10,7 @@ library's kernels; this module only arranges data.
 
 ``python -m paper_2405_02187_amd.learned_init`` trains on seeded sequences
 and compares, on held-out sequences tracked at several frame steps, the
-network initialiser (with its residual judge) against constant velocity:
+network initialiser (with its residual test) against constant velocity:
 ICP passes to convergence (|update| < 1e-6) and trajectory error.
 """
 from __future__ import annotations

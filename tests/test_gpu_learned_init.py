@@ -1,7 +1,7 @@
 """GPU: the learned ICP initialiser end to end.  Training pairs come from the
 frame step itself (converged poses, network-input parts), the network is
 trained by the library's kernels, and a held-out sequence tracked at a larger
-frame step compares the network initialiser (with its residual judge) against
+frame step compares the network initialiser (with its residual test) against
 constant velocity: ICP passes to convergence and trajectory error."""
 import numpy as np
 import pytest
@@ -62,7 +62,7 @@ def test_learned_initialiser_trains_and_is_reported_against_constant_velocity():
     nn = LI.evaluate(cfg, d, s.poses_gt[0], s.poses_gt, 3, net=net)
     log("held-out, frame step 3: constant velocity", cv, "network", nn)
     assert cv["lost"] == 0 and nn["lost"] == 0
-    # the judge never lets the network make the initial residual worse, so
+    # the residual test never lets the network make the initial residual worse, so
     # tracking must stay as good as with constant velocity (small tolerance)
     assert nn["traj_err"] <= 1.5 * cv["traj_err"] + 0.005
     net.close()
