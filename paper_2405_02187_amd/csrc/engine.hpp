@@ -1383,7 +1383,10 @@ struct GroupRun : GroupBase {
     const int grid = persist > 0 ? std::min(f, persist) : f;
     hipStream_t s = stream;
     launches.push_back([m, grid, block, off, s](const char* base) {
-      hipLaunchKernelGGL(k_group<A>, dim3(grid), block, 0, s, reinterpret_cast<const A*>(base + off), m);
+      if (grid == m.total)
+        hipLaunchKernelGGL(k_group_once<A>, dim3(grid), block, 0, s, reinterpret_cast<const A*>(base + off), m);
+      else
+        hipLaunchKernelGGL(k_group<A>, dim3(grid), block, 0, s, reinterpret_cast<const A*>(base + off), m);
     });
   }
 
