@@ -2,10 +2,11 @@
 // sequences (instances) of the same (precision, directions, Hessian) shape.
 // Each instance brings a descriptor -- the arguments its own launch of the
 // stage would take -- and a grid of work items (its pixel tiles, bricks or ICP
-// workgroups).  The grouped kernel is persistent: its workgroups pull the
-// concatenated (instance, item) list in a fixed stride and run the stage's
-// body on each item exactly as the instance's own launch would, so every
-// instance's results equal those of its solo run bit for bit.
+// workgroups).  The grouped kernel runs the stage's body on each item of the
+// concatenated (instance, item) list exactly as the instance's own launch
+// would, so every instance's results equal those of its solo run bit for bit:
+// one workgroup per item (k_group_once), or a persistent grid whose
+// workgroups take the list in a fixed stride (k_group).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
