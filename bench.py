@@ -5,8 +5,10 @@ FP32-complex, 3-level ICP with 10/5/4 passes, on a seeded synthetic scene and
 a smooth trajectory at 30 Hz (inputs resident in HBM before timing).  The
 job is the derivative of the trajectory with respect to the 6-DoF initial
 pose as six runs of one complex-step direction each (phi_x .. rho_z); the
-runs are independent and run side by side, each on its own stream (--runs 1:
-the phi_x run alone).  A step is one whole frame step (measurement,
+runs are independent and run side by side: dealt to two streams, and the runs
+of a stream stepped by grouped launches, one launch per stage for them
+(--groups 0: each run on its own stream; --runs 1: the phi_x run alone).  A
+step is one whole frame step (measurement,
 tracking, fusion and raycast) of every run.  The per-kernel timing and the
 rooflines come from the phi_x run stepping alone afterwards.
 
@@ -313,6 +315,10 @@ def main():
     ap.add_argument("--runs", type=int, default=6, choices=range(1, 7),
                     help="single-direction runs side by side (the first `runs` of phi_x, phi_y, phi_z, rho_x, "
                          "rho_y, rho_z)")
+    ap.add_argument("--groups", type=int, default=2,
+                    help="the runs are dealt to this many streams and each stream's runs are stepped by grouped "
+                         "launches (one launch per stage for them); 0: each run on its own stream, launching its "
+                         "own frames")
     ap.add_argument("--single-steps", type=int, default=60,
                     help="frames of the phi_x run alone after the timed steps (its own rate)")
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
@@ -363,11 +369,16 @@ def main():
     run_dirs = [X.P_PHI_X, X.P_PHI_Y, X.P_PHI_Z, X.P_RHO_X, X.P_RHO_Y, X.P_RHO_Z][:args.runs]
     pert = X.Perturbation([(X.P_PHI_X, h)])
     slam = X.Slam(cfg, pert, seq.poses_gt[0])
-    # the other runs, each on a stream of its own (the phi_x run keeps the
-    # current stream)
+    # the other runs: each on a stream of its own, or dealt to `groups`
+    # streams (the phi_x run keeps the current stream, the first)
     others = []
-    for d in run_dirs[1:]:
-        st = torch.cuda.Stream() if not args.null_stream else torch.cuda.current_stream()
+    ngroups = min(args.groups, len(run_dirs)) if args.groups > 0 and not args.null_stream else 0
+    gstreams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(max(ngroups - 1, 0))]
+    for i, d in enumerate(run_dirs[1:], start=1):
+        if ngroups:
+            st = gstreams[i % ngroups]
+        else:
+            st = torch.cuda.Stream() if not args.null_stream else torch.cuda.current_stream()
         with torch.cuda.stream(st):
             others.append(X.Slam(cfg, X.Perturbation([(d, h)]), seq.poses_gt[0]))
 
@@ -396,16 +407,23 @@ def main():
         for j, s_ in enumerate([slam] + others):
             if j > 0 or k >= k_start:
                 s_.step(dev[k])
+    batch = X.Batch([slam] + others, grouped=True) if ngroups and others else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
-        for s_ in [slam] + others:
-            s_.step(dev[k])
+        if batch is not None:
+            batch.step([dev[k]] * len(run_dirs))
+        else:
+            for s_ in [slam] + others:
+                s_.step(dev[k])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * len(run_dirs) / dt
-    graph_used = all(s_.frame_graph() for s_ in [slam] + others)
-    log(f"{args.steps} frame steps of {len(run_dirs)} runs in {dt:.3f}s (frame graphs: {graph_used})")
+    if batch is not None:
+        batch.close()
+    graph_used = batch is not None or all(s_.frame_graph() for s_ in [slam] + others)
+    log(f"{args.steps} frame steps of {len(run_dirs)} runs in {dt:.3f}s "
+        f"({'grouped, %d streams' % ngroups if batch is not None else 'one stream each'})")
     run_lost = [int(s_.get(X.F_COUNTERS)[:args.warmup + args.steps, 0].sum()) for s_ in [slam] + others]
     # the job's output: the trajectory error over the frames so far and its
     # derivative with respect to each run's initial-pose direction
@@ -515,7 +533,8 @@ def main():
                    "width": 640, "height": 480, "tsdf": 512, "voxel_m": 0.01, "runs": len(run_dirs),
                    "directions_per_run": 1,
                    "run_directions": ["phi_x", "phi_y", "phi_z", "rho_x", "rho_y", "rho_z"][:len(run_dirs)],
-                   "streams": len(run_dirs), "icp_iters": [10, 5, 4], "frames_timed": args.steps},
+                   "streams": ngroups if (ngroups and others) else len(run_dirs),
+                   "grouped": bool(ngroups and others), "icp_iters": [10, 5, 4], "frames_timed": args.steps},
         "single_run": single, "runs_lost_frames": run_lost, "trajectory_derivative": traj,
         "roofline": roofline,
         "kernel_classes": per, "kernel_rooflines": kern, "per_frame": extra,
