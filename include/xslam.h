@@ -367,7 +367,9 @@ int xslam_batch_create(const xslam_ctx* ctxs, int32_t n, xslam_batch* out);
  * persist: workgroups per grouped launch, a multiple of 8 (0: one per work
  * item).  Requirements: the TSDF map, icp.solver 0, no network initialiser
  * attached, kernel timing off.  The raycast tile of a group is that of its
- * first context.  The library
+ * first context; launch shapes (xslam_set_launch) are read when a group's
+ * plan is built, at its first grouped step and whenever the set of stepping
+ * contexts changes.  The library
  * allocates the groups' descriptor tables (device memory, freed by
  * xslam_batch_destroy).  Latency (xslam_batch_latency) is that of the
  * context's group's step: from its first launch to its last.  Errors:
