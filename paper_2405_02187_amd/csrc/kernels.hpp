@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp(KParams<T, D, Q> kp, IcpArg
 // or four groups per thread for jets with many parts (256 threads, so that
 // the solving wave may hold 512 registers: the same sums, fewer spills).
 template <typename T, int D, int Q>
-constexpr int kFinishThreads = Jet<T, D, Q>::N > 8 ? 256 : 1024;
+constexpr int kFinishThreads = Jet<T, D, Q>::N > 2 ? 256 : 1024;
 template <typename T, int D, int Q>
 __device__ __forceinline__ void icp_finish_body(const VB& vb, const IcpArgs<T, D, Q>& g, int nblocks) {
   constexpr int NS = IcpSize<D, Q>::NS;
