@@ -5,6 +5,8 @@
   updates, insertions, surfels in use and valid model pixels equal the
   oracle's; poses (value and derivative) within 1e-10; the final surfel map
   (same order) within 1e-10, time stamps equal.
+* The same at the benchmark's 640 x 480 camera (3 frames, FP64, a pose
+  direction): counts exact, poses, derivatives and surfels within 1e-10.
 * The same in FP32: counts within a few per cent, poses within 1e-4 m.
 * Checkpoint: the surfel map read back and written into a fresh context
   resumes the sequence bit for bit.
@@ -157,3 +159,34 @@ def test_surfel_capacity_and_lost_frame_match_oracle():
     assert np.array_equal(S["t"], r["surfels"]["t"])
     for k in ("v", "n", "r", "c"):
         assert relerr(S[k], r["surfels"][k]) <= 1e-10
+
+
+def test_surfel_sequence_fullsize_fp64_matches_oracle():
+    """The benchmark's 640x480 camera: 3 frames in FP64 with a pose direction
+    on the frame graph; counts equal the oracle's, poses (value and
+    derivative) and the surfel map within 1e-10."""
+    p = sg.preset("c1")
+    seq = sg.make_sequence(p, n_frames=3)
+    d = seq.depths().astype(np.float64)
+    T0 = seq.poses_gt[0]
+    g = _gpu_run(p, d, T0, X.C128, [(X.P_RHO_X, 1e-20)], n=3)
+    r = O.pf_run_sequence(O.config(p), O.seed(1, O.P_RHO_X, h=1e-20), d, T0)
+    cnt, st, pf = g["cnt"], r["stats"], r["pf"]
+    log("full-size surfel counts gpu", cnt[:, [0, 1, 3, 35, 36, 37]].tolist(), "oracle", pf.tolist(), "graph", g["graph"])
+    assert g["graph"]
+    assert np.array_equal(cnt[:, 0], st[:, 0].astype(int))
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
+    assert np.array_equal(cnt[:, 1], pf[:, 0])
+    assert np.array_equal(cnt[:, 35], pf[:, 1])
+    assert np.array_equal(cnt[:, 36], pf[:, 2])
+    assert cnt[-1, 37] == len(r["surfels"]["t"]) == len(g["S"]["t"])
+    P, Pr = g["poses"], np.moveaxis(r["poses"], -1, 1)
+    e_pose, e_der = relerr(P[:, 0], Pr[:, 0]), relerr(P[:, 1], Pr[:, 1])
+    log("full-size surfel pose err", e_pose, "derivative err", e_der)
+    assert e_pose <= 1e-10 and e_der <= 1e-10
+    S, R = g["S"], r["surfels"]
+    assert np.array_equal(S["t"], R["t"])
+    for k in ("v", "n", "r", "c"):
+        e = relerr(S[k], R[k])
+        log("full-size surfel", k, "err", e)
+        assert e <= 1e-10
