@@ -8,7 +8,8 @@ on synthetic queries.
   oracle's (3 frames of the 128^3 sequence), the query's filtered depth the
   oracle's; at the query's true pose and at two poses off it: count equal,
   E, g and H within 1e-10 (FP64).  A second call returns the same bits (the
-  sums' order is fixed), and the context's volume is untouched.
+  sums' order is fixed), and the context's volume is untouched.  The same at
+  the benchmark's size (512^3 at 1 cm, 640x480 query) at one pose.
 * Relocalisation of synthetic queries (reference frames around the query
   at their true poses, a 3 cm / 3 degree initial error): gradient descent,
   gradient descent on finite differences, and Newton with the gradient step
@@ -65,6 +66,35 @@ def test_reloc_energy_matches_oracle():
         Wt = slam.get(X.F_WEIGHT)
         assert np.array_equal(F[0], ref["F"][:, 0]) and np.array_equal(Wt[0], ref["W"][:, 0])
         slam.close()
+
+
+def test_reloc_energy_fullsize_matches_oracle():
+    """The benchmark's workload: a 512^3 reference volume at 1 cm (the
+    oracle's, two frames of the 640x480 sequence) and a 640x480 query 1 cm /
+    1 degree off its true pose: count equal, E, g and H within 1e-10 (FP64)."""
+    p = sg.preset("c1")
+    seq = sg.make_sequence(p, n_frames=3)
+    d = seq.depths().astype(np.float64)
+    c = O.config(p)
+    ref = O.run_sequence(c, O.seed(0), d[:2], seq.poses_gt[0], want_volume=True)
+    meas = O.measure(c, O.seed(0), d[2])
+    Dcat = np.concatenate([m["D"][..., 0].reshape(-1) for m in meas])
+    T = IM.se3_exp([0.01, -0.012, 0.008, 0.01, -0.006, 0.004]) @ seq.poses_gt[2]
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=4)
+        slam = X.Slam(cfg, X.Perturbation([]), seq.poses_gt[0])
+        slam.set(X.F_TSDF, ref["F"].T)
+        slam.set(X.F_WEIGHT, ref["W"].T)
+        slam.measure(torch_dev(d[2], np.float64))
+        slam.set(X.F_MEAS_DEPTH, Dcat)
+        E, g, H, cnt = slam.reloc_energy(T)
+        slam.close()
+    Er, gr, Hr, cr = O.reloc_energy(c, ref["F"], ref["W"], meas[0]["D"], T, order=2)
+    log("full-size reloc: count", cnt, cr, "E", E, Er, "g err", relerr(g, gr), "H err", relerr(H, Hr))
+    assert cnt == cr > 100000
+    assert relerr(E, Er) <= 1e-10
+    assert relerr(g, gr) <= 1e-10
+    assert relerr(H, Hr) <= 1e-10
 
 
 def test_reloc_refuses_runs_with_directions():
