@@ -6,7 +6,8 @@ and the optimiser comparison of Sec. 5.1 (Fig. 3).
   21 pairs per pixel; the oracle: 6 complex-step and 21 bicomplex runs of the
   same pass), correspondences held fixed or through the association, at a
   pose away from the solution, levels 0-2: count equal, E, g and H within
-  1e-10 (FP64).
+  1e-10 (FP64); the same at the benchmark's size (640x480, 512^3), level 0,
+  through the association.
 * Tracking with the Newton solvers (correspondences held fixed per pass, or
   differentiated through the association) on the 128^3 sequence (FP64, no
   directions): per-frame counts equal, poses within 1e-10 of the oracle.
@@ -69,6 +70,39 @@ def test_icp_energy_matches_oracle(through):
             assert relerr(g, gr) <= 1e-10
             assert relerr(H, Hr) <= 1e-10
         slam.close()
+
+
+def test_icp_energy_fullsize_matches_oracle():
+    """The Newton objective at the benchmark's size (640x480 against the model
+    maps raycast from the oracle's 512^3 volume after two frames), with the
+    correspondences differentiated through the association, level 0: count
+    equal, E, g and H within 1e-10 (FP64)."""
+    p = sg.preset("c1")
+    seq = sg.make_sequence(p, n_frames=3)
+    d = seq.depths().astype(np.float64)
+    T0 = seq.poses_gt[0]
+    s0 = O.seed(0)
+    c = O.config(p)
+    r = O.run_sequence(c, s0, d[:2], T0, want_volume=True)
+    Tprev = r["poses"][1][..., 0]
+    model = O.raycast(c, s0, r["F"], r["W"], Tprev[..., None])
+    meas = O.measure(c, s0, d[2])
+    Tj = IM.se3_exp([0.004, -0.003, 0.002, 0.008, -0.005, 0.006]) @ Tprev
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=4)
+        slam = X.Slam(cfg, X.Perturbation([]), T0)
+        _set_model(slam, model["V"], model["N"], model["Z"], model["valid"])
+        slam.set(X.F_PREV_POSE, Tprev[None])
+        slam.measure(torch_dev(d[2], np.float64))
+        slam.set(X.F_POSE, Tj[None])
+        E, g, H, cnt = slam.icp_energy(0, True)
+        slam.close()
+    Er, gr, Hr, cr = O.icp_energy(c, 0, meas[0], model, Tprev, Tj, through=True)
+    log("full-size Newton objective: count", cnt, cr, "E", E, Er, "g err", relerr(g, gr), "H err", relerr(H, Hr))
+    assert cnt == cr > 100000
+    assert relerr(E, Er) <= 1e-10
+    assert relerr(g, gr) <= 1e-10
+    assert relerr(H, Hr) <= 1e-10
 
 
 @pytest.mark.parametrize("solver", [1, 2])
