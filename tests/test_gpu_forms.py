@@ -4,6 +4,9 @@ frame-step robustness study.
 * The original-KinectFusion update (eq. icp_approx: the small-angle
   increment, rotation re-orthonormalised) on the 20-frame 128^3 FP64-complex
   sequence: counts equal, poses and derivative within 1e-10 of the oracle.
+* The same form with the constant-velocity initial pose at 640x480 against a
+  512^3 volume (four FP64 frames, one pose direction, on the frame graph):
+  the same bar.
 * Frame steps 1/2/3 (Sec. 5.1's robustness comparison, on the synthetic
   640x480 / 512^3 spline): the exact-exponential, small-angle and Newton forms
   run through the library on the subsampled sequence; their trajectory errors
@@ -53,6 +56,38 @@ def test_small_angle_form_matches_oracle(param):
     assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
     e0, e1 = relerr(P[..., 0], ref["poses"][..., 0]), relerr(P[..., 1], ref["poses"][..., 1])
     log("small-angle form fp64 vs oracle: pose", e0, "derivative", e1)
+    assert e0 <= 1e-10 and e1 <= 1e-10
+
+
+def test_small_angle_form_fullsize_matches_oracle():
+    """The small-angle form with constant velocity at the benchmark's size
+    (640x480, 512^3 at 1 cm), FP64, four frames (the third and fourth start
+    from the extrapolated pose), one pose direction, on the frame graph:
+    counts equal, poses and derivatives within 1e-10."""
+    p = sg.preset("c1")
+    n = 4
+    seq = sg.make_sequence(p, n_frames=n)
+    d = seq.depths(workers=min(16, os.cpu_count() or 1)).astype(np.float64)
+    T0 = seq.poses_gt[0]
+    with created_stream():
+        cfg = X.config_from_preset(p, prec=X.C128, max_frames=n, update=1, init=1)
+        slam = X.Slam(cfg, X.Perturbation([(X.P_PHI_Z, H20)]), T0)
+        dev = torch_dev(d, np.float64)
+        for k in range(n):
+            slam.step(dev[k])
+        cnt = slam.get(X.F_COUNTERS)
+        P = gpu_pose_to_oracle(slam.get(X.F_POSES))
+        assert slam.frame_graph()
+        slam.close()
+    O.set_threads(min(16, os.cpu_count() or 1))
+    ref = O.run_sequence(O.config(p, update=1, init=1), O.seed(1, O.P_PHI_Z, h=H20), d, T0)
+    st = ref["stats"]
+    assert np.array_equal(cnt[:, 0], st[:, 0].astype(int))
+    assert np.array_equal(cnt[:, 1], st[:, 3].astype(int))
+    assert np.array_equal(cnt[:, 2], st[:, 4].astype(int))
+    assert np.array_equal(cnt[:, 3], st[:, 5].astype(int))
+    e0, e1 = relerr(P[..., 0], ref["poses"][..., 0]), relerr(P[..., 1], ref["poses"][..., 1])
+    log("full-size small-angle form with constant velocity vs oracle: pose", e0, "derivative", e1)
     assert e0 <= 1e-10 and e1 <= 1e-10
 
 
