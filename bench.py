@@ -5,9 +5,11 @@ FP32-complex, 3-level ICP with 10/5/4 passes, on a seeded synthetic scene and
 a smooth trajectory at 30 Hz (inputs resident in HBM before timing).  The
 job is the derivative of the trajectory with respect to the 6-DoF initial
 pose as six runs of one complex-step direction each (phi_x .. rho_z); the
-runs are independent and run side by side: dealt to two streams, and the runs
-of a stream stepped by grouped launches, one launch per stage for them
-(--groups 0: each run on its own stream; --runs 1: the phi_x run alone).  A
+runs are independent and run side by side: dealt to four streams (HIP maps a
+process's streams onto four hardware queues by default; a fifth stream would
+share one), and the runs of a stream stepped by grouped launches, one launch
+per stage for them (--groups 0: each run on its own stream; --runs 1: the
+phi_x run alone).  A
 step is one whole frame step (measurement,
 tracking, fusion and raycast) of every run.  The per-kernel timing and the
 rooflines come from the phi_x run stepping alone afterwards.
@@ -315,7 +317,7 @@ def main():
     ap.add_argument("--runs", type=int, default=6, choices=range(1, 7),
                     help="single-direction runs side by side (the first `runs` of phi_x, phi_y, phi_z, rho_x, "
                          "rho_y, rho_z)")
-    ap.add_argument("--groups", type=int, default=2,
+    ap.add_argument("--groups", type=int, default=4,
                     help="the runs are dealt to this many streams and each stream's runs are stepped by grouped "
                          "launches (one launch per stage for them); 0: each run on its own stream, launching its "
                          "own frames")
