@@ -1,7 +1,7 @@
 """GPU: several independent sequences stepped by grouped launches (one grid
 per stage for every context of a shape, each context's descriptor and work
-items) give, per context, exactly the results of that context run alone;
-one FP64 member checked against the oracle; the batch's refusals."""
+items) give, per context, exactly the results of that context run alone,
+also where a group holds one context; one FP64 member checked against the oracle; the batch's refusals."""
 import ctypes as C
 
 import numpy as np
@@ -57,6 +57,27 @@ def test_grouped_batch_equals_instances_run_alone(persist):
         if inst["preset"]["dim"] <= 256:
             assert np.array_equal(sa.get(X.F_TSDF), sb.get(X.F_TSDF))
             assert np.array_equal(sa.get(X.F_WEIGHT), sb.get(X.F_WEIGHT))
+        sa.close()
+        sb.close()
+
+
+def test_grouped_single_member_groups_equal_instances_run_alone():
+    """Groups of one context (a 1-direction and a 2-direction context of
+    one size, each shape on a stream of its own): the same results as
+    running each alone."""
+    pr = sg.instance_presets(24)
+    presets = []
+    for i, n in ((9, 8), (4, 10)):
+        p = dict(pr[i])
+        p["n_frames"] = n
+        presets.append(p)
+    insts = M.make_instances(presets)
+    assert len({M.shape_of(inst) for inst in insts}) == 2
+    res = M.run_batch(insts, grouped=True)
+    for inst, sb in zip(insts, res["slams"]):
+        sa, _ = M.run_alone(inst)
+        assert np.array_equal(sa.get(X.F_POSES), sb.get(X.F_POSES))
+        assert np.array_equal(sa.get(X.F_COUNTERS), sb.get(X.F_COUNTERS))
         sa.close()
         sb.close()
 
